@@ -1,0 +1,245 @@
+/*
+ * lorenz_cipher.h -- C ABI of the MI355X (gfx950) implementation of the
+ * Lorenz-attractor chaotic cipher of Marco, Martinez and Bruno,
+ * "Fast, parallel and secure cryptography algorithm using Lorenz's attractor"
+ * (arXiv:1201.3114), parallel (fast) version of Section 5.
+ *
+ * Problem statement (Section 1): C = E_pi(P), P = D_pi(C) = E_pi^-1(C), with
+ * P and C strings of bytes and pi the password's bytes.  The integrity claim
+ * (Abstract, end of Section 2) is realised as a 24-byte tag appended to C:
+ * decryption fails when any byte of C was altered.
+ *
+ * Conventions for every entry point:
+ *  - Return value: LZ_OK (0) or a negative LZ_E_* code.  No exception or
+ *    abort crosses the ABI; lz_last_error() gives a thread-local message.
+ *  - "Device pointer": memory of the context's GPU (hipMalloc, or a torch
+ *    tensor's data_ptr()).  "Host pointer": ordinary process memory.
+ *  - The caller owns every buffer it passes and keeps it alive until the
+ *    work enqueued on `stream` has completed.  The library owns only what it
+ *    allocates inside a context, batch or server object.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Plain and batch
+ *    calls are asynchronous on it unless stated otherwise.
+ *  - Byte layouts: a ciphertext is body (n bytes) || T1 || T2 || T3, each tag
+ *    word a little-endian uint64, so n_c = n + LZ_TAG_BYTES.
+ *
+ * Method parameters and their readings of the paper:
+ *  - Euler step of the Lorenz system (Section 3.1, F) with sigma = 10,
+ *    rho = 28, beta = 8/3, step dt, applied n_it times per byte (Step 2);
+ *  - the parallel version (Section 5) cuts a message into blocks of
+ *    block_len bytes; block b starts at r0 + b 2^-24 (every coordinate);
+ *  - r0 = a' + lambda (Section 3.1), Omega_i = SHA-256(i a) mod k_i.
+ */
+#ifndef LORENZ_CIPHER_H
+#define LORENZ_CIPHER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LZ_TAG_BYTES 24
+#define LZ_MAX_PASSWORD 64
+#define LZ_MAX_MESSAGE (1ull << 32)
+
+enum {
+    LZ_OK = 0,
+    LZ_E_INVAL = -1,     /* bad argument: NULL pointer, size or parameter out of range   */
+    LZ_E_INTEGRITY = -2, /* decryption: the recomputed tag differs from the stored one    */
+    LZ_E_NOMEM = -3,     /* device or host allocation failed, or request exceeds a budget */
+    LZ_E_HIP = -4,       /* a HIP runtime call failed (message in lz_last_error)          */
+    LZ_E_AGAIN = -5      /* server: nothing to return yet                                 */
+};
+
+/* Parameters of the method (Section 3.1; readings in the design notes).
+ * Defaults (lz_params_default): dt = 0.01, lambda = (1,1,1), n_it = 3000,
+ * block_len = 256, k = (4,4,4).  Valid ranges (else LZ_E_INVAL):
+ * 0 < dt <= 0.024 (forward Euler diverges from the attractor above it),
+ * each lambda_j inside the paper's range for its coordinate, n_it >= 1,
+ * 1 <= block_len <= 2^20, k_i in {3, 4} (2 < k_i <= floor((xi-14)/8) = 4). */
+typedef struct {
+    double dt;
+    double lambda[3];
+    uint32_t n_it;
+    uint32_t block_len;
+    uint8_t k[3];
+    uint8_t reserved[5]; /* must be zero */
+} lz_params;
+
+/* Output of the password stage of Section 3.1 (64 bytes, plain data). */
+typedef struct {
+    double a_prime[3]; /* a' = a / 10^D, correctly rounded, D = digits of 2^(8(L+1)) */
+    double r0[3];      /* r0 = a' + lambda                                          */
+    uint8_t mu[3];     /* mu_1 = (a1+a2+a3) mod 3, mu_2 = (a1 a2 + a3) mod 3, ...   */
+    uint8_t omega[3];  /* Omega_i = SHA-256(LE32(i a1)||LE32(i a2)||LE32(i a3)) mod k_i */
+    uint8_t k[3];
+    uint8_t reserved[7];
+} lz_key;
+
+/* Launch shape of the hot kernels.  chains_per_lane: blocks one lane
+ * carries at once (1, 2 or 4, interleaved for instruction-level parallelism);
+ * wg_size: 64, 128 or 256 threads; tile: bytes per chain staged through LDS
+ * per refill (16, 32, 64 or 128); waves_per_simd: resident waves per SIMD of
+ * the persistent batched kernel (1..8).  All-zero = use the tuned default. */
+typedef struct {
+    uint32_t chains_per_lane;
+    uint32_t wg_size;
+    uint32_t tile;
+    uint32_t waves_per_simd;
+} lz_launch;
+
+typedef struct lz_ctx lz_ctx;
+typedef struct lz_batch lz_batch;
+typedef struct lz_server lz_server;
+
+/* ---- host-only helpers ---------------------------------------------------- */
+
+/* Fills *out with the defaults above.  LZ_E_INVAL if out is NULL. */
+int lz_params_default(lz_params *out);
+
+/* LZ_OK if *prm is within the valid ranges, else LZ_E_INVAL. */
+int lz_params_check(const lz_params *prm);
+
+/* n + LZ_TAG_BYTES. */
+size_t lz_ciphertext_len(size_t n_plain);
+
+/* Password stage of Section 3.1 on the host: packing of pi into a = (a1,a2,a3),
+ * a' = g(a), r0 = a' + lambda, mu, Omega.  pw: host pointer, 1..64 bytes (any
+ * byte values).  Pure function, thread-safe.  LZ_E_INVAL on NULL or length. */
+int lz_key_setup(const uint8_t *pw, size_t n_pw, const lz_params *prm, lz_key *out);
+
+/* Thread-local description of the last error of this thread ("" if none). */
+const char *lz_last_error(void);
+
+/* ---- context ---------------------------------------------------------------- */
+
+/* Creates a context on HIP device `device` with parameters *prm (NULL =
+ * defaults).  The context owns a small device workspace (tag accumulators,
+ * statuses) and the tuned launch shape.  Calls that share a context are
+ * ordered: a call on a different stream than the previous call first waits
+ * for the previous call's work.  LZ_E_HIP if the device is unavailable. */
+int lz_context_create(int device, const lz_params *prm, lz_ctx **out);
+int lz_context_destroy(lz_ctx *ctx);
+
+/* Reads back the context's parameters. */
+int lz_context_params(const lz_ctx *ctx, lz_params *out);
+
+/* Sets (shape non-NULL) the launch shape used by the plain path and by
+ * batches created later, after validating it; LZ_E_INVAL if out of range. */
+int lz_context_set_launch(lz_ctx *ctx, const lz_launch *shape);
+int lz_context_get_launch(const lz_ctx *ctx, lz_launch *out);
+
+/* ---- plain path (one message) ---------------------------------------------------
+ * Section 3.2 Steps 1-3 over every block of the message in parallel
+ * (Section 5), one GPU lane per block, with the tag of the integrity claim.
+ *
+ * lz_encrypt: d_P device pointer, n bytes (0 <= n <= 2^32; NULL allowed when
+ * n == 0); d_C device pointer of n + 24 bytes (body then tag).  pw host
+ * pointer, 1..64 bytes.  Asynchronous on stream. */
+int lz_encrypt(lz_ctx *ctx, const uint8_t *pw, size_t n_pw, const uint8_t *d_P, size_t n,
+               uint8_t *d_C, void *stream);
+
+/* lz_decrypt: d_C device pointer of n_c >= 24 bytes; d_P device pointer of
+ * n_c - 24 bytes.  If the recomputed tag differs from the stored one the
+ * plaintext is zeroed (unauthenticated bytes are never released) and the
+ * status is LZ_E_INTEGRITY.  d_status: device int32 receiving LZ_OK or
+ * LZ_E_INTEGRITY (asynchronous call); if d_status is NULL the call
+ * synchronises the stream and returns that status itself. */
+int lz_decrypt(lz_ctx *ctx, const uint8_t *pw, size_t n_pw, const uint8_t *d_C, size_t n_c,
+               uint8_t *d_P, int32_t *d_status, void *stream);
+
+/* Plain path with a precomputed key (lz_key_setup) instead of a password. */
+int lz_encrypt_key(lz_ctx *ctx, const lz_key *key, const uint8_t *d_P, size_t n, uint8_t *d_C,
+                   void *stream);
+int lz_decrypt_key(lz_ctx *ctx, const lz_key *key, const uint8_t *d_C, size_t n_c, uint8_t *d_P,
+                   int32_t *d_status, void *stream);
+
+/* ---- batched path: many messages, one persistent launch in a HIP graph ---------
+ * n_msg messages, message i with its own password and plaintext length
+ * lens[i] (host arrays).  Encrypt: input i is lens[i] bytes at d_in +
+ * in_off[i], output i is lens[i] + 24 bytes at d_out + out_off[i].  Decrypt:
+ * input lens[i] + 24 bytes, output lens[i] bytes; d_status[i] (device int32,
+ * n_msg entries) receives LZ_OK or LZ_E_INTEGRITY and failed outputs are
+ * zeroed.  Passwords: bytes pw[pw_off[i] .. pw_off[i] + pw_len[i]) (host).
+ * Output ranges must not overlap each other or the inputs.
+ *
+ * lz_batch_create does key setup for every message, builds and uploads the
+ * work list (full blocks first, then partial blocks longest first), and
+ * captures [reset, persistent kernel, finalize] into a HIP graph bound to
+ * d_in/d_out/d_status; shape NULL = the context's launch shape.  It does not
+ * run the batch.  lz_batch_launch replays the graph on stream (asynchronous;
+ * may be called many times).  The batch owns its device descriptors. */
+int lz_batch_create(lz_ctx *ctx, int decrypt, size_t n_msg, const uint64_t *lens,
+                    const uint64_t *in_off, const uint64_t *out_off, const uint8_t *pw,
+                    const uint64_t *pw_off, const uint32_t *pw_len, const uint8_t *d_in,
+                    uint8_t *d_out, int32_t *d_status, const lz_launch *shape, lz_batch **out);
+int lz_batch_launch(lz_batch *batch, void *stream);
+int lz_batch_destroy(lz_batch *batch);
+
+/* Autotuner: times candidate launch shapes (chains_per_lane x wg_size x tile
+ * x waves_per_simd) of the batched kernel on a synthetic full-device batch
+ * with the context's parameters, stores the fastest in the context and in
+ * *best (may be NULL).  Synchronous; takes a few seconds.  When budget_ms > 0
+ * the sweep stops after that much measured time. */
+int lz_autotune(lz_ctx *ctx, double budget_ms, lz_launch *best);
+
+/* ---- serving: continuous batching ------------------------------------------------
+ * A request loop on a library thread.  Requests are admitted in arrival order
+ * while chain slots and the device-memory budget allow; their per-block chain
+ * state (r, alpha, mu, Omega: an exact checkpoint) and byte buffers stay on
+ * the device, and every tick advances all admitted chains by up to
+ * tick_bytes bytes, so requests that arrive while others run join at the
+ * next tick.  Results are bit-identical to the plain path. */
+typedef struct {
+    uint64_t hbm_budget;  /* bytes of device memory for request buffers + chain state */
+    uint32_t max_chains;  /* chain slots resident on the device (0 = 4 waves per SIMD) */
+    uint32_t tick_bytes;  /* bytes per chain per tick (0 = 16)                        */
+} lz_server_config;
+
+typedef struct {
+    uint64_t id;         /* caller's request id                                   */
+    int32_t status;      /* LZ_OK, LZ_E_INTEGRITY (decrypt) or LZ_E_NOMEM (too big) */
+    int32_t reserved;
+    uint64_t arrival_ns; /* monotonic clock, as submitted                         */
+    uint64_t admit_ns;   /* when the request got slots and memory                 */
+    uint64_t done_ns;    /* when its output was complete in the caller's buffer   */
+} lz_completion;
+
+/* Creates the server and starts its thread. */
+int lz_server_create(lz_ctx *ctx, const lz_server_config *cfg, lz_server **out);
+
+/* Queues a request.  decrypt = 0: src holds n bytes of plaintext, dst
+ * receives n + 24; decrypt = 1: src holds n + 24 bytes of ciphertext, dst
+ * receives n.  src/dst may be host or device pointers; the caller keeps them
+ * valid until the completion is returned.  pw is copied.  arrival_ns is the
+ * CLOCK_MONOTONIC time at which the request arrives (0 = now); the server does
+ * not see it earlier, which lets a recorded trace be replayed.  Thread-safe. */
+int lz_server_submit(lz_server *srv, uint64_t id, int decrypt, const uint8_t *pw, size_t n_pw,
+                     const void *src, uint64_t n, void *dst, uint64_t arrival_ns);
+
+/* Copies up to max completed requests into out, returns how many (>= 0), or
+ * a negative error.  timeout_ms < 0 waits until at least one is available. */
+int lz_server_poll(lz_server *srv, lz_completion *out, int max, int timeout_ms);
+
+/* Counters: ticks run, chains advanced, peak device bytes in use. */
+typedef struct {
+    uint64_t ticks;
+    uint64_t chain_bytes;
+    uint64_t peak_hbm;
+    uint64_t admitted;
+    uint64_t completed;
+    double busy_ms; /* summed device time of tick kernels */
+} lz_server_stats;
+int lz_server_stats_get(lz_server *srv, lz_server_stats *out);
+
+/* Stops the thread after the queued requests complete, frees everything. */
+int lz_server_destroy(lz_server *srv);
+
+/* CLOCK_MONOTONIC now, in ns (the clock of arrival_ns and done_ns). */
+uint64_t lz_now_ns(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LORENZ_CIPHER_H */

@@ -1,0 +1,8 @@
+"""MI355X (gfx950) implementation of the Lorenz-attractor chaotic cipher of
+arXiv:1201.3114 (parallel fast version): C-ABI library liblorenz_cipher.so
+with hand-written HIP kernels, and this thin Python layer over it.
+
+Importing the package loads the library and fails if it is not built.
+"""
+from .cipher import (TAG_BYTES, Batch, Context, IntegrityError, LaunchShape, LorenzError, Server,  # noqa: F401
+                     key_setup, now_ns, packed_offsets, params)

@@ -1,0 +1,244 @@
+"""Python face of the C ABI (include/lorenz_cipher.h): contexts, the plain
+path, batches and the server.  Torch supplies device memory and streams; the
+library does all the work.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import binding as B
+from .binding import IntegrityError, LorenzError, check  # noqa: F401  (re-exported)
+
+TAG_BYTES = B.TAG_BYTES
+
+
+def params(dt: float = 0.01, n_it: int = 3000, block_len: int = 256, lam=(1.0, 1.0, 1.0), k=(4, 4, 4)) -> B.Params:
+    """Method parameters (Section 3.1): Euler step, steps per byte, block length, lambda, k."""
+    p = B.Params()
+    check(B.lib.lz_params_default(ctypes.byref(p)))
+    p.dt = dt
+    p.n_it = n_it
+    p.block_len = block_len
+    p.lam[:] = list(lam)
+    p.k[:] = list(k)
+    return p
+
+
+def key_setup(pw: bytes, prm: B.Params | None = None) -> dict:
+    """Password stage of Section 3.1 (host)."""
+    k = B.Key()
+    buf, n = B.pw_buf(pw)
+    check(B.lib.lz_key_setup(buf, n, ctypes.byref(prm) if prm is not None else None, ctypes.byref(k)))
+    return dict(a_prime=list(k.a_prime), r0=list(k.r0), mu=list(k.mu), omega=list(k.omega), k=list(k.k))
+
+
+def _stream(stream, device):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if t.dtype != torch.uint8 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous torch.uint8 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class LaunchShape:
+    chains_per_lane: int = 1
+    wg_size: int = 256
+    tile: int = 64
+    waves_per_simd: int = 4
+
+    def to_c(self) -> B.Launch:
+        return B.Launch(self.chains_per_lane, self.wg_size, self.tile, self.waves_per_simd)
+
+    @staticmethod
+    def from_c(l: B.Launch) -> "LaunchShape":
+        return LaunchShape(l.chains_per_lane, l.wg_size, l.tile, l.waves_per_simd)
+
+
+class Context:
+    """A device plus method parameters; owns the plain path's small workspace."""
+
+    def __init__(self, device: int = 0, prm: B.Params | None = None):
+        self.device = torch.device("cuda", device)
+        self._h = ctypes.c_void_p()
+        torch.cuda.init()
+        check(B.lib.lz_context_create(device, ctypes.byref(prm) if prm is not None else None,
+                                      ctypes.byref(self._h)))
+        self.params = B.Params()
+        check(B.lib.lz_context_params(self._h, ctypes.byref(self.params)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            B.lib.lz_context_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- launch shape
+    def get_launch(self) -> LaunchShape:
+        l = B.Launch()
+        check(B.lib.lz_context_get_launch(self._h, ctypes.byref(l)))
+        return LaunchShape.from_c(l)
+
+    def set_launch(self, shape: LaunchShape):
+        l = shape.to_c()
+        check(B.lib.lz_context_set_launch(self._h, ctypes.byref(l)))
+
+    def autotune(self, budget_ms: float = 0.0) -> LaunchShape:
+        l = B.Launch()
+        check(B.lib.lz_autotune(self._h, budget_ms, ctypes.byref(l)))
+        return LaunchShape.from_c(l)
+
+    # ---- plain path
+    def encrypt(self, P: torch.Tensor, pw: bytes, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """C = E_pi(P) || tag, asynchronous on the stream."""
+        n = P.numel()
+        if out is None:
+            out = torch.empty(n + TAG_BYTES, dtype=torch.uint8, device=self.device)
+        if out.numel() != n + TAG_BYTES:
+            raise ValueError("out must hold n + 24 bytes")
+        buf, npw = B.pw_buf(pw)
+        check(B.lib.lz_encrypt(self._h, buf, npw, _dev_ptr(P) if n else None, n, _dev_ptr(out),
+                               _stream(stream, self.device)))
+        return out
+
+    def decrypt(self, C: torch.Tensor, pw: bytes, out: torch.Tensor | None = None,
+                status: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """P = D_pi(C).  With status=None the call waits and raises IntegrityError on a
+        tag mismatch; with a device int32 status tensor it stays asynchronous."""
+        nc = C.numel()
+        if nc < TAG_BYTES:
+            raise ValueError("ciphertext shorter than the 24-byte tag")
+        if out is None:
+            out = torch.empty(nc - TAG_BYTES, dtype=torch.uint8, device=self.device)
+        buf, npw = B.pw_buf(pw)
+        st = None
+        if status is not None:
+            if status.dtype != torch.int32 or not status.is_cuda:
+                raise ValueError("status must be a torch.int32 tensor on the GPU")
+            st = ctypes.c_void_p(status.data_ptr())
+        check(B.lib.lz_decrypt(self._h, buf, npw, _dev_ptr(C), nc, _dev_ptr(out) if nc > TAG_BYTES else None, st,
+                               _stream(stream, self.device)))
+        return out
+
+    def encrypt_key(self, key: B.Key, P, out, stream=None):
+        check(B.lib.lz_encrypt_key(self._h, ctypes.byref(key), _dev_ptr(P) if P.numel() else None, P.numel(),
+                                   _dev_ptr(out), _stream(stream, self.device)))
+        return out
+
+
+class Batch:
+    """Many messages, each with its own password, in one graph-captured persistent launch.
+
+    Inputs and outputs are packed into single device tensors at the given byte offsets."""
+
+    def __init__(self, ctx: Context, decrypt: bool, lens, pws, d_in: torch.Tensor, in_off, d_out: torch.Tensor,
+                 out_off, d_status: torch.Tensor | None = None, shape: LaunchShape | None = None):
+        n = len(lens)
+        self.ctx = ctx
+        self.n = n
+        self._keep = (d_in, d_out, d_status)
+        lens_a = np.ascontiguousarray(lens, dtype=np.uint64)
+        in_a = np.ascontiguousarray(in_off, dtype=np.uint64)
+        out_a = np.ascontiguousarray(out_off, dtype=np.uint64)
+        pw_len = np.array([len(p) for p in pws], dtype=np.uint32)
+        pw_off = np.zeros(n, dtype=np.uint64)
+        if n > 1:
+            pw_off[1:] = np.cumsum(pw_len[:-1], dtype=np.uint64)
+        pw_all = np.frombuffer(b"".join(bytes(p) for p in pws) or b"\0", dtype=np.uint8).copy()
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        st = None
+        if d_status is not None:
+            if d_status.dtype != torch.int32 or d_status.numel() < n:
+                raise ValueError("d_status must be an int32 tensor with one entry per message")
+            st = ctypes.c_void_p(d_status.data_ptr())
+        l = shape.to_c() if shape is not None else None
+        self._h = ctypes.c_void_p()
+        check(B.lib.lz_batch_create(ctx.handle, int(decrypt), n, lens_a.ctypes.data_as(u64p), in_a.ctypes.data_as(u64p),
+                                    out_a.ctypes.data_as(u64p), pw_all.ctypes.data_as(B.u8p),
+                                    pw_off.ctypes.data_as(u64p), pw_len.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                    ctypes.c_void_p(d_in.data_ptr()), ctypes.c_void_p(d_out.data_ptr()), st,
+                                    ctypes.byref(l) if l is not None else None, ctypes.byref(self._h)))
+
+    def launch(self, stream=None):
+        check(B.lib.lz_batch_launch(self._h, _stream(stream, self.ctx.device)))
+
+    def close(self):
+        if self._h:
+            B.lib.lz_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def packed_offsets(lens, extra: int = 0, align: int = 1):
+    """Offsets of messages laid end to end (each of len + extra bytes, aligned)."""
+    offs = np.zeros(len(lens), dtype=np.uint64)
+    pos = 0
+    for i, n in enumerate(lens):
+        offs[i] = pos
+        pos += (int(n) + extra + align - 1) // align * align
+    return offs, pos
+
+
+class Server:
+    """Continuous-batching request loop (library thread); see lz_server_* in the header."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, max_chains: int = 0, tick_bytes: int = 0):
+        self.ctx = ctx
+        cfg = B.ServerConfig(hbm_budget, max_chains, tick_bytes)
+        self._h = ctypes.c_void_p()
+        check(B.lib.lz_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(self._h)))
+
+    def submit(self, rid: int, decrypt: bool, pw: bytes, src_ptr: int, n: int, dst_ptr: int, arrival_ns: int = 0):
+        buf, npw = B.pw_buf(pw)
+        check(B.lib.lz_server_submit(self._h, rid, int(decrypt), buf, npw, ctypes.c_void_p(src_ptr), n,
+                                     ctypes.c_void_p(dst_ptr), arrival_ns))
+
+    def poll(self, max_n: int = 4096, timeout_ms: int = 0):
+        arr = (B.Completion * max_n)()
+        k = check(B.lib.lz_server_poll(self._h, arr, max_n, timeout_ms))
+        return [(c.id, c.status, c.arrival_ns, c.admit_ns, c.done_ns) for c in arr[:k]]
+
+    def stats(self) -> dict:
+        s = B.ServerStats()
+        check(B.lib.lz_server_stats_get(self._h, ctypes.byref(s)))
+        return dict(ticks=s.ticks, chain_bytes=s.chain_bytes, peak_hbm=s.peak_hbm, admitted=s.admitted,
+                    completed=s.completed, busy_ms=s.busy_ms)
+
+    def close(self):
+        if self._h:
+            rc = B.lib.lz_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            check(rc)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def now_ns() -> int:
+    return int(B.lib.lz_now_ns())

@@ -1,0 +1,135 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/lorenz_cipher.h"
+
+namespace lz {
+
+// ---- errors -------------------------------------------------------------------
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+#define LZ_HIP(call)                                        \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return ::lz::hip_fail(e_, #call); \
+    } while (0)
+
+// ---- host key setup (keysetup.cpp) ---------------------------------------------
+void sha256(const uint8_t *msg, size_t len, uint8_t out[32]);
+int key_setup(const uint8_t *pw, size_t n, const lz_params &prm, lz_key &key);
+int check_params(const lz_params &prm);
+
+// ---- device-side descriptors -----------------------------------------------------
+
+// Per-message descriptor of the batched and served paths (device memory).
+struct MsgDesc {
+    double ap[3];        // a'
+    double r0[3];        // r0
+    uint8_t mu[3], om[3], k[3], decrypt;
+    uint32_t nb;         // blocks (chains) of this message, >= 1
+    const uint8_t *in;   // message body in
+    uint8_t *out;        // message body out
+    uint64_t n;          // body length in bytes
+};
+
+// Resumable state of one chain (served path), an exact checkpoint.
+struct ChainSlot {
+    double r[3];
+    double al[3];
+    uint8_t mu[3], om[3];
+    uint8_t fresh;       // 1: state not yet initialised from the key
+    uint8_t pad;
+    uint32_t pos;        // bytes of this block already processed
+    uint32_t len;        // bytes of this block
+    uint32_t req;        // request slot
+    uint32_t blk;        // block index within the request
+    uint32_t pad2;
+};
+
+// Per-request record of the served path (device memory).
+struct ReqDesc {
+    MsgDesc m;
+    unsigned long long tag[3];  // XOR accumulator of block digests
+    uint32_t remaining;         // chains not yet finished
+    int32_t status;
+    const uint8_t *stored_tag;  // decrypt: the 24 tag bytes of the input
+};
+
+struct KernelShape {
+    int m;         // chains per lane
+    int wg;        // threads per workgroup
+    int tile;      // LDS bytes per chain per refill
+    int wps;       // resident waves per SIMD (persistent kernel)
+};
+
+struct DevInfo {
+    int cus;
+    int lds_per_wg_max;
+};
+
+// ---- kernel launchers (kernels.hip) --------------------------------------------------
+hipError_t launch_fill_u64(unsigned long long *p, size_t n, hipStream_t s);
+hipError_t launch_plain(const KernelShape &sh, const lz_key &key, const lz_params &prm, int decrypt,
+                        const uint8_t *in, uint8_t *out, uint64_t n, unsigned long long *tag_acc,
+                        hipStream_t s);
+hipError_t launch_plain_finalize(int decrypt, const unsigned long long *tag_acc, const uint8_t *stored_tag,
+                                 uint8_t *tag_out, int32_t *status, uint8_t *body, uint64_t n,
+                                 hipStream_t s);
+// Batched persistent kernel.  full_prefix[i] = number of full blocks of messages [0, i);
+// tail_msg: messages with a partial (or empty) last block, longest first.
+struct BatchDev {
+    const MsgDesc *msgs;
+    const uint64_t *full_prefix;  // n_msg + 1 entries
+    const uint32_t *tail_msg;     // n_tail entries
+    uint32_t n_msg;
+    uint32_t n_tail;
+    uint64_t n_full;              // total full blocks
+    uint64_t n_tasks;
+    unsigned long long *tag_acc;  // 3 per message
+    unsigned long long *counter;  // work-queue head
+    int32_t *status;              // decrypt: per message
+};
+hipError_t launch_batch(const KernelShape &sh, const DevInfo &dev, const lz_params &prm, const BatchDev &b,
+                        hipStream_t s);
+hipError_t launch_batch_finalize(const BatchDev &b, int decrypt, hipStream_t s);
+
+// Served path: advance the listed chains by up to tick_bytes bytes each.
+struct TickDev {
+    ChainSlot *slots;
+    ReqDesc *reqs;
+    const uint32_t *list;         // active chain slot indices
+    uint32_t n_list;
+    uint32_t tick_bytes;
+    uint32_t *done_queue;         // request slots completed in this tick
+    uint32_t *done_count;
+};
+hipError_t launch_tick(const KernelShape &sh, const lz_params &prm, const TickDev &t, hipStream_t s);
+hipError_t launch_install(ReqDesc *reqs, ChainSlot *slots, const ReqDesc *staged, const uint32_t *meta,
+                          const uint32_t *idx, uint32_t n_new, uint32_t block_len, hipStream_t s);
+hipError_t launch_req_zero(const ReqDesc *reqs, const uint32_t *req_ids, uint32_t n, hipStream_t s);
+
+size_t lds_bytes(const KernelShape &sh);
+bool shape_valid(const KernelShape &sh, const DevInfo &dev);
+
+}  // namespace lz
+
+// ---- context (runtime.cpp) ----------------------------------------------------------
+struct lz_ctx {
+    int device;
+    lz_params prm;
+    lz::KernelShape shape;
+    lz::DevInfo dev;
+    unsigned long long *ws_tag;  // 3 words, plain path tag accumulator
+    int32_t *ws_status;          // plain path status (synchronous decrypt)
+    int32_t *host_status;        // pinned
+    hipStream_t last_stream;
+    hipEvent_t last_event;
+    bool has_last;
+};

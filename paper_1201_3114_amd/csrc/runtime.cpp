@@ -1,0 +1,495 @@
+// Host runtime of the C ABI: parameters, contexts, the plain path, the batched
+// path (persistent kernel captured in a HIP graph) and the launch-shape
+// autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace lz {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? LZ_E_NOMEM : LZ_E_HIP,
+                std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+}
+
+int check_params(const lz_params &p) {
+    // 0 < dt <= 0.024: forward Euler from the attractor overflows for dt >= 0.025
+    if (!(p.dt > 0.0 && p.dt <= 0.024)) return fail(LZ_E_INVAL, "dt must be in (0, 0.024]");
+    // lambda inside the ranges of Section 3.1 (stable chaotic phases)
+    if (!(p.lambda[0] > -15.67 && p.lambda[0] < 16.01) || !(p.lambda[1] > -11.28 && p.lambda[1] < 16.01) ||
+        !(p.lambda[2] > 0.090 && p.lambda[2] < 62.0))
+        return fail(LZ_E_INVAL, "lambda outside the ranges of Section 3.1");
+    if (p.n_it == 0) return fail(LZ_E_INVAL, "n_it must be >= 1");
+    if (p.block_len == 0 || p.block_len > (1u << 20)) return fail(LZ_E_INVAL, "block_len must be in [1, 2^20]");
+    for (int i = 0; i < 3; ++i)
+        if (p.k[i] != 3 && p.k[i] != 4) return fail(LZ_E_INVAL, "k_i must be 3 or 4");
+    for (uint8_t r : p.reserved)
+        if (r) return fail(LZ_E_INVAL, "reserved bytes of lz_params must be zero");
+    return LZ_OK;
+}
+
+namespace {
+
+KernelShape to_shape(const lz_launch &l) {
+    return KernelShape{(int)l.chains_per_lane, (int)l.wg_size, (int)l.tile, (int)l.waves_per_simd};
+}
+
+lz_launch to_launch(const KernelShape &s) {
+    lz_launch l;
+    l.chains_per_lane = (uint32_t)s.m;
+    l.wg_size = (uint32_t)s.wg;
+    l.tile = (uint32_t)s.tile;
+    l.waves_per_simd = (uint32_t)s.wps;
+    return l;
+}
+
+// Orders a call on stream s after the previous call that used the same
+// workspace (possibly on another stream).
+int order_after(hipStream_t s, hipStream_t &last_stream, hipEvent_t ev, bool &has_last) {
+    if (has_last && last_stream != s) LZ_HIP(hipStreamWaitEvent(s, ev, 0));
+    return LZ_OK;
+}
+
+int record(hipStream_t s, hipStream_t &last_stream, hipEvent_t ev, bool &has_last) {
+    LZ_HIP(hipEventRecord(ev, s));
+    last_stream = s;
+    has_last = true;
+    return LZ_OK;
+}
+
+}  // namespace
+}  // namespace lz
+
+using namespace lz;
+
+// ---- host-only helpers -------------------------------------------------------------
+
+extern "C" int lz_params_default(lz_params *out) {
+    if (!out) return fail(LZ_E_INVAL, "out is NULL");
+    std::memset(out, 0, sizeof *out);
+    out->dt = 0.01;
+    out->lambda[0] = out->lambda[1] = out->lambda[2] = 1.0;
+    out->n_it = 3000;
+    out->block_len = 256;
+    out->k[0] = out->k[1] = out->k[2] = 4;
+    return LZ_OK;
+}
+
+extern "C" int lz_params_check(const lz_params *prm) {
+    if (!prm) return fail(LZ_E_INVAL, "prm is NULL");
+    return check_params(*prm);
+}
+
+extern "C" size_t lz_ciphertext_len(size_t n_plain) { return n_plain + LZ_TAG_BYTES; }
+
+extern "C" int lz_key_setup(const uint8_t *pw, size_t n_pw, const lz_params *prm, lz_key *out) {
+    if (!pw || !out) return fail(LZ_E_INVAL, "NULL argument");
+    lz_params def;
+    if (!prm) {
+        lz_params_default(&def);
+        prm = &def;
+    }
+    if (int rc = check_params(*prm)) return rc;
+    if (n_pw == 0 || n_pw > LZ_MAX_PASSWORD) return fail(LZ_E_INVAL, "password length must be 1..64");
+    return key_setup(pw, n_pw, *prm, *out);
+}
+
+extern "C" const char *lz_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" uint64_t lz_now_ns(void) {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// ---- context ---------------------------------------------------------------------------
+
+extern "C" int lz_context_create(int device, const lz_params *prm, lz_ctx **out) {
+    if (!out) return fail(LZ_E_INVAL, "out is NULL");
+    *out = nullptr;
+    lz_params p;
+    if (prm) p = *prm;
+    else lz_params_default(&p);
+    if (int rc = check_params(p)) return rc;
+    int ndev = 0;
+    LZ_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(LZ_E_INVAL, "no such HIP device");
+    LZ_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    LZ_HIP(hipGetDeviceProperties(&prop, device));
+    lz_ctx *c = new (std::nothrow) lz_ctx();
+    if (!c) return fail(LZ_E_NOMEM, "host allocation failed");
+    c->device = device;
+    c->prm = p;
+    c->dev.cus = prop.multiProcessorCount;
+    c->dev.lds_per_wg_max = (int)prop.sharedMemPerBlock;
+    c->shape = KernelShape{1, 256, 64, 4};
+    if (!shape_valid(c->shape, c->dev)) c->shape = KernelShape{1, 64, 32, 4};
+    hipError_t e = hipMalloc(&c->ws_tag, 4 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&c->ws_status, sizeof(int32_t));
+    if (e == hipSuccess) e = hipHostMalloc(&c->host_status, sizeof(int32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->last_event, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        int rc = hip_fail(e, "context allocation");
+        lz_context_destroy(c);
+        return rc;
+    }
+    c->has_last = false;
+    c->last_stream = nullptr;
+    *out = c;
+    return LZ_OK;
+}
+
+extern "C" int lz_context_destroy(lz_ctx *c) {
+    if (!c) return LZ_OK;
+    hipSetDevice(c->device);
+    if (c->has_last) hipEventSynchronize(c->last_event);
+    if (c->ws_tag) hipFree(c->ws_tag);
+    if (c->ws_status) hipFree(c->ws_status);
+    if (c->host_status) hipHostFree(c->host_status);
+    if (c->last_event) hipEventDestroy(c->last_event);
+    delete c;
+    return LZ_OK;
+}
+
+extern "C" int lz_context_params(const lz_ctx *c, lz_params *out) {
+    if (!c || !out) return fail(LZ_E_INVAL, "NULL argument");
+    *out = c->prm;
+    return LZ_OK;
+}
+
+extern "C" int lz_context_set_launch(lz_ctx *c, const lz_launch *shape) {
+    if (!c || !shape) return fail(LZ_E_INVAL, "NULL argument");
+    KernelShape s = to_shape(*shape);
+    if (!shape_valid(s, c->dev)) return fail(LZ_E_INVAL, "launch shape out of range or over the LDS limit");
+    c->shape = s;
+    return LZ_OK;
+}
+
+extern "C" int lz_context_get_launch(const lz_ctx *c, lz_launch *out) {
+    if (!c || !out) return fail(LZ_E_INVAL, "NULL argument");
+    *out = to_launch(c->shape);
+    return LZ_OK;
+}
+
+// ---- plain path ----------------------------------------------------------------------------
+
+extern "C" int lz_encrypt_key(lz_ctx *c, const lz_key *key, const uint8_t *d_P, size_t n, uint8_t *d_C,
+                              void *stream) {
+    if (!c || !key || !d_C || (!d_P && n)) return fail(LZ_E_INVAL, "NULL argument");
+    if (n > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+    hipStream_t s = (hipStream_t)stream;
+    LZ_HIP(hipSetDevice(c->device));
+    if (int rc = order_after(s, c->last_stream, c->last_event, c->has_last)) return rc;
+    LZ_HIP(launch_fill_u64(c->ws_tag, 3, s));
+    LZ_HIP(launch_plain(c->shape, *key, c->prm, 0, d_P, d_C, n, c->ws_tag, s));
+    LZ_HIP(launch_plain_finalize(0, c->ws_tag, nullptr, d_C + n, nullptr, nullptr, n, s));
+    return record(s, c->last_stream, c->last_event, c->has_last);
+}
+
+extern "C" int lz_decrypt_key(lz_ctx *c, const lz_key *key, const uint8_t *d_C, size_t n_c, uint8_t *d_P,
+                              int32_t *d_status, void *stream) {
+    if (!c || !key || !d_C) return fail(LZ_E_INVAL, "NULL argument");
+    if (n_c < LZ_TAG_BYTES) return fail(LZ_E_INVAL, "ciphertext shorter than the 24-byte tag");
+    const size_t n = n_c - LZ_TAG_BYTES;
+    if (n > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+    if (!d_P && n) return fail(LZ_E_INVAL, "NULL plaintext buffer");
+    hipStream_t s = (hipStream_t)stream;
+    LZ_HIP(hipSetDevice(c->device));
+    if (int rc = order_after(s, c->last_stream, c->last_event, c->has_last)) return rc;
+    int32_t *st = d_status ? d_status : c->ws_status;
+    LZ_HIP(launch_fill_u64(c->ws_tag, 3, s));
+    LZ_HIP(launch_plain(c->shape, *key, c->prm, 1, d_C, d_P, n, c->ws_tag, s));
+    LZ_HIP(launch_plain_finalize(1, c->ws_tag, d_C + n, nullptr, st, d_P, n, s));
+    if (d_status) return record(s, c->last_stream, c->last_event, c->has_last);
+    LZ_HIP(hipMemcpyAsync(c->host_status, c->ws_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (int rc = record(s, c->last_stream, c->last_event, c->has_last)) return rc;
+    LZ_HIP(hipStreamSynchronize(s));
+    if (*c->host_status != LZ_OK) return fail(LZ_E_INTEGRITY, "integrity check failed: ciphertext altered or wrong password");
+    return LZ_OK;
+}
+
+extern "C" int lz_encrypt(lz_ctx *c, const uint8_t *pw, size_t n_pw, const uint8_t *d_P, size_t n, uint8_t *d_C,
+                          void *stream) {
+    if (!c || !pw) return fail(LZ_E_INVAL, "NULL argument");
+    lz_key key;
+    if (int rc = lz_key_setup(pw, n_pw, &c->prm, &key)) return rc;
+    return lz_encrypt_key(c, &key, d_P, n, d_C, stream);
+}
+
+extern "C" int lz_decrypt(lz_ctx *c, const uint8_t *pw, size_t n_pw, const uint8_t *d_C, size_t n_c, uint8_t *d_P,
+                          int32_t *d_status, void *stream) {
+    if (!c || !pw) return fail(LZ_E_INVAL, "NULL argument");
+    lz_key key;
+    if (int rc = lz_key_setup(pw, n_pw, &c->prm, &key)) return rc;
+    return lz_decrypt_key(c, &key, d_C, n_c, d_P, d_status, stream);
+}
+
+// ---- batched path -----------------------------------------------------------------------------
+
+struct lz_batch {
+    lz_ctx *ctx;
+    int decrypt;
+    KernelShape shape;
+    BatchDev dev;
+    void *dmem;          // one device allocation holding every descriptor array
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    hipEvent_t last_event;
+    hipStream_t last_stream;
+    bool has_last;
+};
+
+namespace {
+
+int batch_free(lz_batch *b) {
+    if (!b) return LZ_OK;
+    hipSetDevice(b->ctx->device);
+    if (b->has_last) hipEventSynchronize(b->last_event);
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->dmem) hipFree(b->dmem);
+    if (b->last_event) hipEventDestroy(b->last_event);
+    delete b;
+    return LZ_OK;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+extern "C" int lz_batch_create(lz_ctx *c, int decrypt, size_t n_msg, const uint64_t *lens, const uint64_t *in_off,
+                               const uint64_t *out_off, const uint8_t *pw, const uint64_t *pw_off,
+                               const uint32_t *pw_len, const uint8_t *d_in, uint8_t *d_out, int32_t *d_status,
+                               const lz_launch *shape, lz_batch **out) {
+    if (!out) return fail(LZ_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !lens || !in_off || !out_off || !pw || !pw_off || !pw_len || !d_in || !d_out)
+        return fail(LZ_E_INVAL, "NULL argument");
+    if (decrypt && !d_status) return fail(LZ_E_INVAL, "decrypt batch needs d_status");
+    if (n_msg == 0 || n_msg > (1u << 30)) return fail(LZ_E_INVAL, "n_msg must be in [1, 2^30]");
+    KernelShape sh = shape ? to_shape(*shape) : c->shape;
+    if (!shape_valid(sh, c->dev)) return fail(LZ_E_INVAL, "launch shape out of range or over the LDS limit");
+    LZ_HIP(hipSetDevice(c->device));
+    const uint32_t B = c->prm.block_len;
+
+    std::vector<MsgDesc> md(n_msg);
+    std::vector<uint64_t> prefix(n_msg + 1, 0);
+    std::vector<uint32_t> tails;
+    for (size_t i = 0; i < n_msg; ++i) {
+        if (lens[i] > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+        lz_key key;
+        if (int rc = lz_key_setup(pw + pw_off[i], pw_len[i], &c->prm, &key)) return rc;
+        MsgDesc &m = md[i];
+        std::memset(&m, 0, sizeof m);
+        for (int j = 0; j < 3; ++j) {
+            m.ap[j] = key.a_prime[j];
+            m.r0[j] = key.r0[j];
+            m.mu[j] = key.mu[j];
+            m.om[j] = key.omega[j];
+            m.k[j] = key.k[j];
+        }
+        m.decrypt = (uint8_t)(decrypt ? 1 : 0);
+        m.n = lens[i];
+        m.nb = (uint32_t)(lens[i] == 0 ? 1 : (lens[i] + B - 1) / B);
+        m.in = d_in + in_off[i];
+        m.out = d_out + out_off[i];
+        prefix[i + 1] = prefix[i] + lens[i] / B;
+        if (lens[i] % B != 0 || lens[i] == 0) tails.push_back((uint32_t)i);
+    }
+    // partial blocks longest first (a wave's lanes then finish together), ties by index
+    std::stable_sort(tails.begin(), tails.end(),
+                     [&](uint32_t a, uint32_t b) { return lens[a] % B > lens[b] % B; });
+
+    lz_batch *b = new (std::nothrow) lz_batch();
+    if (!b) return fail(LZ_E_NOMEM, "host allocation failed");
+    b->ctx = c;
+    b->decrypt = decrypt ? 1 : 0;
+    b->shape = sh;
+    const size_t o_msgs = 0;
+    const size_t o_prefix = align_up(o_msgs + n_msg * sizeof(MsgDesc), 256);
+    const size_t o_tail = align_up(o_prefix + (n_msg + 1) * sizeof(uint64_t), 256);
+    const size_t o_tag = align_up(o_tail + std::max<size_t>(tails.size(), 1) * sizeof(uint32_t), 256);
+    const size_t total = o_tag + (3 * n_msg + 1) * sizeof(unsigned long long);
+    hipError_t e = hipMalloc(&b->dmem, total);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "hipMalloc(batch descriptors)");
+    }
+    char *base = static_cast<char *>(b->dmem);
+    e = hipMemcpy(base + o_msgs, md.data(), n_msg * sizeof(MsgDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(base + o_prefix, prefix.data(), (n_msg + 1) * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tails.empty())
+        e = hipMemcpy(base + o_tail, tails.data(), tails.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "hipMemcpy(batch descriptors)");
+    }
+    BatchDev &d = b->dev;
+    d.msgs = reinterpret_cast<const MsgDesc *>(base + o_msgs);
+    d.full_prefix = reinterpret_cast<const uint64_t *>(base + o_prefix);
+    d.tail_msg = reinterpret_cast<const uint32_t *>(base + o_tail);
+    d.n_msg = (uint32_t)n_msg;
+    d.n_tail = (uint32_t)tails.size();
+    d.n_full = prefix[n_msg];
+    const uint64_t per_task = 64ull * sh.m;
+    d.n_tasks = (d.n_full + d.n_tail + per_task - 1) / per_task;
+    d.tag_acc = reinterpret_cast<unsigned long long *>(base + o_tag);
+    d.counter = d.tag_acc + 3 * n_msg;
+    d.status = d_status;
+
+    // capture [reset, persistent kernel, finalize]
+    hipStream_t cap;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "hipStreamCreate");
+    }
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e1 = launch_fill_u64(d.tag_acc, 3 * n_msg + 1, cap);
+        hipError_t e2 = e1 == hipSuccess ? launch_batch(sh, c->dev, c->prm, d, cap) : e1;
+        hipError_t e3 = e2 == hipSuccess ? launch_batch_finalize(d, b->decrypt, cap) : e2;
+        e = hipStreamEndCapture(cap, &b->graph);
+        if (e3 != hipSuccess) e = e3;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    hipStreamDestroy(cap);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->last_event, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "batch graph capture");
+    }
+    *out = b;
+    return LZ_OK;
+}
+
+extern "C" int lz_batch_launch(lz_batch *b, void *stream) {
+    if (!b) return fail(LZ_E_INVAL, "batch is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    LZ_HIP(hipSetDevice(b->ctx->device));
+    if (int rc = order_after(s, b->last_stream, b->last_event, b->has_last)) return rc;
+    LZ_HIP(hipGraphLaunch(b->exec, s));
+    return record(s, b->last_stream, b->last_event, b->has_last);
+}
+
+extern "C" int lz_batch_destroy(lz_batch *b) { return batch_free(b); }
+
+// ---- autotuner ---------------------------------------------------------------------------------
+
+extern "C" int lz_autotune(lz_ctx *c, double budget_ms, lz_launch *best) {
+    if (!c) return fail(LZ_E_INVAL, "ctx is NULL");
+    LZ_HIP(hipSetDevice(c->device));
+    const uint32_t B = c->prm.block_len;
+    // synthetic batch: about 1.5 resident rounds of single-chain lanes at 4 waves per SIMD,
+    // in messages of 64 full blocks plus a ragged tail, random bytes, distinct passwords
+    const uint64_t chains = (uint64_t)c->dev.cus * 4 * 4 * 64 * 3 / 2;
+    const uint64_t per_msg = 64;
+    const size_t n_msg = (size_t)((chains + per_msg - 1) / per_msg);
+    std::vector<uint64_t> lens(n_msg), in_off(n_msg), out_off(n_msg), pw_off(n_msg);
+    std::vector<uint32_t> pw_len(n_msg);
+    std::vector<uint8_t> pw(n_msg * 16);
+    uint64_t tot_in = 0, tot_out = 0;
+    uint64_t st = 0x9E3779B97F4A7C15ull;
+    auto rnd = [&]() {
+        st ^= st << 13;
+        st ^= st >> 7;
+        st ^= st << 17;
+        return st;
+    };
+    for (size_t i = 0; i < n_msg; ++i) {
+        lens[i] = per_msg * B - (i % 4 == 3 ? (rnd() % B) : 0);
+        in_off[i] = tot_in;
+        out_off[i] = tot_out;
+        tot_in += lens[i];
+        tot_out += lens[i] + LZ_TAG_BYTES;
+        pw_off[i] = 16 * i;
+        pw_len[i] = 16;
+        for (int q = 0; q < 16; ++q) pw[16 * i + q] = (uint8_t)(32 + rnd() % 95);
+    }
+    uint8_t *d_in = nullptr, *d_out = nullptr;
+    LZ_HIP(hipMalloc(&d_in, tot_in));
+    hipError_t e = hipMalloc(&d_out, tot_out);
+    if (e != hipSuccess) {
+        hipFree(d_in);
+        return hip_fail(e, "hipMalloc(autotune)");
+    }
+    {
+        std::vector<uint8_t> h(tot_in);
+        for (auto &v : h) v = (uint8_t)rnd();
+        e = hipMemcpy(d_in, h.data(), tot_in, hipMemcpyHostToDevice);
+    }
+    hipStream_t s = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    KernelShape best_sh = c->shape;
+    double best_ms = 1e30, spent = 0;
+    const int ms_[] = {1, 2, 4};
+    const int wps_[] = {1, 2, 4, 8};
+    const int wg_[] = {64, 256};
+    const int tile_[] = {64, 128};
+    int rc = LZ_OK;
+    for (int m : ms_)
+        for (int wps : wps_)
+            for (int wg : wg_)
+                for (int tile : tile_) {
+                    if (e != hipSuccess || rc != LZ_OK) break;
+                    if (m * wps < 4 || m * wps > 8) continue;  // 4..8 chains in flight per SIMD slot
+                    KernelShape sh{m, wg, tile, wps};
+                    if (!shape_valid(sh, c->dev)) continue;
+                    if (budget_ms > 0 && spent > budget_ms) continue;
+                    lz_launch l = to_launch(sh);
+                    lz_batch *b = nullptr;
+                    rc = lz_batch_create(c, 0, n_msg, lens.data(), in_off.data(), out_off.data(), pw.data(),
+                                         pw_off.data(), pw_len.data(), d_in, d_out, nullptr, &l, &b);
+                    if (rc != LZ_OK) break;
+                    double ms = 0;
+                    rc = lz_batch_launch(b, s);  // warm-up
+                    if (rc == LZ_OK) e = hipEventRecord(t0, s);
+                    if (rc == LZ_OK && e == hipSuccess) rc = lz_batch_launch(b, s);
+                    if (rc == LZ_OK && e == hipSuccess) e = hipEventRecord(t1, s);
+                    if (rc == LZ_OK && e == hipSuccess) e = hipEventSynchronize(t1);
+                    float f = 0;
+                    if (rc == LZ_OK && e == hipSuccess) e = hipEventElapsedTime(&f, t0, t1);
+                    ms = f;
+                    spent += 2 * ms;
+                    lz_batch_destroy(b);
+                    if (rc == LZ_OK && e == hipSuccess && ms < best_ms) {
+                        best_ms = ms;
+                        best_sh = sh;
+                    }
+                }
+    if (t0) hipEventDestroy(t0);
+    if (t1) hipEventDestroy(t1);
+    if (s) hipStreamDestroy(s);
+    hipFree(d_in);
+    hipFree(d_out);
+    if (rc != LZ_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    c->shape = best_sh;
+    if (best) *best = to_launch(best_sh);
+    return LZ_OK;
+}

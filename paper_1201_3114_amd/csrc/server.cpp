@@ -1,0 +1,516 @@
+// Continuous-batching request loop (serving).  Each admitted request gets one
+// chain slot per block (block b of the parallel version, Section 5), a
+// device-side request record and arena space for its input and output bytes.
+// Every tick advances all unfinished chains by up to tick_bytes bytes with
+// the exact per-chain checkpoint (r, alpha, mu, Omega) kept in device memory,
+// so a request's bytes do not depend on what else is admitted.  Requests that
+// arrive while a tick runs are admitted at the next tick boundary, as chain
+// slots and the device-memory budget allow (FIFO, no overtaking).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <queue>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+using namespace lz;
+
+namespace {
+
+// First-fit allocator over [0, size) with coalescing free list.
+class Arena {
+  public:
+    explicit Arena(uint64_t size = 0) { reset(size); }
+    void reset(uint64_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+        size_ = size;
+        used_ = 0;
+    }
+    bool alloc(uint64_t bytes, uint64_t &off) {
+        bytes = (bytes + 255) / 256 * 256;
+        if (bytes == 0) bytes = 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            off = it->first;
+            const uint64_t rest = it->second - bytes;
+            free_.erase(it);
+            if (rest) free_[off + bytes] = rest;
+            used_ += bytes;
+            return true;
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t bytes) {
+        bytes = (bytes + 255) / 256 * 256;
+        if (bytes == 0) bytes = 256;
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t used() const { return used_; }
+    uint64_t size() const { return size_; }
+
+  private:
+    std::map<uint64_t, uint64_t> free_;
+    uint64_t size_ = 0, used_ = 0;
+};
+
+struct Request {
+    uint64_t id, seq;
+    int decrypt;
+    lz_key key;
+    const void *src;
+    void *dst;
+    uint64_t n;          // plaintext length
+    uint64_t arrival_ns;
+    uint64_t admit_ns = 0;
+    // placement
+    uint32_t req_slot = 0;
+    uint32_t nb = 0;
+    std::vector<uint32_t> slots;  // chain slot of block b
+    size_t active_idx = 0;
+    uint64_t arena_off = 0, arena_bytes = 0;
+    uint32_t ticks_full = 0, ticks_tail = 0;  // ticks until full / tail chains finish
+    uint32_t ticks_run = 0;
+};
+
+struct ArrivalLater {
+    bool operator()(const Request *a, const Request *b) const {
+        return a->arrival_ns != b->arrival_ns ? a->arrival_ns > b->arrival_ns : a->seq > b->seq;
+    }
+};
+
+uint64_t in_len(const Request &r) { return r.decrypt ? r.n + LZ_TAG_BYTES : r.n; }
+uint64_t out_len(const Request &r) { return r.decrypt ? r.n : r.n + LZ_TAG_BYTES; }
+
+}  // namespace
+
+struct lz_server {
+    lz_ctx *ctx;
+    lz_server_config cfg;
+    KernelShape shape;
+    uint32_t max_chains, max_reqs;
+    // device memory
+    uint8_t *arena_mem = nullptr;
+    ChainSlot *slots = nullptr;
+    ReqDesc *reqs = nullptr;
+    uint32_t *d_list = nullptr;
+    uint32_t *d_done = nullptr;  // [0] = count, [1..] = queue
+    uint32_t *d_zero_ids = nullptr;
+    ReqDesc *d_stage_reqs = nullptr;
+    uint32_t *d_stage_meta = nullptr;  // per new request: req_slot, nb, index offset
+    uint32_t *d_stage_idx = nullptr;   // chain slots of the new requests
+    // pinned staging
+    uint32_t *h_list = nullptr;
+    uint32_t *h_done = nullptr;
+    uint32_t *h_zero_ids = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    Arena arena;
+    // host bookkeeping (server thread only)
+    std::vector<uint32_t> free_slots;
+    std::vector<uint32_t> free_reqs;
+    std::vector<Request *> by_slot;
+    std::vector<Request *> active;
+    std::deque<Request *> waiting;  // arrived, not admitted (FIFO)
+    uint64_t hbm_fixed = 0;
+    // shared with submitters / pollers
+    std::mutex mu;
+    std::condition_variable cv_submit, cv_done;
+    std::priority_queue<Request *, std::vector<Request *>, ArrivalLater> pending;
+    std::deque<lz_completion> done;
+    uint64_t seq = 0;
+    bool stop = false;
+    int error = LZ_OK;
+    std::thread th;
+    lz_server_stats stats{};
+};
+
+namespace {
+
+void finish(lz_server *s, Request *r, int32_t status, uint64_t done_ns) {
+    lz_completion c{};
+    c.id = r->id;
+    c.status = status;
+    c.arrival_ns = r->arrival_ns;
+    c.admit_ns = r->admit_ns;
+    c.done_ns = done_ns;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->done.push_back(c);
+        s->stats.completed++;
+    }
+    s->cv_done.notify_all();
+    delete r;
+}
+
+// Admits waiting requests in FIFO order while slots and memory allow.
+int admit(lz_server *s, std::vector<Request *> &admitted) {
+    const uint32_t B = s->ctx->prm.block_len;
+    while (!s->waiting.empty()) {
+        Request *r = s->waiting.front();
+        const uint32_t nb = (uint32_t)(r->n == 0 ? 1 : (r->n + B - 1) / B);
+        const uint64_t bytes = ((in_len(*r) + 255) / 256 + (out_len(*r) + 255) / 256) * 256;
+        if (nb > s->max_chains || bytes > s->arena.size()) {  // can never fit
+            s->waiting.pop_front();
+            finish(s, r, LZ_E_NOMEM, lz_now_ns());
+            continue;
+        }
+        if (s->free_reqs.empty() || s->free_slots.size() < nb) break;
+        uint64_t off;
+        if (!s->arena.alloc(bytes, off)) break;
+        s->waiting.pop_front();
+        r->slots.assign(s->free_slots.end() - nb, s->free_slots.end());
+        s->free_slots.resize(s->free_slots.size() - nb);
+        r->nb = nb;
+        r->arena_off = off;
+        r->arena_bytes = bytes;
+        r->req_slot = s->free_reqs.back();
+        s->free_reqs.pop_back();
+        s->by_slot[r->req_slot] = r;
+        r->admit_ns = lz_now_ns();
+        const uint32_t T = s->cfg.tick_bytes;
+        const uint64_t tail = r->n == 0 ? 0 : r->n - (uint64_t)(nb - 1) * B;
+        r->ticks_full = nb > 1 ? (B + T - 1) / T : 0;
+        r->ticks_tail = tail == 0 ? 1 : (uint32_t)((tail + T - 1) / T);
+        r->ticks_run = 0;
+        admitted.push_back(r);
+        s->stats.admitted++;
+    }
+    const uint64_t inuse = s->arena.used() + s->hbm_fixed;
+    if (inuse > s->stats.peak_hbm) s->stats.peak_hbm = inuse;
+    return LZ_OK;
+}
+
+int server_tick(lz_server *s) {
+    hipStream_t st = s->stream;
+    std::vector<Request *> admitted;
+    admit(s, admitted);
+    if (!admitted.empty()) {
+        const size_t k = admitted.size();
+        std::vector<ReqDesc> staged(k);
+        std::vector<uint32_t> meta(3 * k), idx;
+        for (size_t i = 0; i < k; ++i) {
+            Request *r = admitted[i];
+            ReqDesc &d = staged[i];
+            std::memset(&d, 0, sizeof d);
+            for (int j = 0; j < 3; ++j) {
+                d.m.ap[j] = r->key.a_prime[j];
+                d.m.r0[j] = r->key.r0[j];
+                d.m.mu[j] = r->key.mu[j];
+                d.m.om[j] = r->key.omega[j];
+                d.m.k[j] = r->key.k[j];
+            }
+            d.m.decrypt = (uint8_t)r->decrypt;
+            d.m.nb = r->nb;
+            d.m.n = r->n;
+            uint8_t *in = s->arena_mem + r->arena_off;
+            uint8_t *out = in + (in_len(*r) + 255) / 256 * 256;
+            d.m.in = in;
+            d.m.out = out;
+            d.remaining = r->nb;
+            d.status = LZ_OK;
+            d.stored_tag = in + r->n;
+            meta[3 * i] = r->req_slot;
+            meta[3 * i + 1] = r->nb;
+            meta[3 * i + 2] = (uint32_t)idx.size();
+            idx.insert(idx.end(), r->slots.begin(), r->slots.end());
+            if (in_len(*r)) LZ_HIP(hipMemcpyAsync(in, r->src, in_len(*r), hipMemcpyDefault, st));
+        }
+        // install the new request records and their fresh chain slots on the device
+        LZ_HIP(hipMemcpyAsync(s->d_stage_reqs, staged.data(), k * sizeof(ReqDesc), hipMemcpyHostToDevice, st));
+        LZ_HIP(hipMemcpyAsync(s->d_stage_meta, meta.data(), meta.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        LZ_HIP(hipMemcpyAsync(s->d_stage_idx, idx.data(), idx.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        LZ_HIP(launch_install(s->reqs, s->slots, s->d_stage_reqs, s->d_stage_meta, s->d_stage_idx, (uint32_t)k,
+                              s->ctx->prm.block_len, st));
+        for (Request *r : admitted) {
+            r->active_idx = s->active.size();
+            s->active.push_back(r);
+        }
+        LZ_HIP(hipStreamSynchronize(st));  // pageable sources above must be consumed before they go away
+    }
+    if (s->active.empty()) return LZ_OK;
+    // active chain list: full chains until they finish, tail chain until it finishes
+    const uint32_t T = s->cfg.tick_bytes, B = s->ctx->prm.block_len;
+    uint32_t n_list = 0;
+    uint64_t tick_bytes = 0;
+    for (Request *r : s->active) {
+        const uint32_t t = r->ticks_run;
+        if (t < r->ticks_full) {
+            for (uint32_t b = 0; b + 1 < r->nb; ++b) s->h_list[n_list++] = r->slots[b];
+            tick_bytes += (uint64_t)(r->nb - 1) * std::min<uint64_t>(T, B - (uint64_t)t * T);
+        }
+        if (t < r->ticks_tail) {
+            s->h_list[n_list++] = r->slots[r->nb - 1];
+            const uint64_t tail = r->n - (uint64_t)(r->nb - 1) * B;
+            const uint64_t done = (uint64_t)t * T;
+            tick_bytes += tail > done ? std::min<uint64_t>(T, tail - done) : 0;
+        }
+    }
+    LZ_HIP(hipMemcpyAsync(s->d_list, s->h_list, n_list * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    LZ_HIP(launch_fill_u64(reinterpret_cast<unsigned long long *>(s->d_done), 1, st));
+    TickDev t;
+    t.slots = s->slots;
+    t.reqs = s->reqs;
+    t.list = s->d_list;
+    t.n_list = n_list;
+    t.tick_bytes = s->cfg.tick_bytes;
+    t.done_count = s->d_done;
+    t.done_queue = s->d_done + 2;
+    LZ_HIP(hipEventRecord(s->ev_a, st));
+    LZ_HIP(launch_tick(s->shape, s->ctx->prm, t, st));
+    LZ_HIP(hipEventRecord(s->ev_b, st));
+    LZ_HIP(hipMemcpyAsync(s->h_done, s->d_done, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    LZ_HIP(hipStreamSynchronize(st));
+    float ms = 0;
+    hipEventElapsedTime(&ms, s->ev_a, s->ev_b);
+    s->stats.busy_ms += ms;
+    s->stats.ticks++;
+    s->stats.chain_bytes += tick_bytes;
+    for (Request *r : s->active) r->ticks_run++;
+    const uint32_t nd = s->h_done[0];
+    if (nd == 0) return LZ_OK;
+    LZ_HIP(hipMemcpyAsync(s->h_done + 2, s->d_done + 2, nd * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    LZ_HIP(hipStreamSynchronize(st));
+    uint32_t nz = 0;
+    for (uint32_t i = 0; i < nd; ++i)
+        if (s->h_done[2 + i] & 1u) s->h_zero_ids[nz++] = s->h_done[2 + i] >> 1;
+    if (nz) {
+        LZ_HIP(hipMemcpyAsync(s->d_zero_ids, s->h_zero_ids, nz * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        LZ_HIP(launch_req_zero(s->reqs, s->d_zero_ids, nz, st));
+    }
+    std::vector<std::pair<Request *, int32_t>> fin;
+    for (uint32_t i = 0; i < nd; ++i) {
+        const uint32_t slot = s->h_done[2 + i] >> 1;
+        Request *r = s->by_slot[slot];
+        const int32_t status = (s->h_done[2 + i] & 1u) ? LZ_E_INTEGRITY : LZ_OK;
+        uint8_t *in = s->arena_mem + r->arena_off;
+        uint8_t *out = in + (in_len(*r) + 255) / 256 * 256;
+        if (out_len(*r)) LZ_HIP(hipMemcpyAsync(r->dst, out, out_len(*r), hipMemcpyDefault, st));
+        fin.emplace_back(r, status);
+    }
+    LZ_HIP(hipStreamSynchronize(st));
+    const uint64_t now = lz_now_ns();
+    for (auto &f : fin) {
+        Request *r = f.first;
+        s->arena.release(r->arena_off, r->arena_bytes);
+        s->free_slots.insert(s->free_slots.end(), r->slots.begin(), r->slots.end());
+        s->free_reqs.push_back(r->req_slot);
+        s->by_slot[r->req_slot] = nullptr;
+        Request *last = s->active.back();  // swap-remove
+        s->active[r->active_idx] = last;
+        last->active_idx = r->active_idx;
+        s->active.pop_back();
+        finish(s, r, f.second, now);
+    }
+    return LZ_OK;
+}
+
+void server_loop(lz_server *s) {
+    hipSetDevice(s->ctx->device);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> g(s->mu);
+            for (;;) {
+                const uint64_t now = lz_now_ns();
+                while (!s->pending.empty() && s->pending.top()->arrival_ns <= now) {
+                    s->waiting.push_back(s->pending.top());
+                    s->pending.pop();
+                }
+                if (!s->waiting.empty() || !s->active.empty()) break;
+                if (s->stop && s->pending.empty()) return;
+                if (s->pending.empty()) {
+                    s->cv_submit.wait(g);
+                } else {
+                    const uint64_t dt = s->pending.top()->arrival_ns - now;
+                    s->cv_submit.wait_for(g, std::chrono::nanoseconds(dt));
+                }
+            }
+        }
+        if (int rc = server_tick(s)) {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->error = rc;
+            s->stop = true;
+            s->cv_done.notify_all();
+            return;
+        }
+    }
+}
+
+void server_free(lz_server *s) {
+    if (!s) return;
+    hipSetDevice(s->ctx->device);
+    if (s->stream) hipStreamSynchronize(s->stream);
+    hipFree(s->arena_mem);
+    hipFree(s->slots);
+    hipFree(s->reqs);
+    hipFree(s->d_list);
+    hipFree(s->d_done);
+    hipFree(s->d_zero_ids);
+    hipFree(s->d_stage_reqs);
+    hipFree(s->d_stage_meta);
+    hipFree(s->d_stage_idx);
+    hipHostFree(s->h_list);
+    hipHostFree(s->h_done);
+    hipHostFree(s->h_zero_ids);
+    if (s->ev_a) hipEventDestroy(s->ev_a);
+    if (s->ev_b) hipEventDestroy(s->ev_b);
+    if (s->stream) hipStreamDestroy(s->stream);
+    while (!s->pending.empty()) {
+        delete s->pending.top();
+        s->pending.pop();
+    }
+    for (Request *r : s->waiting) delete r;
+    for (Request *r : s->active) delete r;
+    delete s;
+}
+
+}  // namespace
+
+extern "C" int lz_server_create(lz_ctx *c, const lz_server_config *cfg, lz_server **out) {
+    if (!out) return fail(LZ_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !cfg) return fail(LZ_E_INVAL, "NULL argument");
+    LZ_HIP(hipSetDevice(c->device));
+    lz_server *s = new (std::nothrow) lz_server();
+    if (!s) return fail(LZ_E_NOMEM, "host allocation failed");
+    s->ctx = c;
+    s->cfg = *cfg;
+    if (s->cfg.tick_bytes == 0) s->cfg.tick_bytes = 16;
+    if (s->cfg.tick_bytes > (1u << 20)) {
+        delete s;
+        return fail(LZ_E_INVAL, "tick_bytes must be <= 2^20");
+    }
+    s->max_chains = cfg->max_chains ? cfg->max_chains : (uint32_t)c->dev.cus * 4 * 4 * 64;
+    s->max_reqs = s->max_chains;
+    int tile = 16;
+    while (tile < (int)s->cfg.tick_bytes && tile < 128) tile *= 2;
+    s->shape = KernelShape{1, 256, tile, 4};
+    if (!shape_valid(s->shape, c->dev)) s->shape = KernelShape{1, 64, 16, 4};
+    // fixed device memory: chain slots, request records, lists and staging
+    const uint64_t fixed = (uint64_t)s->max_chains * sizeof(ChainSlot) + (uint64_t)s->max_reqs * sizeof(ReqDesc) * 2 +
+                           (uint64_t)s->max_chains * 4 * 2 + (uint64_t)s->max_reqs * 4 * 5 + (1u << 20);
+    if (cfg->hbm_budget <= fixed + 4096) {
+        delete s;
+        return fail(LZ_E_INVAL, "hbm_budget too small for the chain slots");
+    }
+    s->hbm_fixed = fixed;
+    const uint64_t arena_bytes = cfg->hbm_budget - fixed;
+    hipError_t e = hipMalloc(&s->arena_mem, arena_bytes);
+    if (e == hipSuccess) e = hipMalloc(&s->slots, (size_t)s->max_chains * sizeof(ChainSlot));
+    if (e == hipSuccess) e = hipMalloc(&s->reqs, (size_t)s->max_reqs * sizeof(ReqDesc));
+    if (e == hipSuccess) e = hipMalloc(&s->d_list, (size_t)s->max_chains * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&s->d_done, ((size_t)s->max_reqs + 2) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&s->d_zero_ids, (size_t)s->max_reqs * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&s->d_stage_reqs, (size_t)s->max_reqs * sizeof(ReqDesc));
+    if (e == hipSuccess) e = hipMalloc(&s->d_stage_meta, 3 * (size_t)s->max_reqs * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&s->d_stage_idx, (size_t)s->max_chains * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipHostMalloc(&s->h_list, (size_t)s->max_chains * sizeof(uint32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&s->h_done, ((size_t)s->max_reqs + 2) * sizeof(uint32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(&s->h_zero_ids, (size_t)s->max_reqs * sizeof(uint32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&s->ev_a);
+    if (e == hipSuccess) e = hipEventCreate(&s->ev_b);
+    if (e != hipSuccess) {
+        int rc = hip_fail(e, "server allocation");
+        server_free(s);
+        return rc;
+    }
+    s->arena.reset(arena_bytes);
+    s->free_slots.resize(s->max_chains);
+    for (uint32_t i = 0; i < s->max_chains; ++i) s->free_slots[i] = s->max_chains - 1 - i;
+    s->free_reqs.resize(s->max_reqs);
+    for (uint32_t i = 0; i < s->max_reqs; ++i) s->free_reqs[i] = s->max_reqs - 1 - i;
+    s->by_slot.assign(s->max_reqs, nullptr);
+    s->th = std::thread(server_loop, s);
+    *out = s;
+    return LZ_OK;
+}
+
+extern "C" int lz_server_submit(lz_server *s, uint64_t id, int decrypt, const uint8_t *pw, size_t n_pw,
+                                const void *src, uint64_t n, void *dst, uint64_t arrival_ns) {
+    if (!s || !pw) return fail(LZ_E_INVAL, "NULL argument");
+    if (n > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+    const uint64_t nin = decrypt ? n + LZ_TAG_BYTES : n, nout = decrypt ? n : n + LZ_TAG_BYTES;
+    if ((nin && !src) || (nout && !dst)) return fail(LZ_E_INVAL, "NULL buffer");
+    Request *r = new (std::nothrow) Request();
+    if (!r) return fail(LZ_E_NOMEM, "host allocation failed");
+    if (int rc = lz_key_setup(pw, n_pw, &s->ctx->prm, &r->key)) {
+        delete r;
+        return rc;
+    }
+    r->id = id;
+    r->decrypt = decrypt ? 1 : 0;
+    r->src = src;
+    r->dst = dst;
+    r->n = n;
+    r->arrival_ns = arrival_ns ? arrival_ns : lz_now_ns();
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->stop) {
+            delete r;
+            return fail(s->error ? s->error : LZ_E_INVAL, "server stopped");
+        }
+        r->seq = s->seq++;
+        s->pending.push(r);
+    }
+    s->cv_submit.notify_all();
+    return LZ_OK;
+}
+
+extern "C" int lz_server_poll(lz_server *s, lz_completion *out, int max, int timeout_ms) {
+    if (!s || (!out && max > 0) || max < 0) return fail(LZ_E_INVAL, "bad argument");
+    std::unique_lock<std::mutex> g(s->mu);
+    auto ready = [&] { return !s->done.empty() || s->error; };
+    if (timeout_ms < 0) s->cv_done.wait(g, ready);
+    else if (timeout_ms > 0) s->cv_done.wait_for(g, std::chrono::milliseconds(timeout_ms), ready);
+    if (s->error && s->done.empty()) return fail(s->error, "server loop failed");
+    int k = 0;
+    while (k < max && !s->done.empty()) {
+        out[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    return k;
+}
+
+extern "C" int lz_server_stats_get(lz_server *s, lz_server_stats *out) {
+    if (!s || !out) return fail(LZ_E_INVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    *out = s->stats;
+    return LZ_OK;
+}
+
+extern "C" int lz_server_destroy(lz_server *s) {
+    if (!s) return LZ_OK;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+    }
+    s->cv_submit.notify_all();
+    if (s->th.joinable()) s->th.join();
+    const int err = s->error;
+    server_free(s);
+    return err;
+}

@@ -1,0 +1,192 @@
+"""GPU plain path vs the CPU oracle, bit for bit (Sections 3.2 and 5)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import ORACLE_THREADS, host, need_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lz():
+    need_gpu()
+    import paper_1201_3114_amd as lz
+
+    return lz
+
+
+def _ctx(lz, **kw):
+    return lz.Context(0, lz.params(**kw))
+
+
+def test_plain_64k_config_bit_exact(lz):
+    """64 KiB uniform bytes, 16-byte printable password, default parameters: E and D vs oracle."""
+    from paper_1201_3114_amd import workloads
+
+    P, pw = workloads.plain("plain_64k")
+    say("plain_64k", len(P), pw)
+    ctx = _ctx(lz)
+    C = ctx.encrypt(to_dev(P), pw)
+    want = oracle.encrypt(pw, P, nthreads=ORACLE_THREADS)
+    assert np.array_equal(host(C), want)
+    Q = ctx.decrypt(C, pw)
+    assert np.array_equal(host(Q), P)
+    Qo, ok = oracle.decrypt(pw, want, nthreads=ORACLE_THREADS)
+    assert ok and np.array_equal(Qo, P)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65, 255, 256, 257, 1000, 3 * 256 + 77, 64 * 256, 64 * 256 + 1,
+                               300 * 256 + 131])
+def test_plain_sizes_ragged(lz, n):
+    """Empty, sub-block, exact-block and ragged messages spanning several LDS tiles and waves."""
+    rng = np.random.default_rng(1000 + n)
+    P = rng.integers(0, 256, n, dtype=np.uint8)
+    pw = bytes(rng.integers(32, 127, 1 + n % 64, dtype=np.uint8))
+    say("ragged n", n)
+    ctx = _ctx(lz, n_it=40)
+    C = ctx.encrypt(to_dev(P), pw)
+    want = oracle.encrypt(pw, P, nthreads=ORACLE_THREADS, n_it=40)
+    assert np.array_equal(host(C), want)
+    assert np.array_equal(host(ctx.decrypt(C, pw)), P)
+
+
+@pytest.mark.parametrize("m", [1, 2, 4])
+@pytest.mark.parametrize("wg", [64, 256])
+@pytest.mark.parametrize("tile", [16, 32, 64, 128])
+def test_launch_shapes_identical(lz, m, wg, tile):
+    """Every launch shape gives the oracle's bytes (the schedule cannot change the result)."""
+    rng = np.random.default_rng(7)
+    n = 200 * 256 + 99
+    P = rng.integers(0, 256, n, dtype=np.uint8)
+    ctx = _ctx(lz, n_it=25)
+    shape = lz.LaunchShape(m, wg, tile, 4)
+    try:
+        ctx.set_launch(shape)
+    except lz.LorenzError:
+        pytest.skip("shape over the LDS limit of this device")
+    say("shape", shape)
+    C = ctx.encrypt(to_dev(P), b"shapes")
+    want = oracle.encrypt(b"shapes", P, nthreads=ORACLE_THREADS, n_it=25)
+    assert np.array_equal(host(C), want)
+    assert np.array_equal(host(ctx.decrypt(C, b"shapes")), P)
+
+
+@pytest.mark.parametrize("kw", [dict(block_len=1), dict(block_len=3), dict(block_len=64), dict(block_len=1000),
+                                dict(k=(3, 3, 3)), dict(k=(4, 3, 4)), dict(dt=0.024), dict(dt=0.001),
+                                dict(lam=(-15.0, 15.9, 61.5)), dict(n_it=1), dict(n_it=7)])
+def test_parameters_vs_oracle(lz, kw):
+    rng = np.random.default_rng(11)
+    n = 5000
+    P = rng.integers(0, 256, n, dtype=np.uint8)
+    kw2 = dict(n_it=30)
+    kw2.update(kw)
+    say("params", kw2)
+    ctx = _ctx(lz, **kw2)
+    C = ctx.encrypt(to_dev(P), b"parameter sweep")
+    want = oracle.encrypt(b"parameter sweep", P, nthreads=ORACLE_THREADS, **kw2)
+    assert np.array_equal(host(C), want)
+
+
+def test_password_lengths_and_bytes(lz):
+    rng = np.random.default_rng(12)
+    ctx = _ctx(lz, n_it=20)
+    for npw in (1, 2, 3, 4, 5, 17, 18, 63, 64):
+        pw = bytes(rng.integers(0, 256, npw, dtype=np.uint8))
+        P = rng.integers(0, 256, 700, dtype=np.uint8)
+        C = ctx.encrypt(to_dev(P), pw)
+        assert np.array_equal(host(C), oracle.encrypt(pw, P, n_it=20)), npw
+
+
+def test_tamper_detected_and_zeroed(lz):
+    """A changed ciphertext byte (body or tag) fails the tag; the plaintext comes back zeroed."""
+    import torch
+
+    rng = np.random.default_rng(13)
+    P = rng.integers(0, 256, 2000, dtype=np.uint8)
+    ctx = _ctx(lz, n_it=50)
+    C = ctx.encrypt(to_dev(P), b"tamper")
+    for off in (0, 1, 255, 256, 1999, 2000, 2023):
+        bad = C.clone()
+        bad[off] ^= int(rng.integers(1, 256))
+        say("tamper offset", off)
+        with pytest.raises(lz.IntegrityError):
+            ctx.decrypt(bad, b"tamper")
+        st = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+        out = ctx.decrypt(bad, b"tamper", status=st)
+        torch.cuda.synchronize()
+        assert int(st.item()) == -2
+        assert not host(out).any()
+        # the oracle agrees the altered ciphertext fails
+        assert not oracle.decrypt(b"tamper", host(bad), n_it=50)[1]
+    with pytest.raises(lz.IntegrityError):
+        ctx.decrypt(C, b"tamper!")
+    st = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    ctx.decrypt(C, b"tamper", status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+
+
+def test_streams_and_async_status(lz):
+    """Calls on two streams through one context stay ordered; results equal the oracle."""
+    import torch
+
+    rng = np.random.default_rng(14)
+    ctx = _ctx(lz, n_it=30)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    Ps = [rng.integers(0, 256, 3000 + 17 * i, dtype=np.uint8) for i in range(6)]
+    outs = []
+    for i, P in enumerate(Ps):
+        s = s1 if i % 2 else s2
+        with torch.cuda.stream(s):
+            d = to_dev(P)
+            outs.append(ctx.encrypt(d, b"streams %d" % i, stream=s))
+    torch.cuda.synchronize()
+    for i, P in enumerate(Ps):
+        assert np.array_equal(host(outs[i]), oracle.encrypt(b"streams %d" % i, P, n_it=30))
+
+
+def test_invalid_arguments(lz):
+    import torch
+
+    ctx = _ctx(lz)
+    with pytest.raises(lz.LorenzError):
+        ctx.encrypt(torch.zeros(10, dtype=torch.uint8, device="cuda"), b"")
+    with pytest.raises(lz.LorenzError):
+        ctx.encrypt(torch.zeros(10, dtype=torch.uint8, device="cuda"), b"x" * 65)
+    with pytest.raises(ValueError):
+        ctx.decrypt(torch.zeros(10, dtype=torch.uint8, device="cuda"), b"pw")
+    with pytest.raises(lz.LorenzError):
+        ctx.set_launch(lz.LaunchShape(3, 256, 64, 4))
+    with pytest.raises(lz.LorenzError):
+        lz.Context(0, lz.params(dt=0.03))
+
+
+def test_plain_64m_sampled(lz):
+    """64 MiB, 32-byte password, the benchmark's launch shape: sampled blocks vs oracle,
+    round trip, and tamper detection at sampled offsets."""
+    import torch
+
+    from paper_1201_3114_amd import workloads
+
+    P, pw = workloads.plain("plain_64m")
+    n = len(P)
+    B = 256
+    say("plain_64m", n)
+    ctx = _ctx(lz)
+    dP = to_dev(P)
+    C = ctx.encrypt(dP, pw)
+    Cg = host(C)
+    rng = np.random.default_rng(99)
+    nb = n // B
+    blocks = sorted(set([0, 1, nb - 1] + list(rng.integers(0, nb, 45))))
+    for b in blocks:
+        out, _ = oracle.crypt_block(pw, int(b), P[b * B:(b + 1) * B])
+        assert np.array_equal(Cg[b * B:(b + 1) * B], out), b
+    Q = ctx.decrypt(C, pw)
+    assert torch.equal(Q, dP)
+    for off in (0, n // 2 + 3, n - 1, n + 5):
+        bad = C.clone()
+        bad[off] ^= 0x10
+        with pytest.raises(lz.IntegrityError):
+            ctx.decrypt(bad, pw)
