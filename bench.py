@@ -1,0 +1,404 @@
+"""Benchmark of the Lorenz chaotic cipher on one MI355X.
+
+One step = encrypt + decrypt of a 64 MiB message of uniform random bytes with a
+32-byte printable password (parallel version, default parameters, binary64),
+inputs resident in HBM.  value = 2 * 64 MiB * steps / timed seconds (GB = 1e9 B).
+
+Beside it, on the same line:
+  roofline     the plain kernel's algorithmic binary64 operations per launch over
+               its average launch time (HIP events on the launch stream) against
+               the FP64 VALU issue peak of the chip;
+  cpu_baseline the CPU oracle on a bounded prefix of the same message;
+  batched      4096 messages (log-uniform 1 KiB..1 MiB, own passwords) in one
+               graph-captured persistent launch, vs the plain path per message,
+               and the integrity check of 10% altered ciphertexts;
+  served       a Poisson trace of mixed encrypt/decrypt requests through the
+               continuous-batching server: p50/p99 latency and GB/s, vs the plain
+               path one request at a time on a prefix of the same trace.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MiB = 1 << 20
+GB = 1e9
+# MI355X: 256 CUs x 4 SIMDs x 16 binary64 lanes x 2.4 GHz = one binary64 VALU op per lane per clock
+FP64_VALU_OPS_PEAK = 256 * 4 * 16 * 2.4e9  # 39.32e12 op/s (78.6 TFLOP/s counts an FMA as two)
+FP64_FMA_COUNTED_PEAK = 78.6e12
+HBM_PEAK = 8e12
+
+
+def fp64_ops_per_byte(n_it: int) -> int:
+    """Algorithmic binary64 operations per message byte: n_it Euler steps of 14 operations,
+    the Theta division and add, six alpha * 10^13 products of R_nu, three a' adds."""
+    return 14 * n_it + 2 + 6 + 3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(x, q):
+    return float(np.percentile(np.asarray(x, dtype=np.float64), q)) if len(x) else float("nan")
+
+
+# ---------------------------------------------------------------------------------------------
+def bench_plain(lz, torch, steps, warmup):
+    from paper_1201_3114_amd import workloads
+
+    P, pw = workloads.plain("plain_64m")
+    n = len(P)
+    ctx = lz.Context(0)
+    dP = torch.from_numpy(P).cuda()
+    C = torch.empty(n + 24, dtype=torch.uint8, device="cuda")
+    Q = torch.empty(n, dtype=torch.uint8, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ctx.encrypt(dP, pw, out=C)
+        ctx.decrypt(C, pw, out=Q, status=st)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        ctx.encrypt(dP, pw, out=C)
+        ev[k][1].record(stream)
+        ctx.decrypt(C, pw, out=Q, status=st)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    enc_ms = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
+    dec_ms = [ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]
+    ok = bool(torch.equal(Q, dP)) and int(st.item()) == 0
+    shape = ctx.get_launch()
+    n_it = ctx.params.n_it
+    ctx.close()
+    return dict(n=n, wall_s=wall, enc_ms=enc_ms, dec_ms=dec_ms, roundtrip_ok=ok, shape=shape, n_it=n_it)
+
+
+def bench_cpu_baseline(target_s: float = 12.0):
+    """The oracle as it stands on a prefix of the 64 MiB message, encrypt then decrypt."""
+    import oracle
+    from paper_1201_3114_amd import workloads
+
+    P, pw = workloads.plain("plain_64m")
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    threads = max(1, min(16, cores))
+    cal = P[: 4 * 256]
+    t = time.perf_counter()
+    oracle.encrypt(pw, cal, nthreads=1)
+    per_byte = (time.perf_counter() - t) / len(cal)
+    blocks = max(threads, int(target_s / 2 / (per_byte * 256) * threads) // threads * threads)
+    S = min(len(P), blocks * 256)
+    sample = P[:S]
+    t = time.perf_counter()
+    C = oracle.encrypt(pw, sample, nthreads=threads)
+    te = time.perf_counter() - t
+    t = time.perf_counter()
+    Q, ok = oracle.decrypt(pw, C, nthreads=threads)
+    td = time.perf_counter() - t
+    assert ok and np.array_equal(Q, sample)
+    return dict(value=2 * S / (te + td) / GB, unit="GB/s", cores=threads, kind="oracle",
+                sample=f"first {S} bytes ({S // 256} blocks) of the 64 MiB message, encrypt then decrypt, "
+                       f"{threads} pthreads; enc {te:.2f} s, dec {td:.2f} s")
+
+
+# ---------------------------------------------------------------------------------------------
+def bench_batch(lz, torch, steps, plain_sample=256):
+    from paper_1201_3114_amd import workloads
+
+    wl = workloads.batch()
+    sizes = wl.sizes
+    total = int(sizes.sum())
+    ctx = lz.Context(0)
+    tuned = None
+    try:
+        t = time.perf_counter()
+        tuned = ctx.autotune(budget_ms=4000)
+        log(f"autotune: {tuned} in {time.perf_counter() - t:.1f} s")
+    except lz.LorenzError as e:
+        log("autotune failed:", e)
+    in_off = wl.offsets.astype(np.uint64)
+    out_off, out_tot = lz.packed_offsets(sizes, 24)
+    d_in = torch.from_numpy(wl.data).cuda()
+    d_out = torch.empty(out_tot, dtype=torch.uint8, device="cuda")
+    d_back = torch.empty(total, dtype=torch.uint8, device="cuda")
+    st = torch.empty(len(sizes), dtype=torch.int32, device="cuda")
+    t = time.perf_counter()
+    be = lz.Batch(ctx, False, sizes, wl.passwords, d_in, in_off, d_out, out_off)
+    setup_s = time.perf_counter() - t
+    be.launch()
+    torch.cuda.synchronize()
+    bd = lz.Batch(ctx, True, sizes, wl.passwords, d_out, out_off, d_back, in_off, d_status=st)
+    stream = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    enc, dec = [], []
+    for _ in range(steps):
+        e[0].record(stream)
+        be.launch()
+        e[1].record(stream)
+        bd.launch()
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        enc.append(e[0].elapsed_time(e[1]))
+        dec.append(e[1].elapsed_time(e[2]))
+    ok = bool(torch.equal(d_back, d_in)) and bool((st == 0).all())
+    # plain path, one call per message, on a prefix of the batch
+    k = min(plain_sample, len(sizes))
+    pb = int(sizes[:k].sum())
+    outs = [torch.empty(int(s) + 24, dtype=torch.uint8, device="cuda") for s in sizes[:k]]
+    views = [d_in[int(in_off[i]):int(in_off[i]) + int(sizes[i])] for i in range(k)]
+    torch.cuda.synchronize()
+    e[0].record(stream)
+    for i in range(k):
+        ctx.encrypt(views[i], wl.passwords[i], out=outs[i])
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e[0].elapsed_time(e[1])
+    same = all(torch.equal(outs[i], d_out[int(out_off[i]):int(out_off[i]) + int(sizes[i]) + 24]) for i in range(k))
+    # integrity: 10% of the ciphertexts get one altered byte
+    idx, offs, vals = workloads.tamper_plan(sizes + 24)
+    pos = torch.from_numpy((out_off[idx] + offs.astype(np.uint64)).astype(np.int64)).cuda()
+    d_out[pos] ^= torch.from_numpy(vals).cuda()
+    torch.cuda.synchronize()
+    e[0].record(stream)
+    bd.launch()
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    integ_ms = e[0].elapsed_time(e[1])
+    status = st.cpu().numpy()
+    bad = np.zeros(len(sizes), bool)
+    bad[idx] = True
+    flagged_ok = bool((status[bad] == -2).all() and (status[~bad] == 0).all())
+    back = d_back.cpu().numpy()
+    good_exact = True
+    for i in np.nonzero(~bad)[0]:
+        s0, s1 = int(in_off[i]), int(in_off[i]) + int(sizes[i])
+        if not np.array_equal(back[s0:s1], wl.data[s0:s1]):
+            good_exact = False
+            break
+    zeroed = all(not back[int(in_off[i]):int(in_off[i]) + int(sizes[i])].any() for i in idx)
+    shape = ctx.get_launch()
+    be.close()
+    bd.close()
+    ctx.close()
+    enc_ms, dec_ms = float(np.median(enc)), float(np.median(dec))
+    return dict(
+        messages=len(sizes), bytes=total, launch=dict(chains_per_lane=shape.chains_per_lane, wg_size=shape.wg_size,
+                                                      tile=shape.tile, waves_per_simd=shape.waves_per_simd),
+        autotuned=tuned is not None, encrypt_GBps=total / enc_ms / 1e6, decrypt_GBps=total / dec_ms / 1e6,
+        enc_dec_GBps=2 * total / (enc_ms + dec_ms) / 1e6, enc_ms=enc_ms, dec_ms=dec_ms, setup_s=setup_s,
+        roundtrip_exact=ok,
+        plain_per_message=dict(messages=k, bytes=pb, encrypt_GBps=pb / plain_ms / 1e6, ms=plain_ms,
+                               same_bytes_as_batched=same),
+        speedup_vs_plain_per_message=(total / enc_ms) / (pb / plain_ms),
+        integrity=dict(altered=int(len(idx)), flagged_exactly=flagged_ok, untouched_exact=good_exact,
+                       altered_zeroed=zeroed, decrypt_ms=integ_ms))
+
+
+# ---------------------------------------------------------------------------------------------
+def bench_serve(lz, torch, qps, count, plain_prefix, budget):
+    from paper_1201_3114_amd import workloads
+
+    tr = workloads.serve_trace(count=count, qps=qps)
+    sizes = tr.sizes
+    dec = tr.decrypt.astype(bool)
+    tot = int(sizes.sum())
+    ctx = lz.Context(0)
+    # plaintexts on the device (torch's generator, seeded), packed
+    g = torch.Generator(device="cuda")
+    g.manual_seed(workloads.SEED["serve"])
+    p_off, p_tot = lz.packed_offsets(sizes, 0, 256)
+    dP = torch.randint(0, 256, (p_tot,), dtype=torch.uint8, device="cuda", generator=g)
+    # ciphertexts of the decrypt requests and expected ciphertexts of the encrypt requests,
+    # made by the batched path (bit-identical to the plain path)
+    c_off, c_tot = lz.packed_offsets(sizes, 24, 256)
+    dC = torch.zeros(c_tot, dtype=torch.uint8, device="cuda")
+    t = time.perf_counter()
+    b = lz.Batch(ctx, False, sizes, tr.passwords, dP, p_off, dC, c_off)
+    b.launch()
+    torch.cuda.synchronize()
+    b.close()
+    prep_s = time.perf_counter() - t
+    dOut = torch.zeros(c_tot, dtype=torch.uint8, device="cuda")  # outputs at the same offsets as dC / dP
+
+    def src_dst(i):
+        if dec[i]:
+            return dC.data_ptr() + int(c_off[i]), dOut.data_ptr() + int(c_off[i])
+        return dP.data_ptr() + int(p_off[i]), dOut.data_ptr() + int(c_off[i])
+
+    def run_server(ids):
+        srv = lz.Server(ctx, hbm_budget=budget)
+        base = lz.now_ns() + int(3e9) + 12_000 * len(ids)
+        t0 = tr.arrival_s[ids[0]]
+        for i in ids:
+            s, d = src_dst(i)
+            srv.submit(int(i), bool(dec[i]), tr.passwords[i], s, int(sizes[i]), d,
+                       base + int((tr.arrival_s[i] - t0) * 1e9))
+        lat, done, status = [], 0, []
+        first_arr, last_done = None, 0
+        while done < len(ids):
+            for (rid, stc, arr, adm, dn) in srv.poll(8192, 200):
+                lat.append((dn - arr) / 1e6)
+                status.append(stc)
+                first_arr = arr if first_arr is None else min(first_arr, arr)
+                last_done = max(last_done, dn)
+                done += 1
+        stats = srv.stats()
+        srv.close()
+        span = (last_done - first_arr) / 1e9
+        nbytes = int(sizes[ids].sum())
+        return dict(requests=len(ids), bytes=nbytes, GBps=nbytes / span / GB, makespan_s=span,
+                    p50_ms=percentile(lat, 50), p99_ms=percentile(lat, 99), max_ms=float(np.max(lat)),
+                    all_ok=all(s == 0 for s in status), ticks=stats["ticks"], device_busy_ms=stats["busy_ms"],
+                    peak_hbm_GB=stats["peak_hbm"] / GB)
+
+    ids = np.arange(count)
+    log(f"serve: {count} requests, {tot / GB:.2f} GB, qps {qps:.0f}")
+    served = run_server(ids)
+    # every response equals the expected bytes (plaintexts for decrypt, batched ciphertexts for encrypt)
+    torch.cuda.synchronize()
+    exact = True
+    for i in range(count):
+        o = int(c_off[i])
+        if dec[i]:
+            if not torch.equal(dOut[o:o + int(sizes[i])], dP[int(p_off[i]):int(p_off[i]) + int(sizes[i])]):
+                exact = False
+                break
+        elif not torch.equal(dOut[o:o + int(sizes[i]) + 24], dC[o:o + int(sizes[i]) + 24]):
+            exact = False
+            break
+    served["bit_exact_vs_plain"] = exact
+    # plain path, one request at a time in arrival order, on a prefix of the trace
+    k = min(plain_prefix, count)
+    pre = np.arange(k)
+    lat = []
+    stream = torch.cuda.current_stream()
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    outs_ok = True
+    t_start = lz.now_ns()
+    a0 = tr.arrival_s[0]
+    for i in pre:
+        arr = t_start + int((tr.arrival_s[i] - a0) * 1e9)
+        while lz.now_ns() < arr:
+            pass
+        n = int(sizes[i])
+        o = int(c_off[i])
+        if dec[i]:
+            out = torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+            ctx.decrypt(dC[o:o + n + 24], tr.passwords[i], out=out[:n] if n else None, status=st, stream=stream)
+        else:
+            out = torch.empty(n + 24, dtype=torch.uint8, device="cuda")
+            ctx.encrypt(dP[int(p_off[i]):int(p_off[i]) + n], tr.passwords[i], out=out, stream=stream)
+        stream.synchronize()
+        lat.append((lz.now_ns() - arr) / 1e6)
+        if dec[i]:
+            outs_ok &= bool(torch.equal(out[:n], dP[int(p_off[i]):int(p_off[i]) + n]))
+        else:
+            outs_ok &= bool(torch.equal(out, dC[o:o + n + 24]))
+    span = (lz.now_ns() - t_start) / 1e9
+    pbytes = int(sizes[pre].sum())
+    plain = dict(requests=k, bytes=pbytes, GBps=pbytes / span / GB, p50_ms=percentile(lat, 50),
+                 p99_ms=percentile(lat, 99), bit_exact=outs_ok)
+    served_prefix = run_server(pre)
+    ctx.close()
+    return dict(qps=qps, requests=count, bytes=tot, prep_s=prep_s, hbm_budget_GB=budget / GB, continuous=served,
+                plain_per_request_prefix=plain, continuous_same_prefix=served_prefix)
+
+
+# ---------------------------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--only", choices=["all", "plain", "batch", "serve"], default="all")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200_000)
+    ap.add_argument("--serve-qps", type=float, default=0.0, help="0 = 0.7 x plain-path capacity")
+    ap.add_argument("--serve-plain-prefix", type=int, default=200)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--batch-steps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU; every block is independent, so more GPUs "
+                                   "would shard blocks with no collective beyond a 24-byte tag XOR "
+                                   "(see the design notes); --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_1201_3114_amd as lz
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+
+    out = {"metric": "encrypt+decrypt GB/s at 64 MiB; batched/served GB/s + p50/p99 vs plain", "unit": "GB/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded uniform random bytes, printable passwords)"}
+    plain = None
+    if args.only in ("all", "plain", "serve"):
+        log("plain 64 MiB ...")
+        plain = bench_plain(lz, torch, args.steps, args.warmup)
+        t_enc, t_dec = sum(plain["enc_ms"]), sum(plain["dec_ms"])
+        n = plain["n"]
+        ms_step = (t_enc + t_dec) / args.steps
+        value = 2 * n * args.steps / ((t_enc + t_dec) / 1e3) / GB
+        launches = 2 * args.steps
+        avg_launch_s = (t_enc + t_dec) / launches / 1e3
+        ops = n * fp64_ops_per_byte(plain["n_it"])
+        achieved = ops / avg_launch_s
+        sh = plain["shape"]
+        out.update(value=value, ms_per_step=ms_step,
+                   config={"workload": "plain 64 MiB: one 67108864-byte message, 32-byte password, block 256, "
+                                       "n_it 3000, dt 0.01, encrypt then decrypt",
+                           "message_bytes": n, "password_bytes": 32, "block_len": 256, "n_it": plain["n_it"],
+                           "launch": {"chains_per_lane": sh.chains_per_lane, "wg_size": sh.wg_size,
+                                      "tile": sh.tile}},
+                   encrypt_GBps=n / (t_enc / args.steps / 1e3) / GB, decrypt_GBps=n / (t_dec / args.steps / 1e3) / GB,
+                   wall_s=plain["wall_s"], roundtrip_exact=plain["roundtrip_ok"],
+                   roofline={"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_OPS_PEAK / 1e12,
+                             "unit": "TFLOP/s", "frac": achieved / FP64_VALU_OPS_PEAK, "traffic": None,
+                             "kernel": "plain_kernel (binary64 VALU, one op per lane per clock)",
+                             "ops_per_launch": ops, "avg_launch_ms": avg_launch_s * 1e3,
+                             "frac_of_fma_counted_78.6": achieved / FP64_FMA_COUNTED_PEAK,
+                             "hbm_GBps": 2 * n / avg_launch_s / GB})
+    if args.only in ("all", "plain") and not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = bench_cpu_baseline()
+    if args.only in ("all", "batch"):
+        log("batched ...")
+        out["batched"] = bench_batch(lz, torch, args.batch_steps)
+    if args.only in ("all", "serve"):
+        from paper_1201_3114_amd import workloads
+
+        qps = args.serve_qps
+        if qps <= 0:
+            tr = workloads.serve_trace(count=args.serve_requests, qps=1.0)
+            mean_bytes = float(tr.sizes.mean())
+            per_dir = out.get("value", 0.9)
+            qps = 0.7 * per_dir * GB / mean_bytes
+        log("served ...")
+        out["served"] = bench_serve(lz, torch, qps, args.serve_requests, args.serve_plain_prefix,
+                                    int(args.serve_budget_gb * GB))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -378,11 +378,15 @@ __global__ void batch_kernel(BatchArgs a) {
     const uint64_t per_task = (uint64_t)WAVE * M;
     const uint64_t n_chains = a.b.n_full + a.b.n_tail;
 
+    // No lane-conditional region may sit inside this loop: the compiler is free to merge such
+    // regions across the back edge, which leaves lanes re-entering the loop without the others.
+    // Every lane therefore takes part in the task grab (lane 0 adds 1, the others 0) and in the
+    // tag update (a lane past the end XORs 0).
     for (;;) {
-        unsigned long long task = 0;
-        if (lane == 0) task = atomicAdd(a.b.counter, 1ull);
-        task = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(task >> 32)) << 32) |
-               __builtin_amdgcn_readfirstlane((uint32_t)task);
+        const unsigned long long grab = atomicAdd(a.b.counter, lane == 0 ? 1ull : 0ull);
+        const unsigned long long task =
+            ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(grab >> 32)) << 32) |
+            __builtin_amdgcn_readfirstlane((uint32_t)grab);
         if (task >= a.b.n_tasks) break;
 
         Chains<M> c;
@@ -425,25 +429,13 @@ __global__ void batch_kernel(BatchArgs a) {
             d1[m] = digest_word(c.y[m]);
             d2[m] = digest_word(c.z[m]);
         });
-        // tag: XOR of block digests per message
+        // tag: XOR of block digests per message, one atomic per lane and word
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            const uint32_t first = __builtin_amdgcn_readfirstlane(msg[m]);
-            const bool uniform = __all(!valid[m] || msg[m] == first);
-            if (uniform) {
-                const unsigned long long t0 = wave_xor_u64(valid[m] ? d0[m] : 0ull);
-                const unsigned long long t1 = wave_xor_u64(valid[m] ? d1[m] : 0ull);
-                const unsigned long long t2 = wave_xor_u64(valid[m] ? d2[m] : 0ull);
-                if (lane == 0 && __any(valid[m])) {
-                    atomicXor(&a.b.tag_acc[3 * (size_t)first + 0], t0);
-                    atomicXor(&a.b.tag_acc[3 * (size_t)first + 1], t1);
-                    atomicXor(&a.b.tag_acc[3 * (size_t)first + 2], t2);
-                }
-            } else if (valid[m]) {
-                atomicXor(&a.b.tag_acc[3 * (size_t)msg[m] + 0], d0[m]);
-                atomicXor(&a.b.tag_acc[3 * (size_t)msg[m] + 1], d1[m]);
-                atomicXor(&a.b.tag_acc[3 * (size_t)msg[m] + 2], d2[m]);
-            }
+            unsigned long long *t = &a.b.tag_acc[3 * (size_t)msg[m]];
+            atomicXor(t + 0, valid[m] ? d0[m] : 0ull);
+            atomicXor(t + 1, valid[m] ? d1[m] : 0ull);
+            atomicXor(t + 2, valid[m] ? d2[m] : 0ull);
         }
     }
 }

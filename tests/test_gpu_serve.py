@@ -1,0 +1,138 @@
+"""Served path (continuous batching): every result equals the plain path, alone and in a mix."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import host, need_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lz():
+    need_gpu()
+    import paper_1201_3114_amd as lz
+
+    return lz
+
+
+def _drain(srv, count, timeout_s=120):
+    got = {}
+    t_end = time.time() + timeout_s
+    while len(got) < count:
+        assert time.time() < t_end, "server did not complete in time"
+        for c in srv.poll(4096, 100):
+            got[c[0]] = c
+    return got
+
+
+def _requests(lz, ctx, rng, count, max_size, n_it):
+    """Mixed encrypt/decrypt requests with device buffers; decrypt inputs made by the plain path."""
+    import torch
+
+    reqs = []
+    for i in range(count):
+        n = int(rng.integers(0, max_size))
+        pw = bytes(rng.integers(32, 127, int(rng.integers(16, 65)), dtype=np.uint8))
+        P = to_dev(rng.integers(0, 256, n, dtype=np.uint8)) if n else torch.zeros(1, dtype=torch.uint8, device="cuda")
+        dec = bool(rng.integers(0, 2))
+        if dec:
+            C = ctx.encrypt(P[:n] if n else P[:0], pw)
+            src, dst = C, torch.zeros(max(n, 1), dtype=torch.uint8, device="cuda")
+        else:
+            src, dst = P, torch.zeros(n + 24, dtype=torch.uint8, device="cuda")
+        reqs.append(dict(id=i, n=n, pw=pw, P=P, dec=dec, src=src, dst=dst))
+    torch.cuda.synchronize()
+    return reqs
+
+
+def _expected(ctx, r):
+    if r["dec"]:
+        return host(r["P"][:r["n"]])
+    return host(ctx.encrypt(r["P"][:r["n"]] if r["n"] else r["P"][:0], r["pw"]))
+
+
+def test_serve_mix_equals_plain(lz):
+    rng = np.random.default_rng(41)
+    ctx = lz.Context(0, lz.params(n_it=40))
+    reqs = _requests(lz, ctx, rng, 120, 20000, 40)
+    srv = lz.Server(ctx, hbm_budget=1 << 30, tick_bytes=16)
+    t0 = lz.now_ns()
+    for r in reqs:  # staggered arrivals: later requests join while earlier ones run
+        srv.submit(r["id"], r["dec"], r["pw"], r["src"].data_ptr(), r["n"], r["dst"].data_ptr(),
+                   t0 + 200_000 * r["id"])
+    got = _drain(srv, len(reqs))
+    st = srv.stats()
+    srv.close()
+    say("serve stats", st)
+    assert st["completed"] == len(reqs) and st["ticks"] > 1
+    for r in reqs:
+        assert got[r["id"]][1] == 0, r["id"]
+        n_out = r["n"] if r["dec"] else r["n"] + 24
+        assert np.array_equal(host(r["dst"])[:n_out], _expected(ctx, r)), r["id"]
+
+
+def test_serve_alone_equals_in_mix(lz):
+    """The same request gives the same bytes alone on an idle server and inside a mix."""
+    import torch
+
+    rng = np.random.default_rng(42)
+    ctx = lz.Context(0, lz.params(n_it=60))
+    P = to_dev(rng.integers(0, 256, 5 * 256 + 100, dtype=np.uint8))
+    pw = b"alone-or-mixed"
+    outs = []
+    for mixed in (False, True):
+        srv = lz.Server(ctx, hbm_budget=1 << 28, tick_bytes=8)
+        dst = torch.zeros(P.numel() + 24, dtype=torch.uint8, device="cuda")
+        others = _requests(lz, ctx, rng, 40, 6000, 60) if mixed else []
+        for r in others[:20]:
+            srv.submit(1000 + r["id"], r["dec"], r["pw"], r["src"].data_ptr(), r["n"], r["dst"].data_ptr())
+        srv.submit(7, False, pw, P.data_ptr(), P.numel(), dst.data_ptr())
+        for r in others[20:]:
+            srv.submit(1000 + r["id"], r["dec"], r["pw"], r["src"].data_ptr(), r["n"], r["dst"].data_ptr())
+        _drain(srv, 1 + len(others))
+        srv.close()
+        outs.append(host(dst).copy())
+        for r in others:
+            n_out = r["n"] if r["dec"] else r["n"] + 24
+            assert np.array_equal(host(r["dst"])[:n_out], _expected(ctx, r))
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], host(ctx.encrypt(P, pw)))
+    assert np.array_equal(outs[0], oracle.encrypt(pw, host(P), n_it=60))
+
+
+def test_serve_integrity_budget_and_host_buffers(lz):
+    """Tampered ciphertext -> LZ_E_INTEGRITY and zeroed output; a request larger than the budget
+    completes with LZ_E_NOMEM; host (pageable) buffers work as sources and destinations; a budget
+    that holds only a few requests at a time still completes everything in order."""
+    rng = np.random.default_rng(43)
+    ctx = lz.Context(0, lz.params(n_it=30))
+    pw = b"served integrity"
+    P = rng.integers(0, 256, 3000, dtype=np.uint8)
+    C = host(ctx.encrypt(to_dev(P), pw))
+    C_bad = C.copy()
+    C_bad[1234] ^= 1
+    out_ok = np.full(3000, 0xEE, np.uint8)
+    out_bad = np.full(3000, 0xEE, np.uint8)
+    big = np.zeros(4 << 20, np.uint8)
+    big_out = np.zeros((4 << 20) + 24, np.uint8)
+    srv = lz.Server(ctx, hbm_budget=3 << 20, max_chains=4096, tick_bytes=32)
+    srv.submit(1, True, pw, C.ctypes.data, 3000, out_ok.ctypes.data)
+    srv.submit(2, True, pw, C_bad.ctypes.data, 3000, out_bad.ctypes.data)
+    srv.submit(3, False, pw, big.ctypes.data, len(big), big_out.ctypes.data)
+    many = [rng.integers(0, 256, 100_000, dtype=np.uint8) for _ in range(12)]
+    many_out = [np.zeros(100_024, np.uint8) for _ in many]
+    for i, (m, o) in enumerate(zip(many, many_out)):
+        srv.submit(10 + i, False, pw, m.ctypes.data, len(m), o.ctypes.data)
+    got = _drain(srv, 3 + len(many))
+    st = srv.stats()
+    srv.close()
+    assert got[1][1] == 0 and np.array_equal(out_ok, P)
+    assert got[2][1] == -2 and not out_bad.any()
+    assert got[3][1] == -3
+    assert st["peak_hbm"] <= 3 << 20
+    for i, (m, o) in enumerate(zip(many, many_out)):
+        assert got[10 + i][1] == 0
+        assert np.array_equal(o, oracle.encrypt(pw, m, nthreads=8, n_it=30)), i
