@@ -194,7 +194,9 @@ struct WaveLds {
     uint32_t *cnt;
 };
 
-__host__ __device__ constexpr size_t tile_stride(int tile) { return (size_t)tile + 16; }
+// Row stride of the LDS tile: an odd number of 4-byte words past a multiple of 64 banks
+// (tile is a multiple of 16), so the 64 lanes reading their own rows hit distinct banks.
+__host__ __device__ constexpr size_t tile_stride(int tile) { return (size_t)tile + 4; }
 __host__ __device__ constexpr size_t wave_lds_bytes(int m, int tile) {
     return (size_t)WAVE * m * (tile_stride(tile) + 2 * sizeof(void *) + sizeof(uint32_t));
 }

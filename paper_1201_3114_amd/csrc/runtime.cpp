@@ -143,7 +143,8 @@ extern "C" int lz_context_create(int device, const lz_params *prm, lz_ctx **out)
     c->prm = p;
     c->dev.cus = prop.multiProcessorCount;
     c->dev.lds_per_wg_max = (int)prop.sharedMemPerBlock;
-    c->shape = KernelShape{1, 256, 64, 4};
+    // one chain per lane, 4 waves per workgroup, 128-byte tiles (one L2 line per chain per refill)
+    c->shape = KernelShape{1, 256, 128, 4};
     if (!shape_valid(c->shape, c->dev)) c->shape = KernelShape{1, 64, 32, 4};
     hipError_t e = hipMalloc(&c->ws_tag, 4 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc(&c->ws_status, sizeof(int32_t));
