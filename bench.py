@@ -242,7 +242,7 @@ def bench_batch(lz, torch, steps, plain_sample=256):
 
 
 # ---------------------------------------------------------------------------------------------
-def bench_serve(lz, torch, qps, count, plain_prefix, budget):
+def bench_serve(lz, torch, qps, count, plain_prefix, budget, tick_bytes=16):
     from paper_1201_3114_amd import workloads
 
     tr = workloads.serve_trace(count=count, qps=qps)
@@ -250,13 +250,13 @@ def bench_serve(lz, torch, qps, count, plain_prefix, budget):
     dec = tr.decrypt.astype(bool)
     tot = int(sizes.sum())
     ctx = lz.Context(0)
-    # plaintexts on the device (torch's generator, seeded), packed
+    # request plaintexts on the device (torch's generator, seeded), packed 256-byte aligned
     g = torch.Generator(device="cuda")
     g.manual_seed(workloads.SEED["serve"])
     p_off, p_tot = lz.packed_offsets(sizes, 0, 256)
     dP = torch.randint(0, 256, (p_tot,), dtype=torch.uint8, device="cuda", generator=g)
-    # ciphertexts of the decrypt requests and expected ciphertexts of the encrypt requests,
-    # made by the batched path (bit-identical to the plain path)
+    # ciphertexts of every request made by the batched path (bit-identical to the plain path):
+    # the inputs of the decrypt requests and the expected outputs of the encrypt requests
     c_off, c_tot = lz.packed_offsets(sizes, 24, 256)
     dC = torch.zeros(c_tot, dtype=torch.uint8, device="cuda")
     t = time.perf_counter()
@@ -265,55 +265,51 @@ def bench_serve(lz, torch, qps, count, plain_prefix, budget):
     torch.cuda.synchronize()
     b.close()
     prep_s = time.perf_counter() - t
-    dOut = torch.zeros(c_tot, dtype=torch.uint8, device="cuda")  # outputs at the same offsets as dC / dP
-
-    def src_dst(i):
-        if dec[i]:
-            return dC.data_ptr() + int(c_off[i]), dOut.data_ptr() + int(c_off[i])
-        return dP.data_ptr() + int(p_off[i]), dOut.data_ptr() + int(c_off[i])
+    dOut = torch.zeros(c_tot, dtype=torch.uint8, device="cuda")  # every output at its request's c_off
+    src_all = np.where(dec, dC.data_ptr() + c_off, dP.data_ptr() + p_off).astype(np.uint64)
+    dst_all = (dOut.data_ptr() + c_off).astype(np.uint64)
 
     def run_server(ids):
-        srv = lz.Server(ctx, hbm_budget=budget)
-        base = lz.now_ns() + int(3e9) + 12_000 * len(ids)
-        t0 = tr.arrival_s[ids[0]]
-        for i in ids:
-            s, d = src_dst(i)
-            srv.submit(int(i), bool(dec[i]), tr.passwords[i], s, int(sizes[i]), d,
-                       base + int((tr.arrival_s[i] - t0) * 1e9))
-        lat, done, status = [], 0, []
+        srv = lz.Server(ctx, hbm_budget=budget, tick_bytes=tick_bytes)
+        lead_ns = int(1.0e9) + 10_000 * len(ids)
+        base = lz.now_ns() + lead_ns
+        arr = (base + np.round((tr.arrival_s[ids] - tr.arrival_s[ids[0]]) * 1e9)).astype(np.uint64)
+        t_sub = time.perf_counter()
+        srv.submit_many(ids, dec[ids], [tr.passwords[i] for i in ids], src_all[ids], sizes[ids], dst_all[ids], arr)
+        submit_s = time.perf_counter() - t_sub
+        submitted_in_time = lz.now_ns() < base
+        lat, status = [], []
         first_arr, last_done = None, 0
-        while done < len(ids):
-            for (rid, stc, arr, adm, dn) in srv.poll(8192, 200):
-                lat.append((dn - arr) / 1e6)
+        while len(lat) < len(ids):
+            for (rid, stc, a, adm, dn) in srv.poll(8192, 200):
+                lat.append((dn - a) / 1e6)
                 status.append(stc)
-                first_arr = arr if first_arr is None else min(first_arr, arr)
+                first_arr = a if first_arr is None else min(first_arr, a)
                 last_done = max(last_done, dn)
-                done += 1
         stats = srv.stats()
         srv.close()
         span = (last_done - first_arr) / 1e9
         nbytes = int(sizes[ids].sum())
-        return dict(requests=len(ids), bytes=nbytes, GBps=nbytes / span / GB, makespan_s=span,
-                    p50_ms=percentile(lat, 50), p99_ms=percentile(lat, 99), max_ms=float(np.max(lat)),
+        trace_s = float(tr.arrival_s[ids[-1]] - tr.arrival_s[ids[0]])
+        return dict(requests=len(ids), bytes=nbytes, GBps=nbytes / span / GB, offered_GBps=nbytes / max(trace_s, 1e-9) / GB,
+                    makespan_s=span, p50_ms=percentile(lat, 50), p99_ms=percentile(lat, 99), max_ms=float(np.max(lat)),
                     all_ok=all(s == 0 for s in status), ticks=stats["ticks"], device_busy_ms=stats["busy_ms"],
-                    peak_hbm_GB=stats["peak_hbm"] / GB)
+                    device_busy_frac=stats["busy_ms"] / 1e3 / span, peak_hbm_GB=stats["peak_hbm"] / GB,
+                    tick_bytes=tick_bytes, submit_s=submit_s, submitted_before_first_arrival=submitted_in_time)
 
     ids = np.arange(count)
     log(f"serve: {count} requests, {tot / GB:.2f} GB, qps {qps:.0f}")
     served = run_server(ids)
-    # every response equals the expected bytes (plaintexts for decrypt, batched ciphertexts for encrypt)
+    # bit-exactness of every response: expected = batched ciphertexts for encrypt requests and
+    # the original plaintexts (then 24 untouched zero bytes) for decrypt requests
     torch.cuda.synchronize()
-    exact = True
-    for i in range(count):
-        o = int(c_off[i])
-        if dec[i]:
-            if not torch.equal(dOut[o:o + int(sizes[i])], dP[int(p_off[i]):int(p_off[i]) + int(sizes[i])]):
-                exact = False
-                break
-        elif not torch.equal(dOut[o:o + int(sizes[i]) + 24], dC[o:o + int(sizes[i]) + 24]):
-            exact = False
-            break
-    served["bit_exact_vs_plain"] = exact
+    E = dC.clone()
+    for i in np.nonzero(dec)[0]:
+        o, po, n = int(c_off[i]), int(p_off[i]), int(sizes[i])
+        E[o:o + n] = dP[po:po + n]
+        E[o + n:o + n + 24] = 0
+    served["bit_exact_vs_plain"] = bool(torch.equal(E, dOut))
+    del E
     # plain path, one request at a time in arrival order, on a prefix of the trace
     k = min(plain_prefix, count)
     pre = np.arange(k)
@@ -347,8 +343,10 @@ def bench_serve(lz, torch, qps, count, plain_prefix, budget):
                  p99_ms=percentile(lat, 99), bit_exact=outs_ok)
     served_prefix = run_server(pre)
     ctx.close()
-    return dict(qps=qps, requests=count, bytes=tot, prep_s=prep_s, hbm_budget_GB=budget / GB, continuous=served,
-                plain_per_request_prefix=plain, continuous_same_prefix=served_prefix)
+    return dict(qps=qps, requests=count, bytes=tot, mean_request_bytes=tot / count, prep_s=prep_s,
+                hbm_budget_GB=budget / GB, continuous=served, plain_per_request_prefix=plain,
+                continuous_same_prefix=served_prefix,
+                p99_speedup_vs_plain_on_prefix=plain["p99_ms"] / served_prefix["p99_ms"])
 
 
 # ---------------------------------------------------------------------------------------------
@@ -363,6 +361,7 @@ def main():
     ap.add_argument("--serve-qps", type=float, default=0.0, help="0 = 0.7 x plain-path capacity")
     ap.add_argument("--serve-plain-prefix", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-tick-bytes", type=int, default=16)
     ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -440,7 +439,7 @@ def main():
             qps = 0.7 * per_dir * GB / mean_bytes
         log("served ...")
         out["served"] = bench_serve(lz, torch, qps, args.serve_requests, args.serve_plain_prefix,
-                                    int(args.serve_budget_gb * GB))
+                                    int(args.serve_budget_gb * GB), args.serve_tick_bytes)
     print(json.dumps(out))
 
 

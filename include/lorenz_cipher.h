@@ -218,6 +218,16 @@ int lz_server_create(lz_ctx *ctx, const lz_server_config *cfg, lz_server **out);
 int lz_server_submit(lz_server *srv, uint64_t id, int decrypt, const uint8_t *pw, size_t n_pw,
                      const void *src, uint64_t n, void *dst, uint64_t arrival_ns);
 
+/* Queues count requests at once (same meaning as lz_server_submit, element by
+ * element): ids[i], decrypt[i] (0/1), password bytes pw[pw_off[i] ..
+ * pw_off[i] + pw_len[i]), src[i], n[i], dst[i], arrival_ns[i] (all host
+ * arrays).  Key setup runs on the calling thread before any request becomes
+ * visible to the server.  On error nothing is queued. */
+int lz_server_submit_many(lz_server *srv, size_t count, const uint64_t *ids, const uint8_t *decrypt,
+                          const uint8_t *pw, const uint64_t *pw_off, const uint32_t *pw_len,
+                          const void *const *src, const uint64_t *n, void *const *dst,
+                          const uint64_t *arrival_ns);
+
 /* Copies up to max completed requests into out, returns how many (>= 0), or
  * a negative error.  timeout_ms < 0 waits until at least one is available. */
 int lz_server_poll(lz_server *srv, lz_completion *out, int max, int timeout_ms);

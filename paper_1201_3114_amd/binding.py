@@ -75,6 +75,10 @@ SIGNATURES = {
     "lz_server_create": (ctypes.c_int, [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
     "lz_server_submit": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.c_int, u8p, ctypes.c_size_t, vp,
                                         ctypes.c_uint64, vp, ctypes.c_uint64]),
+    "lz_server_submit_many": (ctypes.c_int, [vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint64), u8p, u8p,
+                                             ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32),
+                                             ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(vp),
+                                             ctypes.POINTER(ctypes.c_uint64)]),
     "lz_server_poll": (ctypes.c_int, [vp, ctypes.POINTER(Completion), ctypes.c_int, ctypes.c_int]),
     "lz_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
     "lz_server_destroy": (ctypes.c_int, [vp]),

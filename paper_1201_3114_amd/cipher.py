@@ -216,6 +216,26 @@ class Server:
         check(B.lib.lz_server_submit(self._h, rid, int(decrypt), buf, npw, ctypes.c_void_p(src_ptr), n,
                                      ctypes.c_void_p(dst_ptr), arrival_ns))
 
+    def submit_many(self, ids, decrypt, pws, src_ptrs, ns, dst_ptrs, arrival_ns):
+        """Queues many requests in one call (arrays of equal length; pointers as integers)."""
+        count = len(ids)
+        u64 = lambda a: np.ascontiguousarray(a, dtype=np.uint64)
+        ids_a, n_a, arr_a = u64(ids), u64(ns), u64(arrival_ns)
+        src_a, dst_a = u64(src_ptrs), u64(dst_ptrs)
+        dec_a = np.ascontiguousarray(decrypt, dtype=np.uint8)
+        pw_len = np.array([len(p) for p in pws], dtype=np.uint32)
+        pw_off = np.zeros(count, dtype=np.uint64)
+        if count > 1:
+            pw_off[1:] = np.cumsum(pw_len[:-1], dtype=np.uint64)
+        pw_all = np.frombuffer(b"".join(bytes(p) for p in pws) or b"\0", dtype=np.uint8).copy()
+        P64 = ctypes.POINTER(ctypes.c_uint64)
+        PV = ctypes.POINTER(ctypes.c_void_p)
+        check(B.lib.lz_server_submit_many(self._h, count, ids_a.ctypes.data_as(P64), dec_a.ctypes.data_as(B.u8p),
+                                          pw_all.ctypes.data_as(B.u8p), pw_off.ctypes.data_as(P64),
+                                          pw_len.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                          src_a.ctypes.data_as(PV), n_a.ctypes.data_as(P64), dst_a.ctypes.data_as(PV),
+                                          arr_a.ctypes.data_as(P64)))
+
     def poll(self, max_n: int = 4096, timeout_ms: int = 0):
         arr = (B.Completion * max_n)()
         k = check(B.lib.lz_server_poll(self._h, arr, max_n, timeout_ms))

@@ -480,6 +480,61 @@ extern "C" int lz_server_submit(lz_server *s, uint64_t id, int decrypt, const ui
     return LZ_OK;
 }
 
+extern "C" int lz_server_submit_many(lz_server *s, size_t count, const uint64_t *ids, const uint8_t *decrypt,
+                                     const uint8_t *pw, const uint64_t *pw_off, const uint32_t *pw_len,
+                                     const void *const *src, const uint64_t *n, void *const *dst,
+                                     const uint64_t *arrival_ns) {
+    if (!s || (count && (!ids || !decrypt || !pw || !pw_off || !pw_len || !src || !n || !dst || !arrival_ns)))
+        return fail(LZ_E_INVAL, "NULL argument");
+    std::vector<Request *> batch;
+    batch.reserve(count);
+    auto drop = [&] {
+        for (Request *r : batch) delete r;
+    };
+    const uint64_t now = lz_now_ns();
+    for (size_t i = 0; i < count; ++i) {
+        const int dec = decrypt[i] ? 1 : 0;
+        if (n[i] > LZ_MAX_MESSAGE) {
+            drop();
+            return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+        }
+        const uint64_t nin = dec ? n[i] + LZ_TAG_BYTES : n[i], nout = dec ? n[i] : n[i] + LZ_TAG_BYTES;
+        if ((nin && !src[i]) || (nout && !dst[i])) {
+            drop();
+            return fail(LZ_E_INVAL, "NULL buffer");
+        }
+        Request *r = new (std::nothrow) Request();
+        if (!r) {
+            drop();
+            return fail(LZ_E_NOMEM, "host allocation failed");
+        }
+        batch.push_back(r);
+        if (int rc = lz_key_setup(pw + pw_off[i], pw_len[i], &s->ctx->prm, &r->key)) {
+            drop();
+            return rc;
+        }
+        r->id = ids[i];
+        r->decrypt = dec;
+        r->src = src[i];
+        r->dst = dst[i];
+        r->n = n[i];
+        r->arrival_ns = arrival_ns[i] ? arrival_ns[i] : now;
+    }
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->stop) {
+            drop();
+            return fail(s->error ? s->error : LZ_E_INVAL, "server stopped");
+        }
+        for (Request *r : batch) {
+            r->seq = s->seq++;
+            s->pending.push(r);
+        }
+    }
+    s->cv_submit.notify_all();
+    return LZ_OK;
+}
+
 extern "C" int lz_server_poll(lz_server *s, lz_completion *out, int max, int timeout_ms) {
     if (!s || (!out && max > 0) || max < 0) return fail(LZ_E_INVAL, "bad argument");
     std::unique_lock<std::mutex> g(s->mu);

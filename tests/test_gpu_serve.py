@@ -136,3 +136,24 @@ def test_serve_integrity_budget_and_host_buffers(lz):
     for i, (m, o) in enumerate(zip(many, many_out)):
         assert got[10 + i][1] == 0
         assert np.array_equal(o, oracle.encrypt(pw, m, nthreads=8, n_it=30)), i
+
+
+def test_serve_submit_many_replay(lz):
+    """Bulk submission with future arrival times replays a trace; every result equals the plain path."""
+    rng = np.random.default_rng(44)
+    ctx = lz.Context(0, lz.params(n_it=25))
+    reqs = _requests(lz, ctx, rng, 300, 9000, 25)
+    srv = lz.Server(ctx, hbm_budget=1 << 30, tick_bytes=32)
+    base = lz.now_ns() + 200_000_000
+    arr = [base + 50_000 * r["id"] for r in reqs]
+    srv.submit_many([r["id"] for r in reqs], [r["dec"] for r in reqs], [r["pw"] for r in reqs],
+                    [r["src"].data_ptr() for r in reqs], [r["n"] for r in reqs], [r["dst"].data_ptr() for r in reqs],
+                    arr)
+    got = _drain(srv, len(reqs))
+    srv.close()
+    for r in reqs:
+        rid, status, a, adm, dn = got[r["id"]]
+        assert status == 0
+        assert a == arr[r["id"]] and adm >= a and dn >= adm
+        n_out = r["n"] if r["dec"] else r["n"] + 24
+        assert np.array_equal(host(r["dst"])[:n_out], _expected(ctx, r)), r["id"]
