@@ -38,10 +38,14 @@ FP64_FMA_COUNTED_PEAK = 78.6e12
 HBM_PEAK = 8e12
 
 
-def fp64_ops_per_byte(n_it: int) -> int:
-    """Algorithmic binary64 operations per message byte: n_it Euler steps of 14 operations,
-    the Theta division and add, six alpha * 10^13 products of R_nu, three a' adds."""
-    return 14 * n_it + 2 + 6 + 3
+# binary64 operations per step of each integrator format (one VALU instruction each)
+STEP_OPS = {"euler": 14, "euler_fma": 9, "rk4": 68}
+
+
+def fp64_ops_per_byte(n_it: int, integrator: str = "euler") -> int:
+    """Algorithmic binary64 operations per message byte: n_it integrator steps (14 operations
+    for Euler), the Theta division and add, six alpha * 10^13 products of R_nu, three a' adds."""
+    return STEP_OPS[integrator] * n_it + 2 + 6 + 3
 
 
 def kernel_stamp() -> str:
@@ -146,6 +150,75 @@ def bench_cpu_baseline(target_s: float = 12.0):
     return dict(value=2 * S / (te + td) / GB, unit="GB/s", cores=threads, kind="oracle",
                 sample=f"first {S} bytes ({S // 256} blocks) of the 64 MiB message, encrypt then decrypt, "
                        f"{threads} pthreads; enc {te:.2f} s, dec {td:.2f} s")
+
+
+# ---------------------------------------------------------------------------------------------
+def bench_variants(lz, torch, steps=2):
+    """Integrator formats on the 64 MiB workload: the explicit-FMA Euler (9 roundings per step)
+    and classical RK4 (68), each a distinct ciphertext format."""
+    from paper_1201_3114_amd import workloads
+
+    P, pw = workloads.plain("plain_64m")
+    n = len(P)
+    dP = torch.from_numpy(P).cuda()
+    C = torch.empty(n + 24, dtype=torch.uint8, device="cuda")
+    Q = torch.empty(n, dtype=torch.uint8, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for integ in ("euler_fma", "rk4"):
+        ctx = lz.Context(0, lz.params(integrator=integ))
+        ctx.encrypt(dP, pw, out=C)
+        ctx.decrypt(C, pw, out=Q, status=st)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        for _ in range(steps):
+            ctx.encrypt(dP, pw, out=C)
+            ctx.decrypt(C, pw, out=Q, status=st)
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        ms = e[0].elapsed_time(e[1])
+        launch_s = ms / 1e3 / (2 * steps)
+        ops = n * fp64_ops_per_byte(ctx.params.n_it, integ)
+        res[integ] = dict(enc_dec_GBps=2 * n * steps / (ms / 1e3) / GB, avg_launch_ms=launch_s * 1e3,
+                          ops_per_byte=fp64_ops_per_byte(ctx.params.n_it, integ),
+                          achieved_Tops=ops / launch_s / 1e12, frac_of_issue_peak=ops / launch_s / FP64_VALU_OPS_PEAK,
+                          roundtrip_exact=bool(torch.equal(Q, dP)) and int(st.item()) == 0)
+        ctx.close()
+    return res
+
+
+def bench_sequential(lz, torch, count=4096):
+    """The sequential strong version (one chain per message: block_len >= n), batched one
+    message per lane, against the block mode on the same messages."""
+    from paper_1201_3114_amd import workloads
+
+    wl = workloads.batch(count=count, seed=workloads.SEED["sequential"], lo=256, hi=4096)
+    sizes = wl.sizes
+    total = int(sizes.sum())
+    in_off = wl.offsets.astype(np.uint64)
+    out_off, out_tot = lz.packed_offsets(sizes, 24)
+    d_in = torch.from_numpy(wl.data).cuda()
+    d_out = torch.empty(out_tot, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = dict(messages=count, bytes=total, sizes="log-uniform 256 B..4 KiB, own 8..64-byte passwords")
+    for name, bl in (("sequential", (1 << 32) - 1), ("block_256", 256)):
+        ctx = lz.Context(0, lz.params(block_len=bl))
+        b = lz.Batch(ctx, False, sizes, wl.passwords, d_in, in_off, d_out, out_off)
+        b.launch()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        b.launch()
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        ms = e[0].elapsed_time(e[1])
+        res[name] = dict(encrypt_GBps=total / ms / 1e6, ms=ms, chains=int(count if bl > 4096 else
+                                                                           sum((int(x) + 255) // 256 for x in sizes)))
+        b.close()
+        ctx.close()
+    return res
 
 
 # ---------------------------------------------------------------------------------------------
@@ -355,7 +428,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--only", choices=["all", "plain", "batch", "serve", "copycal"], default="all")
+    ap.add_argument("--only", choices=["all", "plain", "batch", "serve", "variants", "copycal"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200_000)
     ap.add_argument("--serve-qps", type=float, default=0.0, help="0 = 0.7 x plain-path capacity")
@@ -428,6 +501,10 @@ def main():
     if args.only in ("all", "batch"):
         log("batched ...")
         out["batched"] = bench_batch(lz, torch, args.batch_steps)
+    if args.only in ("all", "variants"):
+        log("integrator formats and sequential version ...")
+        out["integrator_formats"] = bench_variants(lz, torch)
+        out["sequential_version"] = bench_sequential(lz, torch)
     if args.only in ("all", "serve"):
         from paper_1201_3114_amd import workloads
 

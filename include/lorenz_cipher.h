@@ -52,19 +52,34 @@ enum {
     LZ_E_AGAIN = -5      /* server: nothing to return yet                                 */
 };
 
+/* Integrator of the dynamical system F (Section 3.1 uses forward Euler and
+ * notes that other numerical methods could be considered).  Each value is a
+ * distinct ciphertext format.
+ *  LZ_INTEGRATOR_EULER      forward Euler, 14 separately rounded operations per
+ *                           step (the method; the default);
+ *  LZ_INTEGRATOR_EULER_FMA  the same step with each update fused into one
+ *                           rounding: dy = fma(x, rho-z, -y), dz = fma(x, y,
+ *                           -(beta z)), x += dt dx as fma(dt, dx, x); 9 roundings;
+ *  LZ_INTEGRATOR_RK4        classical Runge-Kutta 4 with the same vector field,
+ *                           r += dt/6 ((k1 + k4) + 2 (k2 + k3)). */
+enum { LZ_INTEGRATOR_EULER = 0, LZ_INTEGRATOR_EULER_FMA = 1, LZ_INTEGRATOR_RK4 = 2 };
+
 /* Parameters of the method (Section 3.1; readings in the design notes).
  * Defaults (lz_params_default): dt = 0.01, lambda = (1,1,1), n_it = 3000,
- * block_len = 256, k = (4,4,4).  Valid ranges (else LZ_E_INVAL):
- * 0 < dt <= 0.024 (forward Euler diverges from the attractor above it),
- * each lambda_j inside the paper's range for its coordinate, n_it >= 1,
- * 1 <= block_len <= 2^20, k_i in {3, 4} (2 < k_i <= floor((xi-14)/8) = 4). */
+ * block_len = 256, k = (4,4,4), integrator = LZ_INTEGRATOR_EULER.  Valid
+ * ranges (else LZ_E_INVAL): 0 < dt <= 0.024 (forward Euler diverges from the
+ * attractor above it), each lambda_j inside the paper's range for its
+ * coordinate, n_it >= 1, block_len >= 1 (block_len >= n gives the sequential
+ * version of Section 5: the whole message is one chain), k_i in {3, 4}
+ * (2 < k_i <= floor((xi-14)/8) = 4), integrator one of the values above. */
 typedef struct {
     double dt;
     double lambda[3];
     uint32_t n_it;
     uint32_t block_len;
     uint8_t k[3];
-    uint8_t reserved[5]; /* must be zero */
+    uint8_t integrator;
+    uint8_t reserved[4]; /* must be zero */
 } lz_params;
 
 /* Output of the password stage of Section 3.1 (64 bytes, plain data). */

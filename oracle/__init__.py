@@ -33,7 +33,7 @@ def build() -> str:
 
 class Params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("lam", ctypes.c_double * 3), ("n_it", ctypes.c_uint32),
-                ("block_len", ctypes.c_uint32), ("k", ctypes.c_uint32 * 3)]
+                ("block_len", ctypes.c_uint32), ("k", ctypes.c_uint32 * 3), ("integrator", ctypes.c_uint32)]
 
 
 class Key(ctypes.Structure):
@@ -57,6 +57,9 @@ def lib():
         L.orc_key_setup.restype = ctypes.c_int
         L.orc_lorenz.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_uint64]
         L.orc_lorenz.restype = None
+        L.orc_lorenz_integrator.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_uint64,
+                                            ctypes.c_uint32]
+        L.orc_lorenz_integrator.restype = None
         L.orc_R.argtypes = [ctypes.c_double, ctypes.c_int]
         L.orc_R.restype = ctypes.c_int
         L.orc_theta.argtypes = [ctypes.c_int, ctypes.c_int]
@@ -74,8 +77,12 @@ def lib():
     return _lib
 
 
-def params(dt=0.01, n_it=3000, block_len=256, lam=(1.0, 1.0, 1.0), k=(4, 4, 4)) -> Params:
+INTEGRATORS = {"euler": 0, "euler_fma": 1, "rk4": 2}
+
+
+def params(dt=0.01, n_it=3000, block_len=256, lam=(1.0, 1.0, 1.0), k=(4, 4, 4), integrator="euler") -> Params:
     p = Params()
+    p.integrator = INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
     p.dt = dt
     p.lam[:] = list(lam)
     p.n_it = n_it
@@ -103,9 +110,10 @@ def key_setup(pw: bytes, **kw) -> dict:
                 k=list(k.k))
 
 
-def lorenz(r, dt, steps):
+def lorenz(r, dt, steps, integrator="euler"):
     arr = (ctypes.c_double * 3)(*r)
-    lib().orc_lorenz(arr, dt, steps)
+    code = INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
+    lib().orc_lorenz_integrator(arr, dt, steps, code)
     return list(arr)
 
 

@@ -50,6 +50,9 @@ typedef struct {
     uint32_t n_it;      /* Euler steps applied per byte                       */
     uint32_t block_len; /* bytes per independent block (parallel version)     */
     uint32_t k[3];      /* moduli of the byte indices Omega, 2 < k_i <= 4     */
+    uint32_t integrator; /* 0 Euler (the method), 1 Euler with fused multiply-add,
+                            2 classical Runge-Kutta 4 ("other numerical methods
+                            could be considered", Section 3.1)                 */
 } orc_params;
 
 /* Output of the password stage of Section 3.1. */
@@ -243,9 +246,49 @@ static void lorenz_euler_step(double r[3], double dt) {
     r[2] = z + dt * dz;
 }
 
-void orc_lorenz(double r[3], double dt, uint64_t steps) {
-    for (uint64_t t = 0; t < steps; t++) lorenz_euler_step(r, dt);
+/* The same forward Euler step with each update fused into one rounding:
+ * dy = fma(x, rho - z, -y), dz = fma(x, y, -(beta z)), x += dt dx as fma(dt, dx, x). */
+static void lorenz_euler_fma_step(double r[3], double dt) {
+    double x = r[0], y = r[1], z = r[2];
+    double dx = SIGMA * (y - x);
+    double dy = fma(x, RHO - z, -y);
+    double dz = fma(x, y, -(BETA * z));
+    r[0] = fma(dt, dx, x);
+    r[1] = fma(dt, dy, y);
+    r[2] = fma(dt, dz, z);
 }
+
+/* Lorenz vector field, same evaluation order as the Euler step. */
+static void lorenz_field(const double r[3], double k[3]) {
+    k[0] = SIGMA * (r[1] - r[0]);
+    k[1] = (r[0] * (RHO - r[2])) - r[1];
+    k[2] = (r[0] * r[1]) - (BETA * r[2]);
+}
+
+/* Classical Runge-Kutta 4: k1 = f(r), k2 = f(r + dt/2 k1), k3 = f(r + dt/2 k2),
+ * k4 = f(r + dt k3), r += dt/6 ((k1 + k4) + 2 (k2 + k3)). */
+static void lorenz_rk4_step(double r[3], double dt) {
+    const double h2 = dt * 0.5, h6 = dt / 6.0;
+    double k1[3], k2[3], k3[3], k4[3], t[3];
+    lorenz_field(r, k1);
+    for (int j = 0; j < 3; j++) t[j] = r[j] + h2 * k1[j];
+    lorenz_field(t, k2);
+    for (int j = 0; j < 3; j++) t[j] = r[j] + h2 * k2[j];
+    lorenz_field(t, k3);
+    for (int j = 0; j < 3; j++) t[j] = r[j] + dt * k3[j];
+    lorenz_field(t, k4);
+    for (int j = 0; j < 3; j++) r[j] = r[j] + h6 * ((k1[j] + k4[j]) + 2.0 * (k2[j] + k3[j]));
+}
+
+void orc_lorenz_integrator(double r[3], double dt, uint64_t steps, uint32_t integrator) {
+    for (uint64_t t = 0; t < steps; t++) {
+        if (integrator == 1) lorenz_euler_fma_step(r, dt);
+        else if (integrator == 2) lorenz_rk4_step(r, dt);
+        else lorenz_euler_step(r, dt);
+    }
+}
+
+void orc_lorenz(double r[3], double dt, uint64_t steps) { orc_lorenz_integrator(r, dt, steps, 0); }
 
 /* ---- Eq. R_nu: byte Omega of floor(alpha 10^nu) --------------------------- */
 
@@ -290,7 +333,7 @@ void orc_block(const orc_key *K, const orc_params *prm, uint64_t b, const uint8_
         /* Step 2: chaotic operation mode: r[mu_3] += Theta, then F^(n_it) */
         double theta = orc_theta(p, Om[2]);
         r[mu[2]] = r[mu[2]] + theta;
-        orc_lorenz(r, prm->dt, prm->n_it);
+        orc_lorenz_integrator(r, prm->dt, prm->n_it, prm->integrator);
         /* Step 3 */
         int R3 = orc_R(alpha[2], Om[2]);
         int Rold[3] = {R1, R2, R3};
@@ -355,7 +398,7 @@ static int run_blocks(const orc_key *K, const orc_params *prm, const uint8_t *in
 }
 
 static int check_params(const orc_params *prm) {
-    if (!prm || !(prm->dt > 0.0) || prm->n_it == 0 || prm->block_len == 0) return -1;
+    if (!prm || !(prm->dt > 0.0) || prm->n_it == 0 || prm->block_len == 0 || prm->integrator > 2) return -1;
     for (int i = 0; i < 3; i++)
         if (prm->k[i] < 3 || prm->k[i] > 4) return -1;
     return 0;

@@ -71,6 +71,44 @@ def euler(r, dt, steps):
     return [x, y, z]
 
 
+def fma(a: float, b: float, c: float) -> float:
+    """a*b + c with one rounding (exact rational arithmetic, then nearest-even)."""
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def euler_fma(r, dt, steps):
+    """Euler with each update fused into one rounding (variant format of Section 3.1's F)."""
+    x, y, z = r
+    for _ in range(steps):
+        dx = SIGMA * (y - x)
+        dy = fma(x, RHO - z, -y)
+        dz = fma(x, y, -(BETA * z))
+        x, y, z = fma(dt, dx, x), fma(dt, dy, y), fma(dt, dz, z)
+    return [x, y, z]
+
+
+def _field(x, y, z):
+    return SIGMA * (y - x), (x * (RHO - z)) - y, (x * y) - (BETA * z)
+
+
+def rk4(r, dt, steps):
+    """Classical Runge-Kutta 4 of the Lorenz system ("other numerical methods", Section 3.1)."""
+    x, y, z = r
+    h2, h6 = dt * 0.5, dt / 6.0
+    for _ in range(steps):
+        k1 = _field(x, y, z)
+        k2 = _field(x + h2 * k1[0], y + h2 * k1[1], z + h2 * k1[2])
+        k3 = _field(x + h2 * k2[0], y + h2 * k2[1], z + h2 * k2[2])
+        k4 = _field(x + dt * k3[0], y + dt * k3[1], z + dt * k3[2])
+        x = x + h6 * ((k1[0] + k4[0]) + 2.0 * (k2[0] + k3[0]))
+        y = y + h6 * ((k1[1] + k4[1]) + 2.0 * (k2[1] + k3[1]))
+        z = z + h6 * ((k1[2] + k4[2]) + 2.0 * (k2[2] + k3[2]))
+    return [x, y, z]
+
+
+INTEGRATORS = {"euler": euler, "euler_fma": euler_fma, "rk4": rk4}
+
+
 def R(alpha: float, omega: int) -> int:
     """Eq. R_nu: byte Omega of floor(alpha 10^nu), two's complement."""
     return (math.floor(alpha * SCALE) >> (8 * omega)) & 255
@@ -81,7 +119,7 @@ def digest(v: float) -> int:
     return math.floor(v * SCALE) & (2 ** 64 - 1)
 
 
-def crypt_block(key, b, data: bytes, decrypt: bool, dt=0.01, n_it=3000):
+def crypt_block(key, b, data: bytes, decrypt: bool, dt=0.01, n_it=3000, integrator="euler"):
     """Steps 1-3 of Section 3.2 over block b of the parallel version (Section 5)."""
     r = [key["r0"][j] + b * 2.0 ** -24 for j in range(3)]
     mu = list(key["mu"])
@@ -99,7 +137,7 @@ def crypt_block(key, b, data: bytes, decrypt: bool, dt=0.01, n_it=3000):
             out.append((p + R1 + R2) % 256)
         theta = p / 10.0 ** (3 + om[2])
         r[mu[2]] = r[mu[2]] + theta
-        r = euler(r, dt, n_it)
+        r = INTEGRATORS[integrator](r, dt, n_it)
         R3 = R(alpha[2], om[2])
         mu = [(mu[i] + (R1, R2, R3)[i]) % 3 for i in range(3)]
         alpha = [r[mu[i]] for i in range(3)]
@@ -114,25 +152,25 @@ def _blocks(n, B):
     return [(b, b * B, min(n, (b + 1) * B)) for b in range((n + B - 1) // B)]
 
 
-def encrypt(pw: bytes, P: bytes, dt=0.01, n_it=3000, B=256, lam=(1.0, 1.0, 1.0), k=(4, 4, 4)):
+def encrypt(pw: bytes, P: bytes, dt=0.01, n_it=3000, B=256, lam=(1.0, 1.0, 1.0), k=(4, 4, 4), integrator="euler"):
     key = key_setup(pw, lam, k)
     body = bytearray()
     T = [0, 0, 0]
     for b, s, e in _blocks(len(P), B):
-        c, d = crypt_block(key, b, P[s:e], False, dt, n_it)
+        c, d = crypt_block(key, b, P[s:e], False, dt, n_it, integrator)
         body += c
         T = [T[j] ^ d[j] for j in range(3)]
     return bytes(body) + b"".join(t.to_bytes(8, "little") for t in T)
 
 
-def decrypt(pw: bytes, C: bytes, dt=0.01, n_it=3000, B=256, lam=(1.0, 1.0, 1.0), k=(4, 4, 4)):
+def decrypt(pw: bytes, C: bytes, dt=0.01, n_it=3000, B=256, lam=(1.0, 1.0, 1.0), k=(4, 4, 4), integrator="euler"):
     """Returns (plaintext, ok); on a tag mismatch the plaintext is all zeros."""
     key = key_setup(pw, lam, k)
     n = len(C) - 24
     body = bytearray()
     T = [0, 0, 0]
     for b, s, e in _blocks(n, B):
-        p, d = crypt_block(key, b, C[s:e], True, dt, n_it)
+        p, d = crypt_block(key, b, C[s:e], True, dt, n_it, integrator)
         body += p
         T = [T[j] ^ d[j] for j in range(3)]
     stored = [int.from_bytes(C[n + 8 * j:n + 8 * j + 8], "little") for j in range(3)]

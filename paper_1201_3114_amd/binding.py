@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "liblorenz_cipher.so")
 
 LZ_OK, LZ_E_INVAL, LZ_E_INTEGRITY, LZ_E_NOMEM, LZ_E_HIP, LZ_E_AGAIN = 0, -1, -2, -3, -4, -5
 TAG_BYTES = 24
+INTEGRATORS = {"euler": 0, "euler_fma": 1, "rk4": 2}
 
 u8p = ctypes.POINTER(ctypes.c_uint8)
 vp = ctypes.c_void_p
@@ -22,7 +23,8 @@ vp = ctypes.c_void_p
 
 class Params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("lam", ctypes.c_double * 3), ("n_it", ctypes.c_uint32),
-                ("block_len", ctypes.c_uint32), ("k", ctypes.c_uint8 * 3), ("reserved", ctypes.c_uint8 * 5)]
+                ("block_len", ctypes.c_uint32), ("k", ctypes.c_uint8 * 3), ("integrator", ctypes.c_uint8),
+                ("reserved", ctypes.c_uint8 * 4)]
 
 
 class Key(ctypes.Structure):

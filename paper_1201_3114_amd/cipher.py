@@ -16,10 +16,13 @@ from .binding import IntegrityError, LorenzError, check  # noqa: F401  (re-expor
 TAG_BYTES = B.TAG_BYTES
 
 
-def params(dt: float = 0.01, n_it: int = 3000, block_len: int = 256, lam=(1.0, 1.0, 1.0), k=(4, 4, 4)) -> B.Params:
-    """Method parameters (Section 3.1): Euler step, steps per byte, block length, lambda, k."""
+def params(dt: float = 0.01, n_it: int = 3000, block_len: int = 256, lam=(1.0, 1.0, 1.0), k=(4, 4, 4),
+           integrator="euler") -> B.Params:
+    """Method parameters (Section 3.1): step, steps per byte, block length (>= n: the sequential
+    version), lambda, k, and the integrator format ("euler", "euler_fma", "rk4")."""
     p = B.Params()
     check(B.lib.lz_params_default(ctypes.byref(p)))
+    p.integrator = B.INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
     p.dt = dt
     p.n_it = n_it
     p.block_len = block_len

@@ -58,20 +58,59 @@ __device__ __forceinline__ void euler_step(double &x, double &y, double &z, doub
     z = z + dt * dz;
 }
 
-template <int M>
+// Format variant: the Euler step with each update fused into one rounding (9 roundings).
+__device__ __forceinline__ void euler_fma_step(double &x, double &y, double &z, double dt) {
+    const double dx = SIGMA * (y - x);
+    const double dy = __builtin_fma(x, RHO - z, -y);
+    const double dz = __builtin_fma(x, y, -(BETA * z));
+    x = __builtin_fma(dt, dx, x);
+    y = __builtin_fma(dt, dy, y);
+    z = __builtin_fma(dt, dz, z);
+}
+
+// Lorenz vector field in the Euler step's evaluation order.
+__device__ __forceinline__ void lorenz_field(double x, double y, double z, double &fx, double &fy, double &fz) {
+    fx = SIGMA * (y - x);
+    fy = (x * (RHO - z)) - y;
+    fz = (x * y) - (BETA * z);
+}
+
+// Format variant: classical Runge-Kutta 4, r += dt/6 ((k1 + k4) + 2 (k2 + k3)).
+__device__ __forceinline__ void rk4_step(double &x, double &y, double &z, double dt, double h2, double h6) {
+    double ax, ay, az, bx, by, bz, cx, cy, cz, dx, dy, dz;
+    lorenz_field(x, y, z, ax, ay, az);
+    lorenz_field(x + h2 * ax, y + h2 * ay, z + h2 * az, bx, by, bz);
+    lorenz_field(x + h2 * bx, y + h2 * by, z + h2 * bz, cx, cy, cz);
+    lorenz_field(x + dt * cx, y + dt * cy, z + dt * cz, dx, dy, dz);
+    x = x + h6 * ((ax + dx) + 2.0 * (bx + cx));
+    y = y + h6 * ((ay + dy) + 2.0 * (by + cy));
+    z = z + h6 * ((az + dz) + 2.0 * (bz + cz));
+}
+
+template <int I>
+__device__ __forceinline__ void step(double &x, double &y, double &z, double dt, double h2, double h6) {
+    if constexpr (I == LZ_INTEGRATOR_EULER_FMA) euler_fma_step(x, y, z, dt);
+    else if constexpr (I == LZ_INTEGRATOR_RK4) rk4_step(x, y, z, dt, h2, h6);
+    else euler_step(x, y, z, dt);
+}
+
+// Step 2's F^(n_it) for the M chains of a lane, interleaved step by step.
+template <int M, int I>
 __device__ __forceinline__ void lorenz_steps(double (&x)[M], double (&y)[M], double (&z)[M], double dt,
                                              uint32_t n_it) {
-    const uint32_t q = n_it >> 3;
+    const double h2 = dt * 0.5, h6 = I == LZ_INTEGRATOR_RK4 ? dt / 6.0 : 0.0;
+    constexpr int U = I == LZ_INTEGRATOR_RK4 ? 2 : 8;
+    const uint32_t q = n_it / U;
     for (uint32_t i = 0; i < q; ++i) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < U; ++u) {
 #pragma unroll
-            for (int m = 0; m < M; ++m) euler_step(x[m], y[m], z[m], dt);
+            for (int m = 0; m < M; ++m) step<I>(x[m], y[m], z[m], dt, h2, h6);
         }
     }
-    for (uint32_t i = q << 3; i < n_it; ++i) {
+    for (uint32_t i = q * U; i < n_it; ++i) {
 #pragma unroll
-        for (int m = 0; m < M; ++m) euler_step(x[m], y[m], z[m], dt);
+        for (int m = 0; m < M; ++m) step<I>(x[m], y[m], z[m], dt, h2, h6);
     }
 }
 
@@ -109,7 +148,7 @@ __device__ __forceinline__ void init_chain(Chains<M> &c, int m, const double (&r
 __device__ __forceinline__ uint32_t mod_k(uint32_t v, uint32_t k) { return k == 4 ? (v & 3u) : v % 3u; }
 
 // Steps 1-3 of Section 3.2 for one byte of each of the M chains.
-template <int M>
+template <int M, int I>
 __device__ __forceinline__ void crypt_byte(Chains<M> &c, const uint32_t (&bin)[M], uint32_t (&bout)[M], double dt,
                                            uint32_t n_it) {
     uint32_t R1[M], R2[M], p[M];
@@ -130,13 +169,16 @@ __device__ __forceinline__ void crypt_byte(Chains<M> &c, const uint32_t (&bin)[M
         const uint32_t o3 = c.om2[m];
         const double p10 = o3 == 0 ? 1e3 : (o3 == 1 ? 1e4 : (o3 == 2 ? 1e5 : 1e6));
         const double th = (double)p[m] / p10;
+        // r[mu_3] += Theta, written as value selects: a select of the coordinate's address
+        // would force the chain state out of registers
         const uint32_t s = c.mu2[m];
-        if (s == 0) c.x[m] = c.x[m] + th;
-        else if (s == 1) c.y[m] = c.y[m] + th;
-        else c.z[m] = c.z[m] + th;
+        const double moved = sel3(s, c.x[m], c.y[m], c.z[m]) + th;
+        c.x[m] = s == 0 ? moved : c.x[m];
+        c.y[m] = s == 1 ? moved : c.y[m];
+        c.z[m] = s == 2 ? moved : c.z[m];
     }
     // Step 2 (cont.): r <- F^(n_it)(r)
-    lorenz_steps<M>(c.x, c.y, c.z, dt, n_it);
+    lorenz_steps<M, I>(c.x, c.y, c.z, dt, n_it);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         // Step 3: mu_i <- (mu_i + R_i) mod 3 with R_i from the old alpha_i, Omega_i
@@ -219,7 +261,7 @@ __device__ __forceinline__ WaveLds wave_lds(char *base, int tile) {
 // last byte (or before the loop when cnt[m] == 0), with c holding that chain's
 // state; chains past their end keep running on zero bytes but their results
 // are neither stored nor used.
-template <int M, typename OnStop>
+template <int M, int I, typename OnStop>
 __device__ __forceinline__ void wave_run(Chains<M> &c, const WaveLds &w, int tile, const uint8_t *const (&in)[M],
                                          uint8_t *const (&out)[M], const uint32_t (&cnt)[M], double dt,
                                          uint32_t n_it, int lane, OnStop on_stop) {
@@ -250,7 +292,7 @@ __device__ __forceinline__ void wave_run(Chains<M> &c, const WaveLds &w, int til
             uint32_t bin[M], bout[M];
 #pragma unroll
             for (int m = 0; m < M; ++m) bin[m] = j < cnt[m] ? w.tile[(m * WAVE + lane) * stride + kk] : 0u;
-            crypt_byte<M>(c, bin, bout, dt, n_it);
+            crypt_byte<M, I>(c, bin, bout, dt, n_it);
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 if (j < cnt[m]) w.tile[(m * WAVE + lane) * stride + kk] = (uint8_t)bout[m];
@@ -282,8 +324,8 @@ struct PlainArgs {
     unsigned long long *tag_acc;
 };
 
-template <int M>
-__global__ void plain_kernel(PlainArgs a) {
+template <int M, int I>
+__global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
     extern __shared__ char lds[];
     const int lane = threadIdx.x % WAVE;
     const int wid = threadIdx.x / WAVE;
@@ -311,7 +353,7 @@ __global__ void plain_kernel(PlainArgs a) {
         init_chain<M>(c, m, r0, ap, mu, om, k, valid[m] ? g : 0, a.decrypt);
         d0[m] = d1[m] = d2[m] = 0;
     }
-    wave_run<M>(c, w, (int)a.tile, in, out, cnt, a.dt, a.n_it, lane, [&](int m) {
+    wave_run<M, I>(c, w, (int)a.tile, in, out, cnt, a.dt, a.n_it, lane, [&](int m) __attribute__((always_inline)) {
         d0[m] = digest_word(c.x[m]);
         d1[m] = digest_word(c.y[m]);
         d2[m] = digest_word(c.z[m]);
@@ -371,8 +413,8 @@ __device__ __forceinline__ uint32_t find_msg(const uint64_t *prefix, uint32_t n_
     return lo;
 }
 
-template <int M>
-__global__ void batch_kernel(BatchArgs a) {
+template <int M, int I>
+__global__ __launch_bounds__(256) void batch_kernel(BatchArgs a) {
     extern __shared__ char lds[];
     const int lane = threadIdx.x % WAVE;
     const int wid = threadIdx.x / WAVE;
@@ -426,7 +468,7 @@ __global__ void batch_kernel(BatchArgs a) {
             init_chain<M>(c, m, r0, ap, mu, om, k, b, md.decrypt);
             d0[m] = d1[m] = d2[m] = 0;
         }
-        wave_run<M>(c, w, (int)a.tile, in, out, cnt, a.dt, a.n_it, lane, [&](int m) {
+        wave_run<M, I>(c, w, (int)a.tile, in, out, cnt, a.dt, a.n_it, lane, [&](int m) __attribute__((always_inline)) {
             d0[m] = digest_word(c.x[m]);
             d1[m] = digest_word(c.y[m]);
             d2[m] = digest_word(c.z[m]);
@@ -472,8 +514,8 @@ struct TickArgs {
     uint32_t n_it, block_len, tile;
 };
 
-template <int M>
-__global__ void tick_kernel(TickArgs a) {
+template <int M, int I>
+__global__ __launch_bounds__(256) void tick_kernel(TickArgs a) {
     extern __shared__ char lds[];
     const int lane = threadIdx.x % WAVE;
     const int wid = threadIdx.x / WAVE;
@@ -523,7 +565,7 @@ __global__ void tick_kernel(TickArgs a) {
         in[m] = md.in + off;
         out[m] = md.out + off;
     }
-    wave_run<M>(c, w, (int)a.tile, in, out, cnt, a.dt, a.n_it, lane, [&](int m) {
+    wave_run<M, I>(c, w, (int)a.tile, in, out, cnt, a.dt, a.n_it, lane, [&](int m) __attribute__((always_inline)) {
         if (!valid[m]) return;
         ChainSlot &s = a.t.slots[slot[m]];
         s.r[0] = c.x[m]; s.r[1] = c.y[m]; s.r[2] = c.z[m];
@@ -588,12 +630,23 @@ __global__ void install_kernel(ReqDesc *reqs, ChainSlot *slots, const ReqDesc *s
     }
 }
 
+template <int M, typename F>
+hipError_t dispatch_i(uint32_t integ, F f) {
+    switch (integ) {
+        case LZ_INTEGRATOR_EULER: return f(std::integral_constant<int, M>{}, std::integral_constant<int, 0>{});
+        case LZ_INTEGRATOR_EULER_FMA: return f(std::integral_constant<int, M>{}, std::integral_constant<int, 1>{});
+        case LZ_INTEGRATOR_RK4: return f(std::integral_constant<int, M>{}, std::integral_constant<int, 2>{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Calls f(M, I) with the compile-time chains-per-lane and integrator of the launch.
 template <typename F>
-hipError_t dispatch_m(int m, F f) {
+hipError_t dispatch(int m, uint32_t integ, F f) {
     switch (m) {
-        case 1: return f(std::integral_constant<int, 1>{});
-        case 2: return f(std::integral_constant<int, 2>{});
-        case 4: return f(std::integral_constant<int, 4>{});
+        case 1: return dispatch_i<1>(integ, f);
+        case 2: return dispatch_i<2>(integ, f);
+        case 4: return dispatch_i<4>(integ, f);
         default: return hipErrorInvalidValue;
     }
 }
@@ -639,9 +692,10 @@ hipError_t launch_plain(const KernelShape &sh, const lz_key &key, const lz_param
     const uint64_t per_wg = (uint64_t)sh.wg * sh.m;
     const uint64_t grid = (a.nb + per_wg - 1) / per_wg;
     const size_t lds = lds_bytes(sh);
-    return dispatch_m(sh.m, [&](auto mc) {
+    return dispatch(sh.m, prm.integrator, [&](auto mc, auto ic) {
         constexpr int M = decltype(mc)::value;
-        hipLaunchKernelGGL(plain_kernel<M>, dim3((unsigned)grid), dim3(sh.wg), lds, s, a);
+        constexpr int I = decltype(ic)::value;
+        hipLaunchKernelGGL((plain_kernel<M, I>), dim3((unsigned)grid), dim3(sh.wg), lds, s, a);
         return hipGetLastError();
     });
 }
@@ -673,9 +727,10 @@ hipError_t launch_batch(const KernelShape &sh, const DevInfo &dev, const lz_para
     const uint64_t need = (b.n_tasks + wpw - 1) / wpw;
     if (need < grid) grid = need ? need : 1;
     const size_t lds = lds_bytes(sh);
-    return dispatch_m(sh.m, [&](auto mc) {
+    return dispatch(sh.m, prm.integrator, [&](auto mc, auto ic) {
         constexpr int M = decltype(mc)::value;
-        hipLaunchKernelGGL(batch_kernel<M>, dim3((unsigned)grid), dim3(sh.wg), lds, s, a);
+        constexpr int I = decltype(ic)::value;
+        hipLaunchKernelGGL((batch_kernel<M, I>), dim3((unsigned)grid), dim3(sh.wg), lds, s, a);
         return hipGetLastError();
     });
 }
@@ -696,9 +751,10 @@ hipError_t launch_tick(const KernelShape &sh, const lz_params &prm, const TickDe
     const uint64_t per_wg = (uint64_t)sh.wg * sh.m;
     const uint64_t grid = (t.n_list + per_wg - 1) / per_wg;
     const size_t lds = lds_bytes(sh);
-    return dispatch_m(sh.m, [&](auto mc) {
+    return dispatch(sh.m, prm.integrator, [&](auto mc, auto ic) {
         constexpr int M = decltype(mc)::value;
-        hipLaunchKernelGGL(tick_kernel<M>, dim3((unsigned)grid), dim3(sh.wg), lds, s, a);
+        constexpr int I = decltype(ic)::value;
+        hipLaunchKernelGGL((tick_kernel<M, I>), dim3((unsigned)grid), dim3(sh.wg), lds, s, a);
         return hipGetLastError();
     });
 }

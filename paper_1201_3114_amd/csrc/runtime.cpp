@@ -40,7 +40,8 @@ int check_params(const lz_params &p) {
         !(p.lambda[2] > 0.090 && p.lambda[2] < 62.0))
         return fail(LZ_E_INVAL, "lambda outside the ranges of Section 3.1");
     if (p.n_it == 0) return fail(LZ_E_INVAL, "n_it must be >= 1");
-    if (p.block_len == 0 || p.block_len > (1u << 20)) return fail(LZ_E_INVAL, "block_len must be in [1, 2^20]");
+    if (p.block_len == 0) return fail(LZ_E_INVAL, "block_len must be >= 1");
+    if (p.integrator > LZ_INTEGRATOR_RK4) return fail(LZ_E_INVAL, "unknown integrator");
     for (int i = 0; i < 3; ++i)
         if (p.k[i] != 3 && p.k[i] != 4) return fail(LZ_E_INVAL, "k_i must be 3 or 4");
     for (uint8_t r : p.reserved)

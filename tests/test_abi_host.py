@@ -48,8 +48,7 @@ def test_params_default_and_check(B):
     assert B.lib.lz_params_default(ctypes.byref(p)) == 0
     assert (p.dt, p.n_it, p.block_len, list(p.k), list(p.lam)) == (0.01, 3000, 256, [4, 4, 4], [1.0, 1.0, 1.0])
     assert B.lib.lz_params_check(ctypes.byref(p)) == 0
-    for field, bad in [("dt", 0.0), ("dt", 0.025), ("dt", -1.0), ("n_it", 0), ("block_len", 0),
-                       ("block_len", (1 << 20) + 1)]:
+    for field, bad in [("dt", 0.0), ("dt", 0.025), ("dt", -1.0), ("n_it", 0), ("block_len", 0), ("integrator", 3)]:
         q = B.Params()
         B.lib.lz_params_default(ctypes.byref(q))
         setattr(q, field, bad)
@@ -60,6 +59,11 @@ def test_params_default_and_check(B):
         B.lib.lz_params_default(ctypes.byref(q))
         q.k[1] = k
         assert B.lib.lz_params_check(ctypes.byref(q)) == B.LZ_E_INVAL
+    for ok_field, ok in [("block_len", (1 << 32) - 1), ("integrator", 1), ("integrator", 2)]:
+        q = B.Params()
+        B.lib.lz_params_default(ctypes.byref(q))
+        setattr(q, ok_field, ok)
+        assert B.lib.lz_params_check(ctypes.byref(q)) == 0, (ok_field, ok)
     q = B.Params()
     B.lib.lz_params_default(ctypes.byref(q))
     q.lam[2] = 0.05  # outside 0.090 < lambda_3 < 62

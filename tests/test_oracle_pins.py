@@ -337,3 +337,77 @@ def test_threads_do_not_change_output():
     a = oracle.encrypt(b"threads", P, n_it=50, nthreads=1)
     b = oracle.encrypt(b"threads", P, n_it=50, nthreads=8)
     assert np.array_equal(a, b)
+
+
+# ---- integrator variants (Section 3.1: "other numerical methods could be considered") --------
+
+def test_variant_fixed_points():
+    c = math.sqrt(72.0)
+    for integ in ("euler_fma", "rk4"):
+        for r in ([0.0, 0.0, 0.0], [c, c, 27.0], [-c, -c, 27.0]):
+            assert oracle.lorenz(r, 0.01, 3000, integ) == r, integ
+            assert pyref.INTEGRATORS[integ](r, 0.01, 300) == r, integ
+
+
+def test_rk4_fourth_order_convergence():
+    """RK4 reaches the DOP853 solution of the Lorenz ODE with error ratio ~16 per halving of dt."""
+    from scipy.integrate import solve_ivp
+
+    def f(t, r):
+        x, y, z = r
+        return [10.0 * (y - x), x * (28.0 - z) - y, x * y - 8.0 / 3.0 * z]
+
+    r0, T = [1.0, 1.0, 1.0], 0.5
+    ref = solve_ivp(f, (0, T), r0, rtol=1e-13, atol=1e-13, method="DOP853").y[:, -1]
+    errs = [float(np.max(np.abs(np.array(oracle.lorenz(r0, dt, int(round(T / dt)), "rk4")) - ref)))
+            for dt in (0.01, 0.005, 0.0025)]
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 14.0 < e1 / e2 < 20.0, errs
+
+
+def test_euler_fma_first_order_and_close_to_euler():
+    """Fused Euler converges at first order and differs from the 14-rounding Euler only by rounding."""
+    from scipy.integrate import solve_ivp
+
+    def f(t, r):
+        x, y, z = r
+        return [10.0 * (y - x), x * (28.0 - z) - y, x * y - 8.0 / 3.0 * z]
+
+    r0, T = [1.0, 1.0, 1.0], 1.0
+    ref = solve_ivp(f, (0, T), r0, rtol=1e-12, atol=1e-12, method="DOP853").y[:, -1]
+    errs = [float(np.max(np.abs(np.array(oracle.lorenz(r0, dt, int(round(T / dt)), "euler_fma")) - ref)))
+            for dt in (1e-3, 5e-4, 2.5e-4)]
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 1.8 < e1 / e2 < 2.2, errs
+    rng = np.random.default_rng(16)
+    for _ in range(200):
+        r = [float(v) for v in rng.uniform(-20, 20, 3)]
+        a = oracle.lorenz(r, 0.01, 1, "euler")
+        b = oracle.lorenz(r, 0.01, 1, "euler_fma")
+        for u, v in zip(a, b):
+            assert abs(u - v) <= 8 * math.ulp(max(abs(u), 1.0))
+
+
+def test_variants_match_python_reference_bitwise():
+    rng = np.random.default_rng(17)
+    for integ in ("euler_fma", "rk4"):
+        for _ in range(10):
+            r = [float(v) for v in rng.uniform(-15, 15, 3)]
+            r[2] = abs(r[2]) + 5
+            assert oracle.lorenz(r, 0.01, 200, integ) == pyref.INTEGRATORS[integ](r, 0.01, 200), integ
+        P = bytes(rng.integers(0, 256, 50, dtype=np.uint8))
+        for B in (7, 1 << 20):
+            C = oracle.encrypt(b"variant", P, n_it=11, block_len=B, integrator=integ)
+            assert bytes(C) == pyref.encrypt(b"variant", P, n_it=11, B=B, integrator=integ)
+            Q, ok = oracle.decrypt(b"variant", C, n_it=11, block_len=B, integrator=integ)
+            assert ok and bytes(Q) == P
+
+
+def test_variants_are_distinct_formats():
+    P = np.random.default_rng(18).integers(0, 256, 512, dtype=np.uint8)
+    outs = {i: oracle.encrypt(b"formats", P, integrator=i, nthreads=2) for i in ("euler", "euler_fma", "rk4")}
+    assert np.mean(outs["euler"] != outs["euler_fma"]) > 0.5
+    assert np.mean(outs["euler"] != outs["rk4"]) > 0.9
+    for i, C in outs.items():
+        Q, ok = oracle.decrypt(b"formats", C, integrator=i, nthreads=2)
+        assert ok and np.array_equal(Q, P)
