@@ -107,6 +107,7 @@ typedef struct {
 typedef struct lz_ctx lz_ctx;
 typedef struct lz_batch lz_batch;
 typedef struct lz_server lz_server;
+typedef struct lz_stream lz_stream;
 
 /* ---- host-only helpers ---------------------------------------------------- */
 
@@ -199,6 +200,37 @@ int lz_batch_destroy(lz_batch *batch);
  * the sweep stops after that much measured time. */
 int lz_autotune(lz_ctx *ctx, double budget_ms, lz_launch *best);
 
+/* ---- streaming: one message of unknown length, chunk by chunk -----------------
+ * Encrypts (decrypt = 0) or decrypts one message given as a sequence of
+ * chunks.  The concatenated outputs equal the one-shot body (lz_encrypt /
+ * lz_decrypt) and the final tag equals its tag: the parallel version's
+ * blocks (Section 5) are cut at block boundaries, a partial block's chain
+ * state (r, alpha, mu, Omega of Section 3.2) waits on the device for the next
+ * chunk.  Decrypted chunks are NOT authenticated until lz_stream_finish
+ * reports LZ_OK; the caller must not release them before that.
+ *
+ * lz_stream_open: pw host pointer, 1..64 bytes; the stream owns ~128 bytes
+ * of device memory.  Synchronous. */
+int lz_stream_open(lz_ctx *ctx, int decrypt, const uint8_t *pw, size_t n_pw, lz_stream **out);
+
+/* Processes the next n bytes: d_in and d_out device pointers of n bytes
+ * (plaintext in / ciphertext body out, or the reverse; no tag).  Asynchronous
+ * on stream; calls are ordered among themselves even across streams.
+ * LZ_E_INVAL after lz_stream_finish or past 2^32 bytes in total. */
+int lz_stream_update(lz_stream *st, const uint8_t *d_in, size_t n, uint8_t *d_out, void *stream);
+
+/* Ends the message.  Encrypt: writes the 24-byte tag to d_tag (device).
+ * Decrypt: d_tag holds the received tag (device); the result goes to
+ * d_status (device int32: LZ_OK or LZ_E_INTEGRITY), or, with d_status NULL,
+ * the call synchronises and returns it. */
+int lz_stream_finish(lz_stream *st, uint8_t *d_tag, int32_t *d_status, void *stream);
+
+/* Bytes consumed so far. */
+uint64_t lz_stream_position(const lz_stream *st);
+
+/* Waits for the stream's work and frees it. */
+int lz_stream_close(lz_stream *st);
+
 /* ---- serving: continuous batching ------------------------------------------------
  * A request loop on a library thread.  Requests are admitted in arrival order
  * while chain slots and the device-memory budget allow; their per-block chain
@@ -260,6 +292,19 @@ int lz_server_stats_get(lz_server *srv, lz_server_stats *out);
 
 /* Stops the thread after the queued requests complete, frees everything. */
 int lz_server_destroy(lz_server *srv);
+
+/* ---- diagnostics of Section 4 (frequency analysis, autocorrelation) -------------
+ * lz_histogram: d_hist (device, 256 uint64, overwritten) receives the count of
+ * each byte value of d_data (device, n bytes); the Shannon entropy
+ * S = -sum p_i log2 p_i follows from it.  Asynchronous on stream. */
+int lz_histogram(lz_ctx *ctx, const uint8_t *d_data, size_t n, uint64_t *d_hist, void *stream);
+
+/* lz_lag_sums: d_sums (device, max_lag + 1 uint64, overwritten) receives the
+ * exact integer sums S_k = sum_{i < n-k} x_i x_{i+k}, k = 0..max_lag
+ * (max_lag <= 16384), from which the autocorrelation of the byte sequence
+ * follows: r_k = (S_k - m (A_k + B_k) + (n-k) m^2) / (S_0 - n m^2), m the mean,
+ * A_k = sum_{i < n-k} x_i, B_k = sum_{i >= k} x_i.  Asynchronous on stream. */
+int lz_lag_sums(lz_ctx *ctx, const uint8_t *d_data, size_t n, uint32_t max_lag, uint64_t *d_sums, void *stream);
 
 /* CLOCK_MONOTONIC now, in ns (the clock of arrival_ns and done_ns). */
 uint64_t lz_now_ns(void);

@@ -85,6 +85,13 @@ SIGNATURES = {
     "lz_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
     "lz_server_destroy": (ctypes.c_int, [vp]),
     "lz_now_ns": (ctypes.c_uint64, []),
+    "lz_histogram": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp, vp]),
+    "lz_lag_sums": (ctypes.c_int, [vp, vp, ctypes.c_size_t, ctypes.c_uint32, vp, vp]),
+    "lz_stream_open": (ctypes.c_int, [vp, ctypes.c_int, u8p, ctypes.c_size_t, ctypes.POINTER(vp)]),
+    "lz_stream_update": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp, vp]),
+    "lz_stream_finish": (ctypes.c_int, [vp, vp, vp, vp]),
+    "lz_stream_position": (ctypes.c_uint64, [vp]),
+    "lz_stream_close": (ctypes.c_int, [vp]),
 }
 
 

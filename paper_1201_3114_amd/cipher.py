@@ -195,6 +195,49 @@ class Batch:
             pass
 
 
+class Stream:
+    """One message of unknown length, encrypted or decrypted chunk by chunk (lz_stream_*)."""
+
+    def __init__(self, ctx: Context, decrypt: bool, pw: bytes):
+        self.ctx = ctx
+        self.decrypt = bool(decrypt)
+        self._h = ctypes.c_void_p()
+        buf, npw = B.pw_buf(pw)
+        check(B.lib.lz_stream_open(ctx.handle, int(decrypt), buf, npw, ctypes.byref(self._h)))
+
+    def update(self, chunk: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        n = chunk.numel()
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=self.ctx.device)
+        if n:
+            check(B.lib.lz_stream_update(self._h, _dev_ptr(chunk), n, _dev_ptr(out), _stream(stream, self.ctx.device)))
+        return out
+
+    def finish(self, tag: torch.Tensor | None = None, status: torch.Tensor | None = None, stream=None):
+        """Encrypt: returns the 24-byte tag tensor.  Decrypt: checks `tag`; raises IntegrityError
+        (or writes `status` asynchronously when given)."""
+        if not self.decrypt:
+            tag = torch.empty(TAG_BYTES, dtype=torch.uint8, device=self.ctx.device) if tag is None else tag
+        st = ctypes.c_void_p(status.data_ptr()) if status is not None else None
+        check(B.lib.lz_stream_finish(self._h, _dev_ptr(tag), st, _stream(stream, self.ctx.device)))
+        return tag
+
+    @property
+    def position(self) -> int:
+        return int(B.lib.lz_stream_position(self._h))
+
+    def close(self):
+        if self._h:
+            B.lib.lz_stream_close(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def packed_offsets(lens, extra: int = 0, align: int = 1):
     """Offsets of messages laid end to end (each of len + extra bytes, aligned)."""
     offs = np.zeros(len(lens), dtype=np.uint64)
@@ -261,6 +304,48 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def histogram(ctx: Context, data: torch.Tensor, stream=None) -> torch.Tensor:
+    """Byte histogram on the device (256 int64 counts) -- Section 4's frequency analysis."""
+    out = torch.empty(256, dtype=torch.int64, device=ctx.device)
+    n = data.numel()
+    check(B.lib.lz_histogram(ctx.handle, _dev_ptr(data) if n else None, n, ctypes.c_void_p(out.data_ptr()),
+                             _stream(stream, ctx.device)))
+    return out
+
+
+def entropy(hist) -> float:
+    """Shannon entropy in bits per byte of a 256-bin histogram."""
+    h = np.asarray(hist.cpu() if hasattr(hist, "cpu") else hist, dtype=np.float64)
+    p = h[h > 0] / h.sum()
+    return float(-(p * np.log2(p)).sum())
+
+
+def lag_sums(ctx: Context, data: torch.Tensor, max_lag: int, stream=None) -> torch.Tensor:
+    """Exact S_k = sum_i x_i x_{i+k}, k = 0..max_lag, on the device (int64)."""
+    out = torch.empty(max_lag + 1, dtype=torch.int64, device=ctx.device)
+    n = data.numel()
+    check(B.lib.lz_lag_sums(ctx.handle, _dev_ptr(data) if n else None, n, max_lag, ctypes.c_void_p(out.data_ptr()),
+                            _stream(stream, ctx.device)))
+    return out
+
+
+def autocorrelation(ctx: Context, data: torch.Tensor, max_lag: int) -> np.ndarray:
+    """r_k of the byte sequence from the device's exact lag sums (Section 4, autocorrelation)."""
+    n = data.numel()
+    S = lag_sums(ctx, data, max_lag).cpu().numpy().astype(object)
+    total = int(histogram(ctx, data).cpu().numpy() @ np.arange(256))
+    head = data[:max_lag].cpu().numpy().astype(np.int64)
+    tail = data[max(n - max_lag, 0):].cpu().numpy().astype(np.int64)
+    m = total / n
+    den = float(S[0]) - n * m * m
+    r = np.empty(max_lag + 1)
+    for k in range(max_lag + 1):
+        A = total - int(tail[len(tail) - k:].sum()) if k else total
+        Bk = total - int(head[:k].sum())
+        r[k] = (float(S[k]) - m * (A + Bk) + (n - k) * m * m) / den
+    return r
 
 
 def now_ns() -> int:

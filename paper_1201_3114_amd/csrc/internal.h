@@ -78,7 +78,7 @@ struct DevInfo {
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, hipStream_t s);
 hipError_t launch_plain(const KernelShape &sh, const lz_key &key, const lz_params &prm, int decrypt,
                         const uint8_t *in, uint8_t *out, uint64_t n, unsigned long long *tag_acc,
-                        hipStream_t s);
+                        hipStream_t s, uint64_t block_base = 0);
 hipError_t launch_plain_finalize(int decrypt, const unsigned long long *tag_acc, const uint8_t *stored_tag,
                                  uint8_t *tag_out, int32_t *status, uint8_t *body, uint64_t n,
                                  hipStream_t s);
@@ -114,6 +114,14 @@ hipError_t launch_tick(const KernelShape &sh, const lz_params &prm, const TickDe
 hipError_t launch_install(ReqDesc *reqs, ChainSlot *slots, const ReqDesc *staged, const uint32_t *meta,
                           const uint32_t *idx, uint32_t n_new, uint32_t block_len, hipStream_t s);
 hipError_t launch_req_zero(const ReqDesc *reqs, const uint32_t *req_ids, uint32_t n, hipStream_t s);
+
+// Streaming: continue (or start) one chain for cnt bytes from/to its checkpoint in *slot.
+hipError_t launch_resume(const lz_key &key, const lz_params &prm, int decrypt, ChainSlot *slot, uint64_t block,
+                         const uint8_t *in, uint8_t *out, uint32_t cnt, int fresh, int complete,
+                         unsigned long long *tag_acc, hipStream_t s);
+hipError_t launch_stream_finish(const ChainSlot *slot, int pending, int empty, const lz_key &key,
+                                unsigned long long *tag_acc, int decrypt, uint8_t *tag, int32_t *status,
+                                hipStream_t s);
 
 size_t lds_bytes(const KernelShape &sh);
 bool shape_valid(const KernelShape &sh, const DevInfo &dev);

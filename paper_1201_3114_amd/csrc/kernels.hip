@@ -321,6 +321,7 @@ struct PlainArgs {
     const uint8_t *in;
     uint8_t *out;
     uint64_t n, nb;
+    uint64_t block_base;  // index of the first block (0 for a whole message)
     unsigned long long *tag_acc;
 };
 
@@ -350,7 +351,7 @@ __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
         cnt[m] = (valid[m] && off < a.n) ? (uint32_t)(a.n - off < a.block_len ? a.n - off : a.block_len) : 0u;
         in[m] = a.in + (valid[m] && off < a.n ? off : 0);
         out[m] = a.out + (valid[m] && off < a.n ? off : 0);
-        init_chain<M>(c, m, r0, ap, mu, om, k, valid[m] ? g : 0, a.decrypt);
+        init_chain<M>(c, m, r0, ap, mu, om, k, a.block_base + (valid[m] ? g : 0), a.decrypt);
         d0[m] = d1[m] = d2[m] = 0;
     }
     wave_run<M, I>(c, w, (int)a.tile, in, out, cnt, a.dt, a.n_it, lane, [&](int m) __attribute__((always_inline)) {
@@ -603,6 +604,90 @@ __global__ __launch_bounds__(256) void tick_kernel(TickArgs a) {
     }
 }
 
+// ---- streaming: one resumable chain ------------------------------------------------------
+
+struct ResumeArgs {
+    double ap[3], r0[3];
+    uint8_t mu[3], om[3], k[3];
+    uint32_t decrypt;
+    double dt;
+    uint32_t n_it, block_len, tile;
+    ChainSlot *slot;
+    uint64_t block;     // block index of the chain
+    const uint8_t *in;
+    uint8_t *out;
+    uint32_t cnt;       // bytes to process now
+    uint32_t fresh;     // 1: start from the block's initial condition, else from *slot
+    uint32_t complete;  // 1: the block ends after these bytes: XOR its digest into tag_acc
+    unsigned long long *tag_acc;
+};
+
+// One wave; lane 0 carries the chain, the other lanes idle (cnt 0, no memory).
+template <int I>
+__global__ __launch_bounds__(64) void resume_kernel(ResumeArgs a) {
+    extern __shared__ char lds[];
+    const int lane = threadIdx.x % WAVE;
+    const WaveLds w = wave_lds<1>(lds, a.tile);
+    Chains<1> c;
+    const double ap[3] = {a.ap[0], a.ap[1], a.ap[2]};
+    const uint8_t mu0[3] = {a.mu[0], a.mu[1], a.mu[2]}, om0[3] = {a.om[0], a.om[1], a.om[2]},
+                  k[3] = {a.k[0], a.k[1], a.k[2]};
+    const bool mine = lane == 0;
+    if (a.fresh || !mine) {
+        const double r0[3] = {a.r0[0], a.r0[1], a.r0[2]};
+        init_chain<1>(c, 0, r0, ap, mu0, om0, k, a.block, a.decrypt);
+    } else {
+        const ChainSlot &s = *a.slot;
+        c.x[0] = s.r[0]; c.y[0] = s.r[1]; c.z[0] = s.r[2];
+        c.a0[0] = s.al[0]; c.a1[0] = s.al[1]; c.a2[0] = s.al[2];
+        c.mu0[0] = s.mu[0]; c.mu1[0] = s.mu[1]; c.mu2[0] = s.mu[2];
+        c.om0[0] = s.om[0]; c.om1[0] = s.om[1]; c.om2[0] = s.om[2];
+        c.ap0[0] = ap[0]; c.ap1[0] = ap[1]; c.ap2[0] = ap[2];
+        c.k0[0] = k[0]; c.k1[0] = k[1]; c.k2[0] = k[2];
+        c.dec[0] = a.decrypt;
+    }
+    const uint8_t *const in[1] = {mine ? a.in : nullptr};
+    uint8_t *const out[1] = {mine ? a.out : nullptr};
+    const uint32_t cnt[1] = {mine ? a.cnt : 0u};
+    wave_run<1, I>(c, w, a.tile, in, out, cnt, a.dt, a.n_it, lane, [&](int) __attribute__((always_inline)) {
+        if (!mine) return;
+        ChainSlot &s = *a.slot;
+        s.r[0] = c.x[0]; s.r[1] = c.y[0]; s.r[2] = c.z[0];
+        s.al[0] = c.a0[0]; s.al[1] = c.a1[0]; s.al[2] = c.a2[0];
+        s.mu[0] = (uint8_t)c.mu0[0]; s.mu[1] = (uint8_t)c.mu1[0]; s.mu[2] = (uint8_t)c.mu2[0];
+        s.om[0] = (uint8_t)c.om0[0]; s.om[1] = (uint8_t)c.om1[0]; s.om[2] = (uint8_t)c.om2[0];
+        if (a.complete) {
+            atomicXor(&a.tag_acc[0], digest_word(c.x[0]));
+            atomicXor(&a.tag_acc[1], digest_word(c.y[0]));
+            atomicXor(&a.tag_acc[2], digest_word(c.z[0]));
+        }
+    });
+}
+
+// End of a stream: fold in the pending partial block (or, for an empty message, block 0's
+// initial state), then write the tag (encrypt) or compare it (decrypt).
+__global__ void stream_finish_kernel(const ChainSlot *slot, int pending, int empty, double r00, double r01, double r02,
+                                     unsigned long long *tag_acc, int decrypt, uint8_t *tag, int32_t *status) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    unsigned long long t[3] = {tag_acc[0], tag_acc[1], tag_acc[2]};
+    if (pending) {
+        t[0] ^= digest_word(slot->r[0]);
+        t[1] ^= digest_word(slot->r[1]);
+        t[2] ^= digest_word(slot->r[2]);
+    } else if (empty) {
+        t[0] ^= digest_word(r00);
+        t[1] ^= digest_word(r01);
+        t[2] ^= digest_word(r02);
+    }
+    if (!decrypt) {
+        for (int q = 0; q < LZ_TAG_BYTES; ++q) tag[q] = (uint8_t)(t[q / 8] >> (8 * (q % 8)));
+        return;
+    }
+    bool ok = true;
+    for (int q = 0; q < LZ_TAG_BYTES; ++q) ok = ok && tag[q] == (uint8_t)(t[q / 8] >> (8 * (q % 8)));
+    *status = ok ? LZ_OK : LZ_E_INTEGRITY;
+}
+
 // Zeroes the body of each listed request (failed decryptions), one workgroup each.
 __global__ void req_zero_kernel(const ReqDesc *reqs, const uint32_t *ids, uint32_t n) {
     if (blockIdx.x >= n) return;
@@ -670,7 +755,8 @@ hipError_t launch_fill_u64(unsigned long long *p, size_t n, hipStream_t s) {
 }
 
 hipError_t launch_plain(const KernelShape &sh, const lz_key &key, const lz_params &prm, int decrypt,
-                        const uint8_t *in, uint8_t *out, uint64_t n, unsigned long long *tag_acc, hipStream_t s) {
+                        const uint8_t *in, uint8_t *out, uint64_t n, unsigned long long *tag_acc, hipStream_t s,
+                        uint64_t block_base) {
     PlainArgs a;
     for (int j = 0; j < 3; ++j) {
         a.ap[j] = key.a_prime[j];
@@ -688,6 +774,7 @@ hipError_t launch_plain(const KernelShape &sh, const lz_key &key, const lz_param
     a.out = out;
     a.n = n;
     a.nb = n == 0 ? 1 : (n + prm.block_len - 1) / prm.block_len;
+    a.block_base = block_base;
     a.tag_acc = tag_acc;
     const uint64_t per_wg = (uint64_t)sh.wg * sh.m;
     const uint64_t grid = (a.nb + per_wg - 1) / per_wg;
@@ -757,6 +844,46 @@ hipError_t launch_tick(const KernelShape &sh, const lz_params &prm, const TickDe
         hipLaunchKernelGGL((tick_kernel<M, I>), dim3((unsigned)grid), dim3(sh.wg), lds, s, a);
         return hipGetLastError();
     });
+}
+
+hipError_t launch_resume(const lz_key &key, const lz_params &prm, int decrypt, ChainSlot *slot, uint64_t block,
+                         const uint8_t *in, uint8_t *out, uint32_t cnt, int fresh, int complete,
+                         unsigned long long *tag_acc, hipStream_t s) {
+    ResumeArgs a;
+    for (int j = 0; j < 3; ++j) {
+        a.ap[j] = key.a_prime[j];
+        a.r0[j] = key.r0[j];
+        a.mu[j] = key.mu[j];
+        a.om[j] = key.omega[j];
+        a.k[j] = key.k[j];
+    }
+    a.decrypt = (uint32_t)decrypt;
+    a.dt = prm.dt;
+    a.n_it = prm.n_it;
+    a.block_len = prm.block_len;
+    a.tile = 64;
+    a.slot = slot;
+    a.block = block;
+    a.in = in;
+    a.out = out;
+    a.cnt = cnt;
+    a.fresh = (uint32_t)fresh;
+    a.complete = (uint32_t)complete;
+    a.tag_acc = tag_acc;
+    const size_t lds = wave_lds_bytes(1, 64);
+    return dispatch(1, prm.integrator, [&](auto, auto ic) {
+        constexpr int I = decltype(ic)::value;
+        hipLaunchKernelGGL((resume_kernel<I>), dim3(1), dim3(WAVE), lds, s, a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_stream_finish(const ChainSlot *slot, int pending, int empty, const lz_key &key,
+                                unsigned long long *tag_acc, int decrypt, uint8_t *tag, int32_t *status,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(stream_finish_kernel, dim3(1), dim3(64), 0, s, slot, pending, empty, key.r0[0], key.r0[1],
+                       key.r0[2], tag_acc, decrypt, tag, status);
+    return hipGetLastError();
 }
 
 hipError_t launch_install(ReqDesc *reqs, ChainSlot *slots, const ReqDesc *staged, const uint32_t *meta,

@@ -107,27 +107,35 @@ uint64_t out_len(const Request &r) { return r.decrypt ? r.n : r.n + LZ_TAG_BYTES
 
 }  // namespace
 
+// Buffers of one tick.  Two of them alternate so that the host prepares and
+// queues tick k+1 while tick k runs, and reads tick k's completions while
+// tick k+1 runs.
+struct TickSlot {
+    uint32_t *h_list = nullptr, *d_list = nullptr;  // active chain slots
+    uint32_t *h_done = nullptr, *d_done = nullptr;  // [0] count, [1] pad, [2..] completed requests
+    ReqDesc *h_req = nullptr, *d_req = nullptr;     // records of the requests admitted for this tick
+    uint32_t *h_meta = nullptr, *d_meta = nullptr;  // 3 words per admitted request
+    uint32_t *h_idx = nullptr, *d_idx = nullptr;    // chain slots of the admitted requests
+    hipEvent_t ev_start = nullptr, ev_end = nullptr;
+    bool in_flight = false;
+    uint64_t bytes = 0;
+};
+
 struct lz_server {
     lz_ctx *ctx;
     lz_server_config cfg;
     KernelShape shape;
-    uint32_t max_chains, max_reqs;
+    uint32_t max_chains, max_reqs, max_new;
     // device memory
     uint8_t *arena_mem = nullptr;
     ChainSlot *slots = nullptr;
     ReqDesc *reqs = nullptr;
-    uint32_t *d_list = nullptr;
-    uint32_t *d_done = nullptr;  // [0] = count, [1..] = queue
     uint32_t *d_zero_ids = nullptr;
-    ReqDesc *d_stage_reqs = nullptr;
-    uint32_t *d_stage_meta = nullptr;  // per new request: req_slot, nb, index offset
-    uint32_t *d_stage_idx = nullptr;   // chain slots of the new requests
-    // pinned staging
-    uint32_t *h_list = nullptr;
-    uint32_t *h_done = nullptr;
     uint32_t *h_zero_ids = nullptr;
-    hipStream_t stream = nullptr;
-    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    TickSlot ts[2];
+    int cur = 0;
+    hipStream_t stream = nullptr;       // installs, input copies, ticks
+    hipStream_t copy_stream = nullptr;  // completion reads, zeroing, output copies
     Arena arena;
     // host bookkeeping (server thread only)
     std::vector<uint32_t> free_slots;
@@ -166,24 +174,27 @@ void finish(lz_server *s, Request *r, int32_t status, uint64_t done_ns) {
     delete r;
 }
 
-// Admits waiting requests in FIFO order while slots and memory allow.
-int admit(lz_server *s, std::vector<Request *> &admitted) {
+// Admits waiting requests in FIFO order while slots, memory and staging room allow.
+void admit(lz_server *s, std::vector<Request *> &admitted) {
     const uint32_t B = s->ctx->prm.block_len;
-    while (!s->waiting.empty()) {
+    uint64_t staged_chains = 0;
+    while (!s->waiting.empty() && admitted.size() < s->max_new) {
         Request *r = s->waiting.front();
-        const uint32_t nb = (uint32_t)(r->n == 0 ? 1 : (r->n + B - 1) / B);
+        const uint64_t nb64 = r->n == 0 ? 1 : (r->n + B - 1) / B;
         const uint64_t bytes = ((in_len(*r) + 255) / 256 + (out_len(*r) + 255) / 256) * 256;
-        if (nb > s->max_chains || bytes > s->arena.size()) {  // can never fit
+        if (nb64 > s->max_chains || bytes > s->arena.size()) {  // can never fit
             s->waiting.pop_front();
             finish(s, r, LZ_E_NOMEM, lz_now_ns());
             continue;
         }
-        if (s->free_reqs.empty() || s->free_slots.size() < nb) break;
+        const uint32_t nb = (uint32_t)nb64;
+        if (s->free_reqs.empty() || s->free_slots.size() < nb || staged_chains + nb > s->max_chains) break;
         uint64_t off;
         if (!s->arena.alloc(bytes, off)) break;
         s->waiting.pop_front();
         r->slots.assign(s->free_slots.end() - nb, s->free_slots.end());
         s->free_slots.resize(s->free_slots.size() - nb);
+        staged_chains += nb;
         r->nb = nb;
         r->arena_off = off;
         r->arena_bytes = bytes;
@@ -193,7 +204,7 @@ int admit(lz_server *s, std::vector<Request *> &admitted) {
         r->admit_ns = lz_now_ns();
         const uint32_t T = s->cfg.tick_bytes;
         const uint64_t tail = r->n == 0 ? 0 : r->n - (uint64_t)(nb - 1) * B;
-        r->ticks_full = nb > 1 ? (B + T - 1) / T : 0;
+        r->ticks_full = nb > 1 ? (uint32_t)((B + (uint64_t)T - 1) / T) : 0;
         r->ticks_tail = tail == 0 ? 1 : (uint32_t)((tail + T - 1) / T);
         r->ticks_run = 0;
         admitted.push_back(r);
@@ -201,117 +212,44 @@ int admit(lz_server *s, std::vector<Request *> &admitted) {
     }
     const uint64_t inuse = s->arena.used() + s->hbm_fixed;
     if (inuse > s->stats.peak_hbm) s->stats.peak_hbm = inuse;
-    return LZ_OK;
 }
 
-int server_tick(lz_server *s) {
-    hipStream_t st = s->stream;
-    std::vector<Request *> admitted;
-    admit(s, admitted);
-    if (!admitted.empty()) {
-        const size_t k = admitted.size();
-        std::vector<ReqDesc> staged(k);
-        std::vector<uint32_t> meta(3 * k), idx;
-        for (size_t i = 0; i < k; ++i) {
-            Request *r = admitted[i];
-            ReqDesc &d = staged[i];
-            std::memset(&d, 0, sizeof d);
-            for (int j = 0; j < 3; ++j) {
-                d.m.ap[j] = r->key.a_prime[j];
-                d.m.r0[j] = r->key.r0[j];
-                d.m.mu[j] = r->key.mu[j];
-                d.m.om[j] = r->key.omega[j];
-                d.m.k[j] = r->key.k[j];
-            }
-            d.m.decrypt = (uint8_t)r->decrypt;
-            d.m.nb = r->nb;
-            d.m.n = r->n;
-            uint8_t *in = s->arena_mem + r->arena_off;
-            uint8_t *out = in + (in_len(*r) + 255) / 256 * 256;
-            d.m.in = in;
-            d.m.out = out;
-            d.remaining = r->nb;
-            d.status = LZ_OK;
-            d.stored_tag = in + r->n;
-            meta[3 * i] = r->req_slot;
-            meta[3 * i + 1] = r->nb;
-            meta[3 * i + 2] = (uint32_t)idx.size();
-            idx.insert(idx.end(), r->slots.begin(), r->slots.end());
-            if (in_len(*r)) LZ_HIP(hipMemcpyAsync(in, r->src, in_len(*r), hipMemcpyDefault, st));
-        }
-        // install the new request records and their fresh chain slots on the device
-        LZ_HIP(hipMemcpyAsync(s->d_stage_reqs, staged.data(), k * sizeof(ReqDesc), hipMemcpyHostToDevice, st));
-        LZ_HIP(hipMemcpyAsync(s->d_stage_meta, meta.data(), meta.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-        LZ_HIP(hipMemcpyAsync(s->d_stage_idx, idx.data(), idx.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-        LZ_HIP(launch_install(s->reqs, s->slots, s->d_stage_reqs, s->d_stage_meta, s->d_stage_idx, (uint32_t)k,
-                              s->ctx->prm.block_len, st));
-        for (Request *r : admitted) {
-            r->active_idx = s->active.size();
-            s->active.push_back(r);
-        }
-        LZ_HIP(hipStreamSynchronize(st));  // pageable sources above must be consumed before they go away
-    }
-    if (s->active.empty()) return LZ_OK;
-    // active chain list: full chains until they finish, tail chain until it finishes
-    const uint32_t T = s->cfg.tick_bytes, B = s->ctx->prm.block_len;
-    uint32_t n_list = 0;
-    uint64_t tick_bytes = 0;
-    for (Request *r : s->active) {
-        const uint32_t t = r->ticks_run;
-        if (t < r->ticks_full) {
-            for (uint32_t b = 0; b + 1 < r->nb; ++b) s->h_list[n_list++] = r->slots[b];
-            tick_bytes += (uint64_t)(r->nb - 1) * std::min<uint64_t>(T, B - (uint64_t)t * T);
-        }
-        if (t < r->ticks_tail) {
-            s->h_list[n_list++] = r->slots[r->nb - 1];
-            const uint64_t tail = r->n - (uint64_t)(r->nb - 1) * B;
-            const uint64_t done = (uint64_t)t * T;
-            tick_bytes += tail > done ? std::min<uint64_t>(T, tail - done) : 0;
-        }
-    }
-    LZ_HIP(hipMemcpyAsync(s->d_list, s->h_list, n_list * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-    LZ_HIP(launch_fill_u64(reinterpret_cast<unsigned long long *>(s->d_done), 1, st));
-    TickDev t;
-    t.slots = s->slots;
-    t.reqs = s->reqs;
-    t.list = s->d_list;
-    t.n_list = n_list;
-    t.tick_bytes = s->cfg.tick_bytes;
-    t.done_count = s->d_done;
-    t.done_queue = s->d_done + 2;
-    LZ_HIP(hipEventRecord(s->ev_a, st));
-    LZ_HIP(launch_tick(s->shape, s->ctx->prm, t, st));
-    LZ_HIP(hipEventRecord(s->ev_b, st));
-    LZ_HIP(hipMemcpyAsync(s->h_done, s->d_done, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    LZ_HIP(hipStreamSynchronize(st));
+uint8_t *req_in(lz_server *s, const Request *r) { return s->arena_mem + r->arena_off; }
+uint8_t *req_out(lz_server *s, const Request *r) { return req_in(s, r) + (in_len(*r) + 255) / 256 * 256; }
+
+// Reads a finished tick's completions, zeroes failed decryptions, copies the
+// outputs out, frees the requests' slots and memory and reports them.
+int complete_tick(lz_server *s, TickSlot &t) {
+    hipStream_t cs = s->copy_stream;
+    LZ_HIP(hipEventSynchronize(t.ev_end));
     float ms = 0;
-    hipEventElapsedTime(&ms, s->ev_a, s->ev_b);
-    s->stats.busy_ms += ms;
+    if (hipEventElapsedTime(&ms, t.ev_start, t.ev_end) == hipSuccess) s->stats.busy_ms += ms;
     s->stats.ticks++;
-    s->stats.chain_bytes += tick_bytes;
-    for (Request *r : s->active) r->ticks_run++;
-    const uint32_t nd = s->h_done[0];
+    s->stats.chain_bytes += t.bytes;
+    t.in_flight = false;
+    LZ_HIP(hipMemcpyAsync(t.h_done, t.d_done, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, cs));
+    LZ_HIP(hipStreamSynchronize(cs));
+    const uint32_t nd = t.h_done[0];
     if (nd == 0) return LZ_OK;
-    LZ_HIP(hipMemcpyAsync(s->h_done + 2, s->d_done + 2, nd * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    LZ_HIP(hipStreamSynchronize(st));
+    LZ_HIP(hipMemcpyAsync(t.h_done + 2, t.d_done + 2, nd * sizeof(uint32_t), hipMemcpyDeviceToHost, cs));
+    LZ_HIP(hipStreamSynchronize(cs));
     uint32_t nz = 0;
     for (uint32_t i = 0; i < nd; ++i)
-        if (s->h_done[2 + i] & 1u) s->h_zero_ids[nz++] = s->h_done[2 + i] >> 1;
+        if (t.h_done[2 + i] & 1u) s->h_zero_ids[nz++] = t.h_done[2 + i] >> 1;
     if (nz) {
-        LZ_HIP(hipMemcpyAsync(s->d_zero_ids, s->h_zero_ids, nz * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-        LZ_HIP(launch_req_zero(s->reqs, s->d_zero_ids, nz, st));
+        LZ_HIP(hipMemcpyAsync(s->d_zero_ids, s->h_zero_ids, nz * sizeof(uint32_t), hipMemcpyHostToDevice, cs));
+        LZ_HIP(launch_req_zero(s->reqs, s->d_zero_ids, nz, cs));
     }
     std::vector<std::pair<Request *, int32_t>> fin;
+    fin.reserve(nd);
     for (uint32_t i = 0; i < nd; ++i) {
-        const uint32_t slot = s->h_done[2 + i] >> 1;
-        Request *r = s->by_slot[slot];
-        const int32_t status = (s->h_done[2 + i] & 1u) ? LZ_E_INTEGRITY : LZ_OK;
-        uint8_t *in = s->arena_mem + r->arena_off;
-        uint8_t *out = in + (in_len(*r) + 255) / 256 * 256;
-        if (out_len(*r)) LZ_HIP(hipMemcpyAsync(r->dst, out, out_len(*r), hipMemcpyDefault, st));
+        Request *r = s->by_slot[t.h_done[2 + i] >> 1];
+        if (!r) return fail(LZ_E_HIP, "server: completion for an empty request slot");
+        const int32_t status = (t.h_done[2 + i] & 1u) ? LZ_E_INTEGRITY : LZ_OK;
+        if (out_len(*r)) LZ_HIP(hipMemcpyAsync(r->dst, req_out(s, r), out_len(*r), hipMemcpyDefault, cs));
         fin.emplace_back(r, status);
     }
-    LZ_HIP(hipStreamSynchronize(st));
+    LZ_HIP(hipStreamSynchronize(cs));
     const uint64_t now = lz_now_ns();
     for (auto &f : fin) {
         Request *r = f.first;
@@ -328,6 +266,99 @@ int server_tick(lz_server *s) {
     return LZ_OK;
 }
 
+// One scheduling step: admit into the free tick slot, queue its tick, then
+// process the other slot's (previous) tick while the new one runs.
+int server_step(lz_server *s) {
+    hipStream_t st = s->stream;
+    TickSlot &t = s->ts[s->cur];
+    if (t.in_flight)
+        if (int rc = complete_tick(s, t)) return rc;
+    std::vector<Request *> admitted;
+    admit(s, admitted);
+    if (!admitted.empty()) {
+        const size_t k = admitted.size();
+        uint32_t n_idx = 0;
+        for (size_t i = 0; i < k; ++i) {
+            Request *r = admitted[i];
+            ReqDesc &d = t.h_req[i];
+            std::memset(&d, 0, sizeof d);
+            for (int j = 0; j < 3; ++j) {
+                d.m.ap[j] = r->key.a_prime[j];
+                d.m.r0[j] = r->key.r0[j];
+                d.m.mu[j] = r->key.mu[j];
+                d.m.om[j] = r->key.omega[j];
+                d.m.k[j] = r->key.k[j];
+            }
+            d.m.decrypt = (uint8_t)r->decrypt;
+            d.m.nb = r->nb;
+            d.m.n = r->n;
+            d.m.in = req_in(s, r);
+            d.m.out = req_out(s, r);
+            d.remaining = r->nb;
+            d.status = LZ_OK;
+            d.stored_tag = req_in(s, r) + r->n;
+            t.h_meta[3 * i] = r->req_slot;
+            t.h_meta[3 * i + 1] = r->nb;
+            t.h_meta[3 * i + 2] = n_idx;
+            std::memcpy(t.h_idx + n_idx, r->slots.data(), r->nb * sizeof(uint32_t));
+            n_idx += r->nb;
+            if (in_len(*r)) LZ_HIP(hipMemcpyAsync(req_in(s, r), r->src, in_len(*r), hipMemcpyDefault, st));
+            r->active_idx = s->active.size();
+            s->active.push_back(r);
+        }
+        LZ_HIP(hipMemcpyAsync(t.d_req, t.h_req, k * sizeof(ReqDesc), hipMemcpyHostToDevice, st));
+        LZ_HIP(hipMemcpyAsync(t.d_meta, t.h_meta, 3 * k * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        LZ_HIP(hipMemcpyAsync(t.d_idx, t.h_idx, n_idx * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        LZ_HIP(launch_install(s->reqs, s->slots, t.d_req, t.d_meta, t.d_idx, (uint32_t)k, s->ctx->prm.block_len, st));
+    }
+    // the chains that still have bytes to process: each request's full chains until they end,
+    // its last chain until it ends (the tick count of each is known at admission)
+    const uint32_t T = s->cfg.tick_bytes, B = s->ctx->prm.block_len;
+    uint32_t n_list = 0;
+    uint64_t tick_bytes = 0;
+    for (Request *r : s->active) {
+        const uint32_t tr = r->ticks_run;
+        if (tr < r->ticks_full) {
+            std::memcpy(t.h_list + n_list, r->slots.data(), (r->nb - 1) * sizeof(uint32_t));
+            n_list += r->nb - 1;
+            tick_bytes += (uint64_t)(r->nb - 1) * std::min<uint64_t>(T, (uint64_t)B - (uint64_t)tr * T);
+        }
+        if (tr < r->ticks_tail) {
+            t.h_list[n_list++] = r->slots[r->nb - 1];
+            const uint64_t tail = r->n - (uint64_t)(r->nb - 1) * B;
+            const uint64_t done = (uint64_t)tr * T;
+            tick_bytes += tail > done ? std::min<uint64_t>(T, tail - done) : 0;
+        }
+        if (tr < r->ticks_full || tr < r->ticks_tail) r->ticks_run++;
+    }
+    if (n_list) {
+        LZ_HIP(hipMemcpyAsync(t.d_list, t.h_list, n_list * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        LZ_HIP(launch_fill_u64(reinterpret_cast<unsigned long long *>(t.d_done), 1, st));
+        TickDev td;
+        td.slots = s->slots;
+        td.reqs = s->reqs;
+        td.list = t.d_list;
+        td.n_list = n_list;
+        td.tick_bytes = T;
+        td.done_count = t.d_done;
+        td.done_queue = t.d_done + 2;
+        LZ_HIP(hipEventRecord(t.ev_start, st));
+        LZ_HIP(launch_tick(s->shape, s->ctx->prm, td, st));
+        LZ_HIP(hipEventRecord(t.ev_end, st));
+        t.bytes = tick_bytes;
+        t.in_flight = true;
+    }
+    s->cur ^= 1;
+    TickSlot &prev = s->ts[s->cur];
+    if (prev.in_flight)
+        if (int rc = complete_tick(s, prev)) return rc;
+    if (!n_list && !prev.in_flight && !s->ts[s->cur ^ 1].in_flight && !s->active.empty())
+        return fail(LZ_E_HIP, "server: active requests without pending work");
+    return LZ_OK;
+}
+
+bool busy(lz_server *s) { return !s->waiting.empty() || !s->active.empty() || s->ts[0].in_flight || s->ts[1].in_flight; }
+
 void server_loop(lz_server *s) {
     hipSetDevice(s->ctx->device);
     for (;;) {
@@ -339,7 +370,7 @@ void server_loop(lz_server *s) {
                     s->waiting.push_back(s->pending.top());
                     s->pending.pop();
                 }
-                if (!s->waiting.empty() || !s->active.empty()) break;
+                if (busy(s)) break;
                 if (s->stop && s->pending.empty()) return;
                 if (s->pending.empty()) {
                     s->cv_submit.wait(g);
@@ -349,7 +380,7 @@ void server_loop(lz_server *s) {
                 }
             }
         }
-        if (int rc = server_tick(s)) {
+        if (int rc = server_step(s)) {
             std::lock_guard<std::mutex> g(s->mu);
             s->error = rc;
             s->stop = true;
@@ -363,21 +394,28 @@ void server_free(lz_server *s) {
     if (!s) return;
     hipSetDevice(s->ctx->device);
     if (s->stream) hipStreamSynchronize(s->stream);
+    if (s->copy_stream) hipStreamSynchronize(s->copy_stream);
     hipFree(s->arena_mem);
     hipFree(s->slots);
     hipFree(s->reqs);
-    hipFree(s->d_list);
-    hipFree(s->d_done);
     hipFree(s->d_zero_ids);
-    hipFree(s->d_stage_reqs);
-    hipFree(s->d_stage_meta);
-    hipFree(s->d_stage_idx);
-    hipHostFree(s->h_list);
-    hipHostFree(s->h_done);
     hipHostFree(s->h_zero_ids);
-    if (s->ev_a) hipEventDestroy(s->ev_a);
-    if (s->ev_b) hipEventDestroy(s->ev_b);
+    for (TickSlot &t : s->ts) {
+        hipFree(t.d_list);
+        hipFree(t.d_done);
+        hipFree(t.d_req);
+        hipFree(t.d_meta);
+        hipFree(t.d_idx);
+        hipHostFree(t.h_list);
+        hipHostFree(t.h_done);
+        hipHostFree(t.h_req);
+        hipHostFree(t.h_meta);
+        hipHostFree(t.h_idx);
+        if (t.ev_start) hipEventDestroy(t.ev_start);
+        if (t.ev_end) hipEventDestroy(t.ev_end);
+    }
     if (s->stream) hipStreamDestroy(s->stream);
+    if (s->copy_stream) hipStreamDestroy(s->copy_stream);
     while (!s->pending.empty()) {
         delete s->pending.top();
         s->pending.pop();
@@ -405,13 +443,17 @@ extern "C" int lz_server_create(lz_ctx *c, const lz_server_config *cfg, lz_serve
     }
     s->max_chains = cfg->max_chains ? cfg->max_chains : (uint32_t)c->dev.cus * 4 * 4 * 64;
     s->max_reqs = s->max_chains;
+    s->max_new = std::min<uint32_t>(s->max_reqs, 32768);
     int tile = 16;
     while (tile < (int)s->cfg.tick_bytes && tile < 128) tile *= 2;
     s->shape = KernelShape{1, 256, tile, 4};
     if (!shape_valid(s->shape, c->dev)) s->shape = KernelShape{1, 64, 16, 4};
-    // fixed device memory: chain slots, request records, lists and staging
-    const uint64_t fixed = (uint64_t)s->max_chains * sizeof(ChainSlot) + (uint64_t)s->max_reqs * sizeof(ReqDesc) * 2 +
-                           (uint64_t)s->max_chains * 4 * 2 + (uint64_t)s->max_reqs * 4 * 5 + (1u << 20);
+    // fixed device memory: chain slots, request records, and per tick slot the list, the
+    // completion queue and the staging of admitted requests
+    const uint64_t per_tick = (uint64_t)s->max_chains * 4 * 2 + ((uint64_t)s->max_reqs + 2) * 4 +
+                              (uint64_t)s->max_new * (sizeof(ReqDesc) + 12);
+    const uint64_t fixed = (uint64_t)s->max_chains * sizeof(ChainSlot) + (uint64_t)s->max_reqs * sizeof(ReqDesc) +
+                           (uint64_t)s->max_reqs * 4 + 2 * per_tick + (1u << 20);
     if (cfg->hbm_budget <= fixed + 4096) {
         delete s;
         return fail(LZ_E_INVAL, "hbm_budget too small for the chain slots");
@@ -421,18 +463,26 @@ extern "C" int lz_server_create(lz_ctx *c, const lz_server_config *cfg, lz_serve
     hipError_t e = hipMalloc(&s->arena_mem, arena_bytes);
     if (e == hipSuccess) e = hipMalloc(&s->slots, (size_t)s->max_chains * sizeof(ChainSlot));
     if (e == hipSuccess) e = hipMalloc(&s->reqs, (size_t)s->max_reqs * sizeof(ReqDesc));
-    if (e == hipSuccess) e = hipMalloc(&s->d_list, (size_t)s->max_chains * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc(&s->d_done, ((size_t)s->max_reqs + 2) * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&s->d_zero_ids, (size_t)s->max_reqs * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc(&s->d_stage_reqs, (size_t)s->max_reqs * sizeof(ReqDesc));
-    if (e == hipSuccess) e = hipMalloc(&s->d_stage_meta, 3 * (size_t)s->max_reqs * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc(&s->d_stage_idx, (size_t)s->max_chains * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipHostMalloc(&s->h_list, (size_t)s->max_chains * sizeof(uint32_t), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc(&s->h_done, ((size_t)s->max_reqs + 2) * sizeof(uint32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc(&s->h_zero_ids, (size_t)s->max_reqs * sizeof(uint32_t), hipHostMallocDefault);
+    for (TickSlot &t : s->ts) {
+        if (e == hipSuccess) e = hipMalloc(&t.d_list, (size_t)s->max_chains * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&t.d_done, ((size_t)s->max_reqs + 2) * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&t.d_req, (size_t)s->max_new * sizeof(ReqDesc));
+        if (e == hipSuccess) e = hipMalloc(&t.d_meta, 3 * (size_t)s->max_new * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&t.d_idx, (size_t)s->max_chains * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipHostMalloc(&t.h_list, (size_t)s->max_chains * sizeof(uint32_t), hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc(&t.h_done, ((size_t)s->max_reqs + 2) * sizeof(uint32_t), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc(&t.h_req, (size_t)s->max_new * sizeof(ReqDesc), hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc(&t.h_meta, 3 * (size_t)s->max_new * sizeof(uint32_t), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc(&t.h_idx, (size_t)s->max_chains * sizeof(uint32_t), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreate(&t.ev_start);
+        if (e == hipSuccess) e = hipEventCreate(&t.ev_end);
+    }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreate(&s->ev_a);
-    if (e == hipSuccess) e = hipEventCreate(&s->ev_b);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         int rc = hip_fail(e, "server allocation");
         server_free(s);

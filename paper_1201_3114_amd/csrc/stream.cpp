@@ -1,0 +1,154 @@
+// Streaming (resumable) encryption and decryption of one message whose length
+// is not known in advance.  The message is the concatenation of the update
+// chunks; the output and the final tag equal those of the one-shot path.
+// Each chunk is cut at block boundaries of the parallel version (Section 5):
+// the pending partial block continues from its device-resident checkpoint
+// (r, alpha, mu, Omega), the full blocks run as one plain launch at the right
+// block index, and the remainder starts the next partial block.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using namespace lz;
+
+struct lz_stream {
+    lz_ctx *ctx;
+    int decrypt;
+    lz_key key;
+    uint64_t pos;        // bytes consumed so far
+    bool finished;
+    void *dmem;          // ChainSlot, then 3 tag words, then the status word
+    ChainSlot *slot;
+    unsigned long long *tag;
+    int32_t *status;
+    int32_t *h_status;   // pinned
+    hipEvent_t ev;
+    hipStream_t last;
+    bool has_last;
+};
+
+namespace {
+
+void stream_free(lz_stream *st) {
+    if (!st) return;
+    hipSetDevice(st->ctx->device);
+    if (st->has_last) hipEventSynchronize(st->ev);
+    if (st->dmem) hipFree(st->dmem);
+    if (st->h_status) hipHostFree(st->h_status);
+    if (st->ev) hipEventDestroy(st->ev);
+    delete st;
+}
+
+int stream_order(lz_stream *st, hipStream_t s) {
+    if (st->has_last && st->last != s) LZ_HIP(hipStreamWaitEvent(s, st->ev, 0));
+    return LZ_OK;
+}
+
+int stream_record(lz_stream *st, hipStream_t s) {
+    LZ_HIP(hipEventRecord(st->ev, s));
+    st->last = s;
+    st->has_last = true;
+    return LZ_OK;
+}
+
+}  // namespace
+
+extern "C" int lz_stream_open(lz_ctx *c, int decrypt, const uint8_t *pw, size_t n_pw, lz_stream **out) {
+    if (!out) return fail(LZ_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!c || !pw) return fail(LZ_E_INVAL, "NULL argument");
+    LZ_HIP(hipSetDevice(c->device));
+    lz_stream *st = new (std::nothrow) lz_stream();
+    if (!st) return fail(LZ_E_NOMEM, "host allocation failed");
+    st->ctx = c;
+    st->decrypt = decrypt ? 1 : 0;
+    if (int rc = lz_key_setup(pw, n_pw, &c->prm, &st->key)) {
+        delete st;
+        return rc;
+    }
+    const size_t bytes = sizeof(ChainSlot) + 4 * sizeof(unsigned long long) + sizeof(int32_t);
+    hipError_t e = hipMalloc(&st->dmem, bytes);
+    if (e == hipSuccess) e = hipMemset(st->dmem, 0, bytes);
+    if (e == hipSuccess) e = hipHostMalloc(&st->h_status, sizeof(int32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        int rc = hip_fail(e, "stream allocation");
+        stream_free(st);
+        return rc;
+    }
+    char *base = static_cast<char *>(st->dmem);
+    st->slot = reinterpret_cast<ChainSlot *>(base);
+    st->tag = reinterpret_cast<unsigned long long *>(base + sizeof(ChainSlot));
+    st->status = reinterpret_cast<int32_t *>(base + sizeof(ChainSlot) + 4 * sizeof(unsigned long long));
+    *out = st;
+    return LZ_OK;
+}
+
+extern "C" int lz_stream_update(lz_stream *st, const uint8_t *d_in, size_t n, uint8_t *d_out, void *stream) {
+    if (!st) return fail(LZ_E_INVAL, "stream is NULL");
+    if (st->finished) return fail(LZ_E_INVAL, "stream already finished");
+    if (n == 0) return LZ_OK;
+    if (!d_in || !d_out) return fail(LZ_E_INVAL, "NULL buffer");
+    if (st->pos + n > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+    lz_ctx *c = st->ctx;
+    hipStream_t s = (hipStream_t)stream;
+    LZ_HIP(hipSetDevice(c->device));
+    if (int rc = stream_order(st, s)) return rc;
+    const uint64_t B = c->prm.block_len;
+    uint64_t off = 0;
+    // head: continue the pending partial block
+    const uint64_t r = st->pos % B;
+    if (r != 0) {
+        const uint64_t h = n < B - r ? n : B - r;
+        LZ_HIP(launch_resume(st->key, c->prm, st->decrypt, st->slot, st->pos / B, d_in, d_out, (uint32_t)h, 0,
+                             r + h == B, st->tag, s));
+        off += h;
+        st->pos += h;
+    }
+    // body: whole blocks in one plain launch starting at block pos / B
+    const uint64_t full = (n - off) / B;
+    if (full > 0) {
+        LZ_HIP(launch_plain(c->shape, st->key, c->prm, st->decrypt, d_in + off, d_out + off, full * B, st->tag, s,
+                            st->pos / B));
+        off += full * B;
+        st->pos += full * B;
+    }
+    // tail: start the next partial block and keep its checkpoint
+    const uint64_t rem = n - off;
+    if (rem > 0) {
+        LZ_HIP(launch_resume(st->key, c->prm, st->decrypt, st->slot, st->pos / B, d_in + off, d_out + off,
+                             (uint32_t)rem, 1, 0, st->tag, s));
+        st->pos += rem;
+    }
+    return stream_record(st, s);
+}
+
+extern "C" int lz_stream_finish(lz_stream *st, uint8_t *d_tag, int32_t *d_status, void *stream) {
+    if (!st || !d_tag) return fail(LZ_E_INVAL, "NULL argument");
+    if (st->finished) return fail(LZ_E_INVAL, "stream already finished");
+    lz_ctx *c = st->ctx;
+    hipStream_t s = (hipStream_t)stream;
+    LZ_HIP(hipSetDevice(c->device));
+    if (int rc = stream_order(st, s)) return rc;
+    const int pending = st->pos % c->prm.block_len != 0;
+    const int empty = st->pos == 0;
+    int32_t *status = d_status ? d_status : st->status;
+    LZ_HIP(launch_stream_finish(st->slot, pending, empty, st->key, st->tag, st->decrypt, d_tag, status, s));
+    st->finished = true;
+    if (!st->decrypt || d_status) return stream_record(st, s);
+    LZ_HIP(hipMemcpyAsync(st->h_status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (int rc = stream_record(st, s)) return rc;
+    LZ_HIP(hipStreamSynchronize(s));
+    if (*st->h_status != LZ_OK) return fail(LZ_E_INTEGRITY, "integrity check failed: stream altered or wrong password");
+    return LZ_OK;
+}
+
+extern "C" uint64_t lz_stream_position(const lz_stream *st) { return st ? st->pos : 0; }
+
+extern "C" int lz_stream_close(lz_stream *st) {
+    stream_free(st);
+    return LZ_OK;
+}

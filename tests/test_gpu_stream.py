@@ -1,0 +1,133 @@
+"""Streaming (resumable) encryption: any chunking gives the one-shot ciphertext and tag."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import host, need_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lz():
+    need_gpu()
+    import paper_1201_3114_amd as lz
+
+    return lz
+
+
+def _chunks(rng, n):
+    cuts, pos = [], 0
+    while pos < n:
+        step = int(rng.choice([0, 1, 7, 100, 255, 256, 257, 600, 3000]))
+        step = min(step, n - pos)
+        cuts.append((pos, pos + step))
+        pos += step
+    return cuts
+
+
+def _stream_encrypt(lz, ctx, P_dev, pw, cuts):
+    import torch
+
+    st = lz.Stream(ctx, False, pw)
+    out = torch.empty(P_dev.numel(), dtype=torch.uint8, device="cuda")
+    for a, b in cuts:
+        if b > a:
+            st.update(P_dev[a:b], out=out[a:b])
+        else:
+            st.update(P_dev[a:a])
+    tag = st.finish()
+    st.close()
+    return torch.cat([out, tag])
+
+
+@pytest.mark.parametrize("n", [0, 1, 100, 256, 257, 1000, 70000])
+def test_stream_equals_one_shot(lz, n):
+    import torch
+
+    rng = np.random.default_rng(60 + n)
+    ctx = lz.Context(0, lz.params(n_it=25))
+    P = rng.integers(0, 256, n, dtype=np.uint8)
+    Pd = to_dev(P) if n else torch.zeros(0, dtype=torch.uint8, device="cuda")
+    one = host(ctx.encrypt(Pd, b"stream pw"))
+    assert np.array_equal(one, oracle.encrypt(b"stream pw", P, n_it=25))
+    for trial in range(3):
+        cuts = _chunks(rng, n) if n else []
+        say("n", n, "chunks", len(cuts))
+        got = host(_stream_encrypt(lz, ctx, Pd, b"stream pw", cuts))
+        assert np.array_equal(got, one), (n, trial)
+    # decrypt as a stream with another chunking; tag verified at the end
+    C = to_dev(one)
+    st = lz.Stream(ctx, True, b"stream pw")
+    back = torch.empty(n, dtype=torch.uint8, device="cuda")
+    for a, b in (_chunks(rng, n) if n else []):
+        if b > a:
+            st.update(C[a:b], out=back[a:b])
+    st.finish(tag=C[n:n + 24].clone())
+    st.close()
+    assert np.array_equal(host(back), P)
+
+
+def test_stream_tamper_and_wrong_tag(lz):
+    import torch
+
+    rng = np.random.default_rng(70)
+    ctx = lz.Context(0, lz.params(n_it=25))
+    P = rng.integers(0, 256, 5000, dtype=np.uint8)
+    C = ctx.encrypt(to_dev(P), b"tamper stream")
+    for flip in (10, 2599, 4999, 5003):
+        bad = C.clone()
+        bad[flip] ^= 0x08
+        st = lz.Stream(ctx, True, b"tamper stream")
+        out = torch.empty(5000, dtype=torch.uint8, device="cuda")
+        st.update(bad[:3000], out=out[:3000])
+        st.update(bad[3000:5000], out=out[3000:])
+        status = torch.full((1,), 9, dtype=torch.int32, device="cuda")
+        st.finish(tag=bad[5000:].clone(), status=status)
+        torch.cuda.synchronize()
+        assert int(status.item()) == -2, flip
+        st.close()
+    st = lz.Stream(ctx, True, b"tamper stream")
+    st.update(C[:5000], out=torch.empty(5000, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(lz.IntegrityError):
+        st.finish(tag=torch.zeros(24, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(lz.LorenzError):
+        st.update(C[:10])  # finished
+    st.close()
+
+
+@pytest.mark.parametrize("kw", [dict(block_len=1 << 20), dict(integrator="euler_fma"), dict(integrator="rk4"),
+                                dict(block_len=3)])
+def test_stream_sequential_and_formats(lz, kw):
+    rng = np.random.default_rng(71)
+    ctx = lz.Context(0, lz.params(n_it=12, **kw))
+    P = rng.integers(0, 256, 2345, dtype=np.uint8)
+    Pd = to_dev(P)
+    one = host(ctx.encrypt(Pd, b"formats"))
+    assert np.array_equal(one, oracle.encrypt(b"formats", P, n_it=12, **kw))
+    got = host(_stream_encrypt(lz, ctx, Pd, b"formats", _chunks(rng, len(P))))
+    assert np.array_equal(got, one)
+
+
+def test_two_streams_interleaved_on_two_streams(lz):
+    import torch
+
+    rng = np.random.default_rng(72)
+    ctx = lz.Context(0, lz.params(n_it=20))
+    Ps = [rng.integers(0, 256, 3333, dtype=np.uint8), rng.integers(0, 256, 1111, dtype=np.uint8)]
+    devs = [to_dev(p) for p in Ps]
+    torch.cuda.synchronize()
+    sts = [lz.Stream(ctx, False, b"first"), lz.Stream(ctx, False, b"second")]
+    tss = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [torch.empty(p.numel(), dtype=torch.uint8, device="cuda") for p in devs]
+    for a in range(0, 3333, 500):
+        for i in (0, 1):
+            b = min(a + 500, devs[i].numel())
+            if b > a:
+                sts[i].update(devs[i][a:b], out=outs[i][a:b], stream=tss[i])
+    tags = [sts[i].finish(stream=tss[i]) for i in (0, 1)]
+    torch.cuda.synchronize()
+    for i, pw in enumerate((b"first", b"second")):
+        got = np.concatenate([host(outs[i]), host(tags[i])])
+        assert np.array_equal(got, oracle.encrypt(pw, Ps[i], n_it=20))
+        sts[i].close()
