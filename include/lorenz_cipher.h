@@ -306,6 +306,38 @@ int lz_histogram(lz_ctx *ctx, const uint8_t *d_data, size_t n, uint64_t *d_hist,
  * A_k = sum_{i < n-k} x_i, B_k = sum_{i >= k} x_i.  Asynchronous on stream. */
 int lz_lag_sums(lz_ctx *ctx, const uint8_t *d_data, size_t n, uint32_t max_lag, uint64_t *d_sums, void *stream);
 
+/* lz_entropy: d_S (device, 1 double) receives S = -sum p_i log2 p_i, p_i =
+ * h_i / n, over the occupied values of the 256-bin histogram d_hist (device,
+ * as written by lz_histogram); S = 0 for an empty histogram (Section 4, the
+ * entropy formula; S_max = 8).  Asynchronous on stream. */
+int lz_entropy(lz_ctx *ctx, const uint64_t *d_hist, double *d_S, void *stream);
+
+/* lz_autocorrelation: d_r (device, max_lag + 1 doubles, overwritten) receives
+ * the autocorrelation coefficients of the mean-removed byte sequence d_data
+ * (device, n bytes): r_k = sum_{i<n-k} (x_i - m)(x_{i+k} - m) / sum_i (x_i - m)^2,
+ * r_0 = 1, r_k = 0 for k >= n, all NaN when every byte is equal or n = 0.
+ * Uses the context's diagnostics workspace (calls of one context are ordered
+ * across streams).  max_lag <= 16384.  Asynchronous on stream. */
+int lz_autocorrelation(lz_ctx *ctx, const uint8_t *d_data, size_t n, uint32_t max_lag, double *d_r, void *stream);
+
+/* Byte matrices (Section 4, the text and image experiments): d_img (device)
+ * holds h rows of w bytes, row-major, 1 <= h, w <= 65536, h * w <= 2^24.
+ *
+ * lz_power_spectrum_2d: d_power (device, h * w doubles, row-major) receives
+ * P[u][v] = |sum_{x,y} X[x][y] exp(-2 pi i (u x / h + v y / w))|^2, unshifted
+ * (the zero frequency at [0][0]).
+ *
+ * lz_autocorrelation_2d: d_acf (device, h * w doubles, row-major) receives the
+ * circular autocorrelation matrix of the mean-removed matrix,
+ * A[dx][dy] = sum_{x,y} Xc[x][y] Xc[(x+dx) mod h][(y+dy) mod w] / sum Xc^2,
+ * Xc = X - mean; all NaN for a constant matrix.  It is computed as the inverse
+ * 2-D DFT of the mean-removed power spectrum (Wiener-Khinchin).
+ *
+ * Both use the context's diagnostics workspace (about 32 h w bytes, grown on
+ * demand: LZ_E_NOMEM if it does not fit) and run asynchronously on stream. */
+int lz_power_spectrum_2d(lz_ctx *ctx, const uint8_t *d_img, uint32_t h, uint32_t w, double *d_power, void *stream);
+int lz_autocorrelation_2d(lz_ctx *ctx, const uint8_t *d_img, uint32_t h, uint32_t w, double *d_acf, void *stream);
+
 /* CLOCK_MONOTONIC now, in ns (the clock of arrival_ns and done_ns). */
 uint64_t lz_now_ns(void);
 

@@ -87,6 +87,10 @@ SIGNATURES = {
     "lz_now_ns": (ctypes.c_uint64, []),
     "lz_histogram": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp, vp]),
     "lz_lag_sums": (ctypes.c_int, [vp, vp, ctypes.c_size_t, ctypes.c_uint32, vp, vp]),
+    "lz_entropy": (ctypes.c_int, [vp, vp, vp, vp]),
+    "lz_autocorrelation": (ctypes.c_int, [vp, vp, ctypes.c_size_t, ctypes.c_uint32, vp, vp]),
+    "lz_power_spectrum_2d": (ctypes.c_int, [vp, vp, ctypes.c_uint32, ctypes.c_uint32, vp, vp]),
+    "lz_autocorrelation_2d": (ctypes.c_int, [vp, vp, ctypes.c_uint32, ctypes.c_uint32, vp, vp]),
     "lz_stream_open": (ctypes.c_int, [vp, ctypes.c_int, u8p, ctypes.c_size_t, ctypes.POINTER(vp)]),
     "lz_stream_update": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp, vp]),
     "lz_stream_finish": (ctypes.c_int, [vp, vp, vp, vp]),

@@ -315,11 +315,11 @@ def histogram(ctx: Context, data: torch.Tensor, stream=None) -> torch.Tensor:
     return out
 
 
-def entropy(hist) -> float:
-    """Shannon entropy in bits per byte of a 256-bin histogram."""
-    h = np.asarray(hist.cpu() if hasattr(hist, "cpu") else hist, dtype=np.float64)
-    p = h[h > 0] / h.sum()
-    return float(-(p * np.log2(p)).sum())
+def entropy(ctx: Context, hist: torch.Tensor, stream=None) -> float:
+    """Shannon entropy in bits per byte of a device histogram (Section 4), computed on the device."""
+    out = torch.empty(1, dtype=torch.float64, device=ctx.device)
+    check(B.lib.lz_entropy(ctx.handle, _dev_ptr(hist), ctypes.c_void_p(out.data_ptr()), _stream(stream, ctx.device)))
+    return float(out.item())
 
 
 def lag_sums(ctx: Context, data: torch.Tensor, max_lag: int, stream=None) -> torch.Tensor:
@@ -331,21 +331,37 @@ def lag_sums(ctx: Context, data: torch.Tensor, max_lag: int, stream=None) -> tor
     return out
 
 
-def autocorrelation(ctx: Context, data: torch.Tensor, max_lag: int) -> np.ndarray:
-    """r_k of the byte sequence from the device's exact lag sums (Section 4, autocorrelation)."""
+def autocorrelation(ctx: Context, data: torch.Tensor, max_lag: int, stream=None) -> torch.Tensor:
+    """r_k, k = 0..max_lag, of the mean-removed byte sequence, on the device (Section 4, autocorrelation)."""
+    out = torch.empty(max_lag + 1, dtype=torch.float64, device=ctx.device)
     n = data.numel()
-    S = lag_sums(ctx, data, max_lag).cpu().numpy().astype(object)
-    total = int(histogram(ctx, data).cpu().numpy() @ np.arange(256))
-    head = data[:max_lag].cpu().numpy().astype(np.int64)
-    tail = data[max(n - max_lag, 0):].cpu().numpy().astype(np.int64)
-    m = total / n
-    den = float(S[0]) - n * m * m
-    r = np.empty(max_lag + 1)
-    for k in range(max_lag + 1):
-        A = total - int(tail[len(tail) - k:].sum()) if k else total
-        Bk = total - int(head[:k].sum())
-        r[k] = (float(S[k]) - m * (A + Bk) + (n - k) * m * m) / den
-    return r
+    check(B.lib.lz_autocorrelation(ctx.handle, _dev_ptr(data) if n else None, n, max_lag,
+                                   ctypes.c_void_p(out.data_ptr()), _stream(stream, ctx.device)))
+    return out
+
+
+def _matrix(img: torch.Tensor):
+    if img.dim() != 2 or img.dtype != torch.uint8 or not img.is_contiguous():
+        raise LorenzError(-1, "expected a contiguous 2-D uint8 tensor")
+    return img.shape[0], img.shape[1]
+
+
+def power_spectrum_2d(ctx: Context, img: torch.Tensor, stream=None) -> torch.Tensor:
+    """|DFT2|^2 of a byte matrix (h x w float64, zero frequency at [0, 0]) -- Section 4's image spectrum."""
+    h, w = _matrix(img)
+    out = torch.empty((h, w), dtype=torch.float64, device=ctx.device)
+    check(B.lib.lz_power_spectrum_2d(ctx.handle, _dev_ptr(img), h, w, ctypes.c_void_p(out.data_ptr()),
+                                     _stream(stream, ctx.device)))
+    return out
+
+
+def autocorrelation_2d(ctx: Context, img: torch.Tensor, stream=None) -> torch.Tensor:
+    """Circular autocorrelation matrix of a mean-removed byte matrix (h x w float64) -- Section 4."""
+    h, w = _matrix(img)
+    out = torch.empty((h, w), dtype=torch.float64, device=ctx.device)
+    check(B.lib.lz_autocorrelation_2d(ctx.handle, _dev_ptr(img), h, w, ctypes.c_void_p(out.data_ptr()),
+                                      _stream(stream, ctx.device)))
+    return out
 
 
 def now_ns() -> int:

@@ -1,7 +1,9 @@
-// Statistical diagnostics of Section 4, as GPU kernels: the byte histogram
-// (frequency analysis; Shannon entropy follows from it) and the
-// autocorrelation of a byte sequence.  The sums are integers, so the results
-// do not depend on the reduction order.
+// Statistical analyses of Section 4 as GPU kernels: the byte histogram
+// (frequency analysis) and Shannon entropy, the autocorrelation of a byte
+// sequence, and, for a byte matrix (a text or an image laid out row by row),
+// the circular autocorrelation matrix and the 2-D Fourier power spectrum.
+// Integer sums are exact (the results do not depend on the reduction order);
+// the floating-point results are binary64.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -57,6 +59,201 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_kernel(const uint8_t *data, ui
     }
 }
 
+
+// ---- entropy and the normalised 1-D autocorrelation -------------------------------------
+
+// Block-wide sum over 256 threads (LDS tree, fixed order, so the result is deterministic).
+template <typename T>
+__device__ T block_sum(T v, T *red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = DIAG_WG / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const T r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// S = -sum p_i log2 p_i with p_i = h_i / n over the occupied byte values; S = 0 when n = 0.
+__global__ __launch_bounds__(DIAG_WG) void entropy_kernel(const unsigned long long *hist, double *out) {
+    __shared__ unsigned long long ired[DIAG_WG];
+    __shared__ double dred[DIAG_WG];
+    const unsigned long long h = hist[threadIdx.x];
+    const unsigned long long n = block_sum<unsigned long long>(h, ired);
+    double term = 0.0;
+    if (h != 0) {
+        const double p = (double)h / (double)n;
+        term = -p * log2(p);
+    }
+    const double S = block_sum<double>(term, dred);
+    if (threadIdx.x == 0) out[0] = S;
+}
+
+// r_k for k = 0..L of a byte sequence x_0..x_{n-1} with mean m:
+//   r_k = sum_{i<n-k} (x_i - m)(x_{i+k} - m) / sum_i (x_i - m)^2
+//       = (S_k - m (A_k + B_k) + (n-k) m^2) / (S_0 - n m^2),
+// A_k = sum_{i<n-k} x_i = T - (sum of the last k bytes), B_k = sum_{i>=k} x_i = T - (sum of the first k bytes).
+// One workgroup scans the first and last L bytes in chunks of 256.
+__global__ __launch_bounds__(DIAG_WG) void autocorr_norm_kernel(const uint8_t *data, uint64_t n, uint32_t L,
+                                                                 const unsigned long long *sums,
+                                                                 const unsigned long long *hist, double *r) {
+    __shared__ unsigned long long ired[DIAG_WG];
+    __shared__ unsigned long long sh[DIAG_WG], st[DIAG_WG];
+    const unsigned long long T =
+        block_sum<unsigned long long>(hist[threadIdx.x] * (unsigned long long)threadIdx.x, ired);
+    const double m = (double)T / (double)n;
+    const double den = (double)sums[0] - (double)n * m * m;
+    // no coefficient when every byte is equal (or there are none): at most one occupied value
+    const bool constant = block_sum<unsigned long long>(hist[threadIdx.x] != 0, ired) <= 1;
+    unsigned long long carry_h = 0, carry_t = 0;
+    if (threadIdx.x == 0) r[0] = constant ? __builtin_nan("") : 1.0;
+    for (uint32_t c = 0; c < L; c += DIAG_WG) {
+        const uint64_t i = (uint64_t)c + threadIdx.x;  // k = i + 1 includes byte i of the head / tail
+        sh[threadIdx.x] = i < n ? data[i] : 0;
+        st[threadIdx.x] = i < n ? data[n - 1 - i] : 0;
+        __syncthreads();
+        for (int s = 1; s < DIAG_WG; s <<= 1) {  // inclusive scans
+            const unsigned long long a = threadIdx.x >= (unsigned)s ? sh[threadIdx.x - s] : 0;
+            const unsigned long long b = threadIdx.x >= (unsigned)s ? st[threadIdx.x - s] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += a;
+            st[threadIdx.x] += b;
+            __syncthreads();
+        }
+        const uint64_t k = i + 1;
+        if (k <= L) {
+            double v;
+            if (constant) {
+                v = __builtin_nan("");
+            } else if (k >= n) {
+                v = 0.0;
+            } else {
+                const double Ak = (double)(T - (carry_t + st[threadIdx.x]));
+                const double Bk = (double)(T - (carry_h + sh[threadIdx.x]));
+                v = ((double)sums[k] - m * (Ak + Bk) + (double)(n - k) * m * m) / den;
+            }
+            r[k] = v;
+        }
+        carry_h += sh[DIAG_WG - 1];
+        carry_t += st[DIAG_WG - 1];
+        __syncthreads();
+    }
+}
+
+// ---- 2-D discrete Fourier transform as two passes ----------------------------------------
+//
+// One pass applies the N-point DFT along the rows index of an N x M matrix and
+// writes the result transposed:  dst[c][r] = sum_k e^{sign 2 pi i r k / N} src[k][c].
+// Two passes (first along the H rows of the H x W image, then along its W
+// columns) give the 2-D DFT in natural layout.  Every size is allowed (no
+// power-of-two restriction); the twiddle index r k mod N is kept exact in
+// integers, so every twiddle is one table entry.
+
+constexpr int DFT_T = 64;  // output tile edge (r and c)
+constexpr int DFT_K = 16;  // k values per LDS stage
+
+// tw[j] = (cos 2 pi j / N, sin 2 pi j / N)
+__global__ void twiddle_kernel(double2 *tw, uint32_t N) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double s, c;
+    sincospi(2.0 * (double)j / (double)N, &s, &c);
+    tw[j] = make_double2(c, s);
+}
+
+__device__ __forceinline__ double2 dft_load(const uint8_t *p, size_t i) { return make_double2((double)p[i], 0.0); }
+__device__ __forceinline__ double2 dft_load(const double *p, size_t i) { return make_double2(p[i], 0.0); }
+__device__ __forceinline__ double2 dft_load(const double2 *p, size_t i) { return p[i]; }
+
+template <typename In>
+__global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32_t N, uint32_t M, const double2 *tw,
+                                                            double sign, double2 *dst) {
+    __shared__ double2 s_src[DFT_K][DFT_T];  // [k][c]
+    __shared__ double2 s_tw[DFT_K][DFT_T];   // [k][r]
+    const uint32_t r0 = blockIdx.x * DFT_T, c0 = blockIdx.y * DFT_T;
+    const uint32_t tr = threadIdx.x % 16, tc = threadIdx.x / 16;  // consecutive lanes: consecutive r
+    // staging role: column cc of the tile, k rows kq + 4q (q = 0..3)
+    const uint32_t cc = threadIdx.x % DFT_T, kq = threadIdx.x / DFT_T;
+    const uint32_t rs = r0 + cc;  // the twiddle row this thread stages
+    const uint32_t rmod = rs < N ? rs : 0;
+    uint32_t off[4];
+    for (int q = 0; q < 4; ++q) off[q] = (uint32_t)(((uint64_t)rmod * (kq + 4 * q)) % N);
+    const uint32_t step = (uint32_t)(((uint64_t)rmod * DFT_K) % N);
+    uint32_t base = 0;  // rs * k0 mod N
+    double ar[4][4], ai[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) ar[i][j] = ai[i][j] = 0.0;
+    for (uint32_t k0 = 0; k0 < N; k0 += DFT_K) {
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t kk = kq + 4 * q, k = k0 + kk, c = c0 + cc;
+            s_src[kk][cc] = (k < N && c < M) ? dft_load(src, (size_t)k * M + c) : make_double2(0.0, 0.0);
+            uint32_t j = base + off[q];
+            if (j >= N) j -= N;
+            double2 w = make_double2(0.0, 0.0);
+            if (k < N && rs < N) {
+                w = tw[j];
+                w.y *= sign;
+            }
+            s_tw[kk][cc] = w;
+        }
+        base += step;
+        if (base >= N) base -= N;
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < DFT_K; ++kk) {
+            double2 w[4], x[4];
+            for (int i = 0; i < 4; ++i) w[i] = s_tw[kk][tr + 16 * i];
+            for (int j = 0; j < 4; ++j) x[j] = s_src[kk][tc + 16 * j];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    ar[i][j] = __builtin_fma(w[i].x, x[j].x, __builtin_fma(-w[i].y, x[j].y, ar[i][j]));
+                    ai[i][j] = __builtin_fma(w[i].x, x[j].y, __builtin_fma(w[i].y, x[j].x, ai[i][j]));
+                }
+        }
+        __syncthreads();
+    }
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t c = c0 + tc + 16 * j;
+        if (c >= M) continue;
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t r = r0 + tr + 16 * i;
+            if (r < N) dst[(size_t)c * N + r] = make_double2(ar[i][j], ai[i][j]);
+        }
+    }
+}
+
+// |Z|^2 element by element; with zero_dc the (0, 0) entry is set to 0 (the
+// spectrum of the mean-removed image differs from the image's only there).
+__global__ void power_kernel(const double2 *Z, size_t n, double *P, int zero_dc) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const double2 z = Z[i];
+        P[i] = (zero_dc && i == 0) ? 0.0 : z.x * z.x + z.y * z.y;
+    }
+}
+
+// n S2 - S1^2 from the histogram (exact: n <= 2^24 keeps both products below 2^64),
+// the zero-lag sum of the mean-removed image scaled by n.
+__global__ __launch_bounds__(DIAG_WG) void acf2_den_kernel(const unsigned long long *hist, uint64_t n,
+                                                            double *den) {
+    __shared__ unsigned long long ired[DIAG_WG];
+    const unsigned long long v = threadIdx.x, h = hist[threadIdx.x];
+    const unsigned long long s1 = block_sum<unsigned long long>(h * v, ired);
+    const unsigned long long s2 = block_sum<unsigned long long>(h * v * v, ired);
+    if (threadIdx.x == 0) {
+        const unsigned long long d = (unsigned long long)n * s2 - s1 * s1;
+        den[0] = d == 0 ? __builtin_nan("") : (double)d;
+    }
+}
+
+// A = Re(G) / (n S2 - S1^2), G the unnormalised inverse DFT of the mean-removed power spectrum.
+__global__ void acf2_norm_kernel(const double2 *G, size_t n, const double *den, double *A) {
+    const double d = den[0];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        A[i] = d != d ? d : G[i].x / d;
+}
+
 }  // namespace
 }  // namespace lz
 
@@ -90,4 +287,167 @@ extern "C" int lz_lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t 
                        (uint64_t)n, max_lag, reinterpret_cast<unsigned long long *>(d_sums));
     LZ_HIP(hipGetLastError());
     return LZ_OK;
+}
+
+namespace {
+
+// The context's diagnostics workspace: grown on demand, and calls on different
+// streams are ordered through one event so that they never share it at once.
+int diag_begin(lz_ctx *c, hipStream_t s, size_t bytes, char **ws) {
+    if (c->diag_has_last && c->diag_last != s) LZ_HIP(hipStreamWaitEvent(s, c->diag_event, 0));
+    if (bytes > c->diag_ws_bytes) {
+        if (c->diag_has_last) LZ_HIP(hipEventSynchronize(c->diag_event));
+        if (c->diag_ws) LZ_HIP(hipFree(c->diag_ws));
+        c->diag_ws = nullptr;
+        c->diag_ws_bytes = 0;
+        const hipError_t e = hipMalloc(&c->diag_ws, bytes);
+        if (e != hipSuccess) {
+            c->diag_ws = nullptr;
+            return e == hipErrorOutOfMemory ? fail(LZ_E_NOMEM, "diagnostics workspace does not fit")
+                                            : hip_fail(e, "diagnostics workspace");
+        }
+        c->diag_ws_bytes = bytes;
+    }
+    *ws = static_cast<char *>(c->diag_ws);
+    return LZ_OK;
+}
+
+int diag_end(lz_ctx *c, hipStream_t s) {
+    LZ_HIP(hipEventRecord(c->diag_event, s));
+    c->diag_last = s;
+    c->diag_has_last = true;
+    return LZ_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int check_matrix(const lz_ctx *c, const uint8_t *img, uint32_t h, uint32_t w, const void *out) {
+    if (!c || !img || !out) return fail(LZ_E_INVAL, "NULL argument");
+    if (h == 0 || w == 0) return fail(LZ_E_INVAL, "empty matrix");
+    if (h > 65536 || w > 65536 || (uint64_t)h * w > (1ull << 24))
+        return fail(LZ_E_INVAL, "matrix too large: h, w <= 65536 and h * w <= 2^24");
+    return LZ_OK;
+}
+
+struct Dft2 {
+    double2 *tw_h, *tw_w, *a, *b;
+};
+
+// Workspace: twiddles for h and w, then two h*w complex buffers; extra bytes go first.
+Dft2 dft2_layout(char *ws, uint32_t h, uint32_t w, size_t extra) {
+    Dft2 d;
+    size_t off = align256(extra);
+    d.tw_h = reinterpret_cast<double2 *>(ws + off);
+    off += align256((size_t)h * sizeof(double2));
+    d.tw_w = reinterpret_cast<double2 *>(ws + off);
+    off += align256((size_t)w * sizeof(double2));
+    d.a = reinterpret_cast<double2 *>(ws + off);
+    off += align256((size_t)h * w * sizeof(double2));
+    d.b = reinterpret_cast<double2 *>(ws + off);
+    return d;
+}
+
+size_t dft2_bytes(uint32_t h, uint32_t w, size_t extra) {
+    return align256(extra) + align256((size_t)h * sizeof(double2)) + align256((size_t)w * sizeof(double2)) +
+           2 * align256((size_t)h * w * sizeof(double2));
+}
+
+int launch_twiddles(const Dft2 &d, uint32_t h, uint32_t w, hipStream_t s) {
+    hipLaunchKernelGGL(twiddle_kernel, dim3((h + 255) / 256), dim3(256), 0, s, d.tw_h, h);
+    hipLaunchKernelGGL(twiddle_kernel, dim3((w + 255) / 256), dim3(256), 0, s, d.tw_w, w);
+    LZ_HIP(hipGetLastError());
+    return LZ_OK;
+}
+
+// dst (M x N) = transpose of (DFT_N along the rows of src (N x M))
+template <typename In>
+int launch_dft_pass(const In *src, uint32_t N, uint32_t M, const double2 *tw, double sign, double2 *dst,
+                    hipStream_t s) {
+    const dim3 grid((N + DFT_T - 1) / DFT_T, (M + DFT_T - 1) / DFT_T);
+    hipLaunchKernelGGL((dft_pass_kernel<In>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, dst);
+    LZ_HIP(hipGetLastError());
+    return LZ_OK;
+}
+
+unsigned grid_for(size_t n, const lz_ctx *c) {
+    size_t b = (n + 255) / 256;
+    const size_t cap = (size_t)c->dev.cus * 8;
+    return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+
+extern "C" int lz_entropy(lz_ctx *c, const uint64_t *d_hist, double *d_S, void *stream) {
+    if (!c || !d_hist || !d_S) return fail(LZ_E_INVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    LZ_HIP(hipSetDevice(c->device));
+    hipLaunchKernelGGL(entropy_kernel, dim3(1), dim3(DIAG_WG), 0, s,
+                       reinterpret_cast<const unsigned long long *>(d_hist), d_S);
+    LZ_HIP(hipGetLastError());
+    return LZ_OK;
+}
+
+extern "C" int lz_autocorrelation(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, double *d_r,
+                                  void *stream) {
+    if (!c || !d_r || (!d_data && n)) return fail(LZ_E_INVAL, "NULL argument");
+    if (max_lag > 16384) return fail(LZ_E_INVAL, "max_lag must be <= 16384");
+    hipStream_t s = (hipStream_t)stream;
+    LZ_HIP(hipSetDevice(c->device));
+    char *ws;
+    if (int rc = diag_begin(c, s, 256 * 8 + ((size_t)max_lag + 1) * 8, &ws)) return rc;
+    uint64_t *hist = reinterpret_cast<uint64_t *>(ws);
+    uint64_t *sums = hist + 256;
+    if (int rc = lz_histogram(c, d_data, n, hist, stream)) return rc;
+    if (int rc = lz_lag_sums(c, d_data, n, max_lag, sums, stream)) return rc;
+    hipLaunchKernelGGL(autocorr_norm_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag,
+                       reinterpret_cast<const unsigned long long *>(sums),
+                       reinterpret_cast<const unsigned long long *>(hist), d_r);
+    LZ_HIP(hipGetLastError());
+    return diag_end(c, s);
+}
+
+extern "C" int lz_power_spectrum_2d(lz_ctx *c, const uint8_t *d_img, uint32_t h, uint32_t w, double *d_power,
+                                    void *stream) {
+    if (int rc = check_matrix(c, d_img, h, w, d_power)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    LZ_HIP(hipSetDevice(c->device));
+    char *ws;
+    if (int rc = diag_begin(c, s, dft2_bytes(h, w, 0), &ws)) return rc;
+    const Dft2 d = dft2_layout(ws, h, w, 0);
+    if (int rc = launch_twiddles(d, h, w, s)) return rc;
+    if (int rc = launch_dft_pass<uint8_t>(d_img, h, w, d.tw_h, -1.0, d.a, s)) return rc;  // a: w x h
+    if (int rc = launch_dft_pass<double2>(d.a, w, h, d.tw_w, -1.0, d.b, s)) return rc;   // b: h x w = Z
+    const size_t n = (size_t)h * w;
+    hipLaunchKernelGGL(power_kernel, dim3(grid_for(n, c)), dim3(256), 0, s, d.b, n, d_power, 0);
+    LZ_HIP(hipGetLastError());
+    return diag_end(c, s);
+}
+
+extern "C" int lz_autocorrelation_2d(lz_ctx *c, const uint8_t *d_img, uint32_t h, uint32_t w, double *d_acf,
+                                     void *stream) {
+    if (int rc = check_matrix(c, d_img, h, w, d_acf)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    LZ_HIP(hipSetDevice(c->device));
+    char *ws;
+    const size_t extra = 256 * 8 + 8;  // histogram, then the denominator
+    if (int rc = diag_begin(c, s, dft2_bytes(h, w, extra), &ws)) return rc;
+    uint64_t *hist = reinterpret_cast<uint64_t *>(ws);
+    double *den = reinterpret_cast<double *>(hist + 256);
+    const Dft2 d = dft2_layout(ws, h, w, extra);
+    const size_t n = (size_t)h * w;
+    if (int rc = lz_histogram(c, d_img, n, hist, stream)) return rc;
+    hipLaunchKernelGGL(acf2_den_kernel, dim3(1), dim3(DIAG_WG), 0, s,
+                       reinterpret_cast<const unsigned long long *>(hist), (uint64_t)n, den);
+    LZ_HIP(hipGetLastError());
+    if (int rc = launch_twiddles(d, h, w, s)) return rc;
+    if (int rc = launch_dft_pass<uint8_t>(d_img, h, w, d.tw_h, -1.0, d.a, s)) return rc;  // a: w x h
+    if (int rc = launch_dft_pass<double2>(d.a, w, h, d.tw_w, -1.0, d.b, s)) return rc;   // b: Z, h x w
+    double *pm = reinterpret_cast<double *>(d.a);                                         // a: |Z|^2, DC = 0
+    hipLaunchKernelGGL(power_kernel, dim3(grid_for(n, c)), dim3(256), 0, s, d.b, n, pm, 1);
+    LZ_HIP(hipGetLastError());
+    if (int rc = launch_dft_pass<double>(pm, h, w, d.tw_h, 1.0, d.b, s)) return rc;       // b: w x h
+    if (int rc = launch_dft_pass<double2>(d.b, w, h, d.tw_w, 1.0, d.a, s)) return rc;     // a: G, h x w
+    hipLaunchKernelGGL(acf2_norm_kernel, dim3(grid_for(n, c)), dim3(256), 0, s, d.a, n, den, d_acf);
+    LZ_HIP(hipGetLastError());
+    return diag_end(c, s);
 }

@@ -140,4 +140,10 @@ struct lz_ctx {
     hipStream_t last_stream;
     hipEvent_t last_event;
     bool has_last;
+    // diagnostics workspace (grown on demand) and the event that orders its users
+    void *diag_ws;
+    size_t diag_ws_bytes;
+    hipEvent_t diag_event;
+    hipStream_t diag_last;
+    bool diag_has_last;
 };

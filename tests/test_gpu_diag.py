@@ -1,11 +1,18 @@
-"""Section 4 diagnostics on the GPU (byte histogram, lag sums / autocorrelation) vs numpy, exactly."""
+"""Section 4 diagnostics on the GPU vs the oracle (oracle/diagnostics.py).
+
+Integer results (histogram, lag sums) are compared exactly.  Floating-point
+results use error bounds derived from the arithmetic, written in each test
+(eps = 2^-53 is the unit roundoff of binary64).
+"""
 import numpy as np
 import pytest
 
 import oracle
-from gpu_util import host, need_gpu, to_dev
+from oracle import diagnostics as dg
+from gpu_util import host, need_gpu, say, to_dev
 
 pytestmark = pytest.mark.gpu
+EPS = 2.0 ** -53
 
 
 @pytest.fixture(scope="module")
@@ -16,47 +23,209 @@ def lz():
     return lz
 
 
-@pytest.mark.parametrize("n", [0, 1, 3, 4, 5, 1000, 65537, 3_000_001])
-def test_histogram_exact(lz, n):
+@pytest.fixture(scope="module")
+def ctx(lz):
+    return lz.Context(0)
+
+
+def _dev(x):
     import torch
 
+    return to_dev(x) if x.size else torch.zeros(0, dtype=torch.uint8, device="cuda")
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 4, 5, 1000, 65537, 3_000_001])
+def test_histogram_exact(lz, ctx, n):
     rng = np.random.default_rng(80 + n)
     x = rng.integers(0, 256, n, dtype=np.uint8)
-    ctx = lz.Context(0)
-    d = to_dev(x) if n else torch.zeros(0, dtype=torch.uint8, device="cuda")
+    d = _dev(x)
     h = host(lz.histogram(ctx, d)).astype(np.int64)
-    assert np.array_equal(h, np.bincount(x, minlength=256))
+    assert np.array_equal(h, dg.histogram(x))
     if n > 1:  # misaligned start
-        h2 = host(lz.histogram(ctx, d[1:])).astype(np.int64)
-        assert np.array_equal(h2, np.bincount(x[1:], minlength=256))
+        assert np.array_equal(host(lz.histogram(ctx, d[1:])).astype(np.int64), dg.histogram(x[1:]))
+
+
+@pytest.mark.parametrize("kind", ["empty", "one", "two", "uniform", "skewed", "all"])
+def test_entropy(lz, ctx, kind):
+    rng = np.random.default_rng(81)
+    x = {"empty": np.zeros(0, np.uint8), "one": np.full(100, 5, np.uint8),
+         "two": np.array([1, 2] * 500, np.uint8), "uniform": rng.integers(0, 256, 1 << 20, dtype=np.uint8),
+         "skewed": (rng.exponential(20, 200_000).clip(0, 255)).astype(np.uint8),
+         "all": np.arange(256 * 7, dtype=np.int64).astype(np.uint8)}[kind]
+    S = lz.entropy(ctx, lz.histogram(ctx, _dev(x)))
+    want = dg.entropy(dg.histogram(x))
+    # 256 terms, each within a few ulps (log2 and one division), summed in another order: |dS| <= 256 * 16 eps * 8
+    assert abs(S - want) <= 256 * 16 * EPS * 8, (S, want)
+    if kind in ("empty", "one"):
+        assert S == 0.0
+    if kind == "two":
+        assert S == 1.0
 
 
 @pytest.mark.parametrize("n,L", [(0, 5), (1, 0), (10, 20), (5000, 300), (200_003, 256), (1_000_000, 1000)])
-def test_lag_sums_exact(lz, n, L):
-    import torch
-
+def test_lag_sums_exact(lz, ctx, n, L):
     rng = np.random.default_rng(90 + n)
     x = rng.integers(0, 256, n, dtype=np.uint8)
-    ctx = lz.Context(0)
-    d = to_dev(x) if n else torch.zeros(0, dtype=torch.uint8, device="cuda")
-    got = host(lz.lag_sums(ctx, d, L)).astype(np.int64)
-    xi = x.astype(np.int64)
-    want = np.array([int(np.dot(xi[:n - k], xi[k:])) if k < n else 0 for k in range(L + 1)], dtype=np.int64)
-    assert np.array_equal(got, want)
+    got = host(lz.lag_sums(ctx, _dev(x), L)).astype(np.int64)
+    assert np.array_equal(got, dg.lag_sums(x, L))
 
 
-def test_autocorrelation_and_entropy_of_ciphertext(lz):
-    """Sanity only: a low-entropy plaintext's ciphertext is near-uniform and uncorrelated (Section 4)."""
-    rng = np.random.default_rng(95)
-    P = rng.integers(64, 96, 1 << 16, dtype=np.uint8)
-    ctx = lz.Context(0)
-    C = ctx.encrypt(to_dev(P), b"123456")[:-24].contiguous()
-    assert np.array_equal(host(C), oracle.encrypt(b"123456", P, nthreads=8)[:-24])
-    S = lz.entropy(lz.histogram(ctx, C))
-    assert S > 7.99
-    r = lz.autocorrelation(ctx, C, 64)
-    xc = host(C).astype(np.float64) - host(C).mean()
-    want = np.array([np.dot(xc[:len(xc) - k], xc[k:]) for k in range(65)]) / np.dot(xc, xc)
-    assert np.allclose(r, want, rtol=0, atol=1e-9)
-    assert abs(r[0] - 1.0) < 1e-12
-    assert np.max(np.abs(r[1:])) < 0.03
+@pytest.mark.parametrize("n,L,kind", [(0, 4, "rand"), (1, 3, "rand"), (7, 12, "rand"), (40, 6, "alt"),
+                                      (5000, 300, "rand"), (100_000, 700, "text"), (1000, 5, "const"),
+                                      (300_001, 2000, "rand")])
+def test_autocorrelation_1d(lz, ctx, n, L, kind):
+    rng = np.random.default_rng(91 + n)
+    if kind == "alt":
+        x = np.array([10, 30] * (n // 2), np.uint8)
+    elif kind == "const":
+        x = np.full(n, 77, np.uint8)
+    elif kind == "text":  # letters and spaces, strongly non-uniform
+        x = rng.choice(np.frombuffer(b"etaoin shrdlu       ", np.uint8), n)
+    else:
+        x = rng.integers(0, 256, n, dtype=np.uint8)
+    got = host(lz.autocorrelation(ctx, _dev(x), L))
+    want = dg.autocorrelation(x, L)
+    if kind == "const" or n == 0 or (n == 1):
+        assert np.isnan(got).all() and np.isnan(want).all()
+        return
+    xs = x.astype(np.float64)
+    S0, T = float((xs * xs).sum()), float(xs.sum())
+    # every term of num and den is at most S0 in size and carries a few roundings: |dr| <= 64 eps S0 / den
+    tol = 64 * EPS * S0 / (S0 - T * T / n)
+    assert np.max(np.abs(got - want)) <= tol, (np.max(np.abs(got - want)), tol)
+    if kind == "alt":
+        assert np.allclose(got, [(-1) ** k * (n - k) / n for k in range(L + 1)], rtol=0, atol=tol)
+
+
+def _dz_max(x):
+    """Bound on the error of each DFT value Z[u][v] after the two passes.  A pass sums N complex
+    products w x with |w| = 1 in fused multiply-adds, 2N roundings per real component, so each
+    component is off by at most 2N eps sum|x| (twiddle errors add a few eps more); the complex
+    magnitude adds sqrt 2 twice over.  Both passes: |dZ| <= 4 (h + w + 4) eps S1, S1 = sum x."""
+    h, w = x.shape
+    return 4 * (h + w + 4) * EPS * float(x.astype(np.float64).sum())
+
+
+def _power_tol(x):
+    """|dP| <= 2 |Z| |dZ| + |dZ|^2 + 2 eps |Z|^2 with |Z| <= S1."""
+    S1 = float(x.astype(np.float64).sum())
+    dz = _dz_max(x)
+    return 2 * S1 * dz + dz * dz + 2 * EPS * S1 * S1
+
+
+@pytest.mark.parametrize("h,w", [(1, 1), (1, 37), (29, 1), (8, 8), (64, 64), (67, 131), (128, 200), (512, 512),
+                                 (3, 4096)])
+def test_power_spectrum_2d(lz, ctx, h, w):
+    rng = np.random.default_rng(100 + h * 7 + w)
+    x = rng.integers(0, 256, (h, w), dtype=np.uint8)
+    say("power spectrum", h, w)
+    got = host(lz.power_spectrum_2d(ctx, to_dev(x.ravel()).view(h, w)))
+    want = dg.power_spectrum_2d(x)
+    err = np.max(np.abs(got - want))
+    assert err <= _power_tol(x), (err, _power_tol(x))
+    # the zero frequency is exactly (sum x)^2 up to the same bound
+    assert abs(got[0, 0] - float(x.astype(np.int64).sum()) ** 2) <= _power_tol(x)
+
+
+def test_power_spectrum_2d_closed_forms(lz, ctx):
+    H, W = 96, 70
+    xx, yy = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    chk = ((xx + yy) % 2).astype(np.uint8)
+    got = host(lz.power_spectrum_2d(ctx, to_dev(chk.ravel()).view(H, W)))
+    want = np.zeros((H, W))
+    want[0, 0] = want[H // 2, W // 2] = (H * W / 2) ** 2
+    assert np.max(np.abs(got - want)) <= _power_tol(chk)
+    imp = np.zeros((H, W), np.uint8)
+    imp[5, 9] = 200
+    got = host(lz.power_spectrum_2d(ctx, to_dev(imp.ravel()).view(H, W)))
+    assert np.max(np.abs(got - 40000.0)) <= _power_tol(imp)
+
+
+def _acf2_tol(x):
+    """A = G / den, G the inverse DFT of P' (the spectrum with the zero frequency removed) and
+    den = n S2 - S1^2, which is also sum P' (Parseval).  Errors entering G:
+      from dP': sum |dP'| <= 2 dZ sum|Z| + n dZ^2 + 2 eps sum|Z|^2, with sum|Z| <= n sqrt(S2)
+                (Cauchy-Schwarz and Parseval: sum|Z|^2 = n S2);
+      from the inverse passes: 4 (h + w + 4) eps sum|P'| = 4 (h + w + 4) eps den;
+    and the final division adds eps."""
+    h, w = x.shape
+    n = h * w
+    xs = x.astype(np.int64)
+    S1, S2 = int(xs.sum()), int((xs * xs).sum())
+    den = float(n * S2 - S1 * S1)
+    dz = _dz_max(x)
+    from_p = 2 * dz * n * np.sqrt(S2) + n * dz * dz + 2 * EPS * n * S2
+    return from_p / den + 4 * (h + w + 4) * EPS + 2 * EPS
+
+
+@pytest.mark.parametrize("h,w", [(1, 2), (2, 1), (5, 7), (16, 16), (24, 40), (33, 17), (1, 300)])
+def test_autocorrelation_2d_full(lz, ctx, h, w):
+    rng = np.random.default_rng(110 + h * 5 + w)
+    x = rng.integers(0, 256, (h, w), dtype=np.uint8)
+    got = host(lz.autocorrelation_2d(ctx, to_dev(x.ravel()).view(h, w)))
+    want = dg.autocorrelation_2d(x)
+    err = np.max(np.abs(got - want))
+    assert err <= _acf2_tol(x), (err, _acf2_tol(x))
+
+
+def test_autocorrelation_2d_closed_forms_and_constant(lz, ctx):
+    H, W = 40, 64
+    xx, yy = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    chk = (100 + 50 * ((xx + yy) % 2)).astype(np.uint8)
+    got = host(lz.autocorrelation_2d(ctx, to_dev(chk.ravel()).view(H, W)))
+    assert np.max(np.abs(got - (-1.0) ** (xx + yy))) <= _acf2_tol(chk)
+    const = np.full((9, 13), 42, np.uint8)
+    assert np.isnan(host(lz.autocorrelation_2d(ctx, to_dev(const.ravel()).view(9, 13)))).all()
+    one = np.full((1, 1), 3, np.uint8)
+    assert np.isnan(host(lz.autocorrelation_2d(ctx, to_dev(one.ravel()).view(1, 1)))).all()
+
+
+def test_autocorrelation_2d_sampled_large(lz, ctx):
+    """A 512 x 768 image-like matrix (smooth gradient + noise), checked at sampled lags."""
+    rng = np.random.default_rng(120)
+    H, W = 512, 768
+    xx, yy = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    img = ((xx * 255 // H + yy * 255 // W) // 2 + rng.integers(0, 40, (H, W))).clip(0, 255).astype(np.uint8)
+    got = host(lz.autocorrelation_2d(ctx, to_dev(img.ravel()).view(H, W)))
+    tol = _acf2_tol(img)
+    lags = [(0, 0), (1, 0), (0, 1), (1, 1), (7, 300), (H - 1, W - 1), (256, 384), (100, 5)]
+    lags += [tuple(v) for v in rng.integers(0, [H, W], (8, 2))]
+    for dx, dy in lags:
+        want = dg.autocorrelation_2d_at(img, int(dx), int(dy))
+        assert abs(got[dx, dy] - want) <= tol, (dx, dy, got[dx, dy], want, tol)
+    assert abs(got[0, 0] - 1.0) <= tol
+
+
+def test_diagnostics_of_a_ciphertext(lz, ctx):
+    """Sanity (Section 4): a structured plaintext's ciphertext has a flat histogram, near-zero
+    autocorrelation and a spectrum with no dominant frequency.  Not a security claim."""
+    H, W = 128, 128
+    xx, yy = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    img = ((xx + yy) % 64 + 96).astype(np.uint8)
+    C = ctx.encrypt(to_dev(img.ravel()), b"123456")[:-24].contiguous()
+    assert np.array_equal(host(C), oracle.encrypt(b"123456", img.ravel(), nthreads=8)[:-24])
+    S = lz.entropy(ctx, lz.histogram(ctx, C))
+    assert S > 7.98
+    r = host(lz.autocorrelation(ctx, C, 64))
+    assert abs(r[0] - 1.0) < 1e-12 and np.max(np.abs(r[1:])) < 0.05
+    A = host(lz.autocorrelation_2d(ctx, C.view(H, W)))
+    assert np.max(np.abs(A.ravel()[1:])) < 0.05
+    P = host(lz.power_spectrum_2d(ctx, C.view(H, W)))
+    Pp = host(lz.power_spectrum_2d(ctx, to_dev(img.ravel()).view(H, W)))
+    ac_c = P.ravel()[1:]
+    ac_p = Pp.ravel()[1:]
+    assert ac_c.max() / ac_c.mean() < 30 < ac_p.max() / ac_p.mean()
+
+
+def test_invalid_arguments(lz, ctx):
+    import torch
+
+    x = torch.zeros((4, 4), dtype=torch.uint8, device="cuda")
+    with pytest.raises(lz.LorenzError):
+        lz.power_spectrum_2d(ctx, torch.zeros((0, 4), dtype=torch.uint8, device="cuda"))
+    with pytest.raises(lz.LorenzError):
+        lz.autocorrelation_2d(ctx, torch.zeros((1, 1 << 17), dtype=torch.uint8, device="cuda"))
+    with pytest.raises(lz.LorenzError):
+        lz.autocorrelation(ctx, x.view(-1), 16385)
+    with pytest.raises(lz.LorenzError):
+        lz.power_spectrum_2d(ctx, x.view(-1))
