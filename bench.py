@@ -222,6 +222,50 @@ def bench_sequential(lz, torch, count=4096):
 
 
 # ---------------------------------------------------------------------------------------------
+def bench_diag(lz, torch, reps=5):
+    """Section 4 analyses on ciphertext-like (uniform random) bytes: histogram of 64 MiB (HBM-bound),
+    the autocorrelation up to lag 256 of 16 MiB, and the 2-D power spectrum and autocorrelation
+    matrix of a 1024 x 1024 byte image (two / four DFT passes, binary64 FMA)."""
+    ctx = lz.Context(0)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(130)
+    x = torch.randint(0, 256, (64 * MiB,), dtype=torch.uint8, device="cuda", generator=g)
+    img = x[:1 << 20].view(1024, 1024)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record(stream)
+        for _ in range(reps):
+            fn()
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        return e[0].elapsed_time(e[1]) / reps
+
+    res = {}
+    ms = timed(lambda: lz.histogram(ctx, x))
+    res["histogram_64MiB"] = dict(ms=ms, GBps=x.numel() / ms / 1e6, frac_of_hbm=x.numel() / ms * 1e3 / HBM_PEAK)
+    h = lz.histogram(ctx, x)
+    res["entropy_bits"] = lz.entropy(ctx, h)
+    n16, L = 16 * MiB, 256
+    ms = timed(lambda: lz.autocorrelation(ctx, x[:n16], L))
+    res["autocorrelation_16MiB_lag256"] = dict(ms=ms, int_MAC_per_s=n16 * (L + 1) / ms * 1e3)
+    N = 1024
+    flops_pass = N * N * N * 8  # complex multiply-add = 4 FMA = 8 flops, N x N outputs of N terms
+    ms = timed(lambda: lz.power_spectrum_2d(ctx, img))
+    res["power_spectrum_1024x1024"] = dict(ms=ms, TFLOPs=2 * flops_pass / ms / 1e9,
+                                           frac_of_fp64_fma_peak=2 * flops_pass / ms * 1e3 / FP64_FMA_COUNTED_PEAK)
+    ms = timed(lambda: lz.autocorrelation_2d(ctx, img))
+    res["autocorrelation_2d_1024x1024"] = dict(ms=ms, TFLOPs=4 * flops_pass / ms / 1e9)
+    a = lz.autocorrelation_2d(ctx, img)
+    res["max_abs_offzero_acf2"] = float(a.flatten()[1:].abs().max())
+    ctx.close()
+    return res
+
+
+# ---------------------------------------------------------------------------------------------
 def bench_batch(lz, torch, steps, plain_sample=256):
     from paper_1201_3114_amd import workloads
 
@@ -428,7 +472,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--only", choices=["all", "plain", "batch", "serve", "variants", "copycal"], default="all")
+    ap.add_argument("--only", choices=["all", "plain", "batch", "serve", "variants", "diag", "copycal"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200_000)
     ap.add_argument("--serve-qps", type=float, default=0.0, help="0 = 0.7 x plain-path capacity")
@@ -505,6 +549,9 @@ def main():
         log("integrator formats and sequential version ...")
         out["integrator_formats"] = bench_variants(lz, torch)
         out["sequential_version"] = bench_sequential(lz, torch)
+    if args.only in ("all", "diag"):
+        log("diagnostics ...")
+        out["diagnostics"] = bench_diag(lz, torch)
     if args.only in ("all", "serve"):
         from paper_1201_3114_amd import workloads
 
