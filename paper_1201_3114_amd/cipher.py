@@ -317,8 +317,11 @@ def histogram(ctx: Context, data: torch.Tensor, stream=None) -> torch.Tensor:
 
 def entropy(ctx: Context, hist: torch.Tensor, stream=None) -> float:
     """Shannon entropy in bits per byte of a device histogram (Section 4), computed on the device."""
+    if hist.dtype != torch.int64 or hist.numel() != 256 or not hist.is_cuda or not hist.is_contiguous():
+        raise ValueError("expected the 256-bin int64 device histogram of histogram()")
     out = torch.empty(1, dtype=torch.float64, device=ctx.device)
-    check(B.lib.lz_entropy(ctx.handle, _dev_ptr(hist), ctypes.c_void_p(out.data_ptr()), _stream(stream, ctx.device)))
+    check(B.lib.lz_entropy(ctx.handle, ctypes.c_void_p(hist.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                           _stream(stream, ctx.device)))
     return float(out.item())
 
 

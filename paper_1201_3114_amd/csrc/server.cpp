@@ -443,7 +443,7 @@ extern "C" int lz_server_create(lz_ctx *c, const lz_server_config *cfg, lz_serve
     }
     s->max_chains = cfg->max_chains ? cfg->max_chains : (uint32_t)c->dev.cus * 4 * 4 * 64;
     s->max_reqs = s->max_chains;
-    s->max_new = std::min<uint32_t>(s->max_reqs, 32768);
+    s->max_new = std::min<uint32_t>(s->max_reqs, 2048);  // admissions per tick (staging size)
     int tile = 16;
     while (tile < (int)s->cfg.tick_bytes && tile < 128) tile *= 2;
     s->shape = KernelShape{1, 256, tile, 4};
