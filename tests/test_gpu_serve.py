@@ -157,3 +157,69 @@ def test_serve_submit_many_replay(lz):
         assert a == arr[r["id"]] and adm >= a and dn >= adm
         n_out = r["n"] if r["dec"] else r["n"] + 24
         assert np.array_equal(host(r["dst"])[:n_out], _expected(ctx, r)), r["id"]
+
+
+def test_serve_workload_prefix_vs_batched_and_oracle(lz):
+    """The first 2,000 requests of the 200,000-request serving workload (lognormal sizes, mixed
+    directions, 16..64-byte passwords, Poisson arrivals at 12,000 requests/s) at full parameters
+    (n_it 3000): every result equals the batched path (bit-identical to the plain path) and a seeded
+    1% sample, at most 1 MiB in all, equals the oracle."""
+    import torch
+
+    from paper_1201_3114_amd import workloads
+
+    count = 2000
+    tr = workloads.serve_trace(count=count, qps=12000.0)
+    sizes = tr.sizes.astype(np.int64)
+    rng = np.random.default_rng(workloads.SEED["serve"] + 1)
+    P_all = rng.integers(0, 256, int(sizes.sum()), dtype=np.uint8)
+    in_off = np.zeros(count, np.int64)
+    in_off[1:] = np.cumsum(sizes[:-1])
+    ctx = lz.Context(0)
+    d_P = to_dev(P_all)
+    c_off, c_tot = lz.packed_offsets(sizes, 24)
+    c_off = c_off.astype(np.int64)
+    d_C = torch.empty(int(c_tot), dtype=torch.uint8, device="cuda")
+    b = lz.Batch(ctx, False, sizes, tr.passwords, d_P, in_off, d_C, c_off)
+    b.launch()
+    torch.cuda.synchronize()
+    b.close()
+    C_all = host(d_C)
+    out_len = np.where(tr.decrypt == 1, sizes, sizes + 24)
+    o_off = np.zeros(count, np.int64)
+    o_off[1:] = np.cumsum(out_len[:-1])
+    d_out = torch.zeros(int(out_len.sum()), dtype=torch.uint8, device="cuda")
+    src = [d_C[int(c_off[i]):].data_ptr() if tr.decrypt[i] else d_P[int(in_off[i]):].data_ptr() for i in range(count)]
+    dst = [d_out[int(o_off[i]):].data_ptr() for i in range(count)]
+    ns = [int(sizes[i]) + (24 if tr.decrypt[i] else 0) for i in range(count)]
+    srv = lz.Server(ctx, hbm_budget=8 << 30, tick_bytes=16)
+    base = lz.now_ns() + 100_000_000
+    arr = [base + int(t * 1e9) for t in tr.arrival_s]
+    say("serving", count, "requests,", int(sizes.sum()), "bytes")
+    srv.submit_many(list(range(count)), [bool(d) for d in tr.decrypt], tr.passwords, src, ns, dst, arr)
+    got = _drain(srv, count, timeout_s=240)
+    srv.close()
+    out = host(d_out)
+    for i in range(count):
+        assert got[i][1] == 0, i
+        a, n = int(o_off[i]), int(out_len[i])
+        want = (P_all[in_off[i]:in_off[i] + sizes[i]] if tr.decrypt[i]
+                else C_all[c_off[i]:c_off[i] + sizes[i] + 24])
+        assert np.array_equal(out[a:a + n], want), i
+    pick, total = [], 0
+    for i in np.random.default_rng(workloads.SEED["serve"] + 2).permutation(count):
+        if len(pick) == count // 100:
+            break
+        if total + sizes[i] <= 1 << 20:
+            pick.append(int(i))
+            total += int(sizes[i])
+    say("oracle sample", len(pick), "requests,", total, "bytes")
+    assert len(pick) >= 10
+    for i in pick:
+        a, n, pw = int(o_off[i]), int(sizes[i]), tr.passwords[i]
+        P = P_all[in_off[i]:in_off[i] + n]
+        if tr.decrypt[i]:
+            back, ok = oracle.decrypt(pw, C_all[c_off[i]:c_off[i] + n + 24], nthreads=8)
+            assert ok and np.array_equal(back, P) and np.array_equal(out[a:a + n], back), i
+        else:
+            assert np.array_equal(out[a:a + n + 24], oracle.encrypt(pw, P, nthreads=8)), i
