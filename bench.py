@@ -147,9 +147,21 @@ def bench_cpu_baseline(target_s: float = 12.0):
     Q, ok = oracle.decrypt(pw, C, nthreads=threads)
     td = time.perf_counter() - t
     assert ok and np.array_equal(Q, sample)
+    # one thread, on 16 blocks, for the per-core rate
+    one = P[:16 * 256]
+    t = time.perf_counter()
+    oracle.encrypt(pw, one, nthreads=1)
+    t1 = time.perf_counter() - t
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=2 * S / (te + td) / GB, unit="GB/s", cores=threads, kind="oracle",
                 sample=f"first {S} bytes ({S // 256} blocks) of the 64 MiB message, encrypt then decrypt, "
-                       f"{threads} pthreads; enc {te:.2f} s, dec {td:.2f} s")
+                       f"{threads} pthreads; enc {te:.2f} s, dec {td:.2f} s",
+                one_thread_GBps=len(one) / t1 / GB, host_cores=cores, cpu_model=model)
 
 
 # ---------------------------------------------------------------------------------------------
