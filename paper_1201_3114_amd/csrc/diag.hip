@@ -62,28 +62,50 @@ __global__ __launch_bounds__(DIAG_WG) void histogram_kernel(const uint8_t *data,
     if (c) atomicAdd(&hist[threadIdx.x], c);
 }
 
-// S_k = sum_{i < n-k} x_i x_{i+k} for k = 0..L.  A workgroup stages TILE + L bytes in LDS;
-// each thread owns lags k = threadIdx.x, threadIdx.x + 256, ...
-constexpr int AC_TILE = 4096;
+// S_k = sum_{i < n-k} x_i x_{i+k} for k = 0..L.  A workgroup owns AC_TILE
+// positions i and stages them, plus the L + 4 bytes after them, in LDS (zero
+// past n, so out-of-range products vanish).  A work item is a group of four
+// consecutive lags 4g..4g+3 over a run of rows: per four rows it reads one
+// aligned word of x_i and one new aligned word of the shifted window, forms the
+// three byte-shifted windows with alignbyte, and accumulates four-byte dot
+// products (v_dot4_u32_u8) in 32-bit sums (at most 4096 * 255^2 < 2^32).
+constexpr int AC_TILE = 4096;  // a multiple of 4
 
 __global__ __launch_bounds__(DIAG_WG) void lagsum_kernel(const uint8_t *data, uint64_t n, uint32_t L,
                                                           unsigned long long *sums) {
-    extern __shared__ uint8_t t[];
+    extern __shared__ uint32_t t32[];
+    uint8_t *t = reinterpret_cast<uint8_t *>(t32);
     const uint64_t i0 = (uint64_t)blockIdx.x * AC_TILE;
-    const uint32_t span = AC_TILE + L;
+    const uint32_t span = AC_TILE + ((L + 3) & ~3u) + 8;
     for (uint32_t j = threadIdx.x; j < span; j += DIAG_WG) t[j] = i0 + j < n ? data[i0 + j] : 0;
     __syncthreads();
-    const uint32_t rows = n - i0 < (uint64_t)AC_TILE ? (uint32_t)(n - i0) : (uint32_t)AC_TILE;
-    for (uint32_t k = threadIdx.x; k <= L; k += DIAG_WG) {
-        // positions i0 + r with r < rows and i0 + r + k < n contribute
-        const uint64_t lim = n - i0 > k ? n - i0 - k : 0;
-        const uint32_t rk = lim < rows ? (uint32_t)lim : rows;
-        uint64_t s = 0;
-        for (uint32_t r = 0; r < rk; ++r) s += (uint32_t)t[r] * (uint32_t)t[r + k];
-        if (s) atomicAdd(&sums[k], (unsigned long long)s);
+    const uint64_t left = n - i0;
+    const uint32_t rows = left < (uint64_t)AC_TILE ? (uint32_t)((left + 3) & ~3ull) : (uint32_t)AC_TILE;
+    const uint32_t G = (L + 4) / 4;                         // lag groups: 4g .. 4g + 3 covers 0..L
+    const uint32_t P = G >= DIAG_WG ? 1 : DIAG_WG / G;      // row runs per group
+    const uint32_t plen = ((rows / 4 + P - 1) / P) * 4;     // rows per run, a multiple of 4
+    for (uint32_t item = threadIdx.x; item < G * P; item += DIAG_WG) {
+        const uint32_t g = item % G, p = item / G;
+        const uint32_t r_lo = p * plen;
+        const uint32_t r_hi = r_lo + plen < rows ? r_lo + plen : rows;
+        if (r_lo >= r_hi) continue;
+        const uint32_t k0 = 4 * g;
+        uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        uint32_t w0 = t32[(r_lo + k0) / 4];
+        for (uint32_t r = r_lo; r < r_hi; r += 4) {
+            const uint32_t a = t32[r / 4];
+            const uint32_t w1 = t32[(r + k0) / 4 + 1];
+            s0 = __builtin_amdgcn_udot4(a, w0, s0, false);
+            s1 = __builtin_amdgcn_udot4(a, __builtin_amdgcn_alignbyte(w1, w0, 1), s1, false);
+            s2 = __builtin_amdgcn_udot4(a, __builtin_amdgcn_alignbyte(w1, w0, 2), s2, false);
+            s3 = __builtin_amdgcn_udot4(a, __builtin_amdgcn_alignbyte(w1, w0, 3), s3, false);
+            w0 = w1;
+        }
+        const uint32_t sk[4] = {s0, s1, s2, s3};
+        for (int q = 0; q < 4; ++q)
+            if (k0 + q <= L && sk[q]) atomicAdd(&sums[k0 + q], (unsigned long long)sk[q]);
     }
 }
-
 
 // ---- entropy and the normalised 1-D autocorrelation -------------------------------------
 
@@ -312,7 +334,8 @@ extern "C" int lz_lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t 
     if (n == 0) return LZ_OK;
     const uint64_t blocks = (n + AC_TILE - 1) / AC_TILE;
     if (blocks > 0x7FFFFFFFull) return fail(LZ_E_INVAL, "input too long");
-    hipLaunchKernelGGL(lagsum_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), (size_t)AC_TILE + max_lag, s, d_data,
+    const size_t lds = (size_t)AC_TILE + ((max_lag + 3) & ~3u) + 8;
+    hipLaunchKernelGGL(lagsum_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), lds, s, d_data,
                        (uint64_t)n, max_lag, reinterpret_cast<unsigned long long *>(d_sums));
     LZ_HIP(hipGetLastError());
     return LZ_OK;
