@@ -191,7 +191,7 @@ def test_serve_workload_prefix_vs_batched_and_oracle(lz):
     d_out = torch.zeros(int(out_len.sum()), dtype=torch.uint8, device="cuda")
     src = [d_C[int(c_off[i]):].data_ptr() if tr.decrypt[i] else d_P[int(in_off[i]):].data_ptr() for i in range(count)]
     dst = [d_out[int(o_off[i]):].data_ptr() for i in range(count)]
-    ns = [int(sizes[i]) + (24 if tr.decrypt[i] else 0) for i in range(count)]
+    ns = [int(v) for v in sizes]  # plaintext lengths in both directions
     srv = lz.Server(ctx, hbm_budget=8 << 30, tick_bytes=16)
     base = lz.now_ns() + 100_000_000
     arr = [base + int(t * 1e9) for t in tr.arrival_s]
