@@ -62,48 +62,75 @@ __global__ __launch_bounds__(DIAG_WG) void histogram_kernel(const uint8_t *data,
     if (c) atomicAdd(&hist[threadIdx.x], c);
 }
 
-// S_k = sum_{i < n-k} x_i x_{i+k} for k = 0..L.  A workgroup owns AC_TILE
-// positions i and stages them, plus the L + 4 bytes after them, in LDS (zero
-// past n, so out-of-range products vanish).  A work item is a group of four
-// consecutive lags 4g..4g+3 over a run of rows: per four rows it reads one
+// S_k = sum_{i < n-k} x_i x_{i+k} for k = 0..L.  A workgroup takes tiles of
+// AC_TILE positions i in turn and stages each, plus the L + 4 bytes after it, in
+// LDS (zero past n, so out-of-range products vanish).  A work item is a group of
+// four consecutive lags 4g..4g+3 over a run of rows: per four rows it reads one
 // aligned word of x_i and one new aligned word of the shifted window, forms the
 // three byte-shifted windows with alignbyte, and accumulates four-byte dot
-// products (v_dot4_u32_u8) in 32-bit sums (at most 4096 * 255^2 < 2^32).
-constexpr int AC_TILE = 4096;  // a multiple of 4
+// products (v_dot4_u32_u8) in 32-bit sums (at most AC_TILE * 255^2 < 2^32).
+// For L < AC_LDS_LAGS the sums of all items and tiles meet in 64-bit LDS
+// counters, so a workgroup issues one global atomic per lag; beyond that each
+// item adds its sums to the global counters directly.
+constexpr int AC_TILE = 16384;         // a multiple of 4
+constexpr uint32_t AC_LDS_LAGS = 4096;
+
+size_t lagsum_lds_bytes(uint32_t L) {
+    const size_t acc = L < AC_LDS_LAGS ? ((size_t)(L + 1) * 8 + 15) / 16 * 16 : 0;
+    return acc + AC_TILE + ((L + 3) & ~3u) + 8;
+}
 
 __global__ __launch_bounds__(DIAG_WG) void lagsum_kernel(const uint8_t *data, uint64_t n, uint32_t L,
                                                           unsigned long long *sums) {
-    extern __shared__ uint32_t t32[];
+    extern __shared__ uint32_t lds[];
+    const bool use_acc = L < AC_LDS_LAGS;
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(lds);
+    const size_t acc_words = use_acc ? ((size_t)(L + 1) * 8 + 15) / 16 * 4 : 0;
+    uint32_t *t32 = lds + acc_words;
     uint8_t *t = reinterpret_cast<uint8_t *>(t32);
-    const uint64_t i0 = (uint64_t)blockIdx.x * AC_TILE;
+    if (use_acc)
+        for (uint32_t k = threadIdx.x; k <= L; k += DIAG_WG) acc[k] = 0;
     const uint32_t span = AC_TILE + ((L + 3) & ~3u) + 8;
-    for (uint32_t j = threadIdx.x; j < span; j += DIAG_WG) t[j] = i0 + j < n ? data[i0 + j] : 0;
-    __syncthreads();
-    const uint64_t left = n - i0;
-    const uint32_t rows = left < (uint64_t)AC_TILE ? (uint32_t)((left + 3) & ~3ull) : (uint32_t)AC_TILE;
     const uint32_t G = (L + 4) / 4;                         // lag groups: 4g .. 4g + 3 covers 0..L
     const uint32_t P = G >= DIAG_WG ? 1 : DIAG_WG / G;      // row runs per group
-    const uint32_t plen = ((rows / 4 + P - 1) / P) * 4;     // rows per run, a multiple of 4
-    for (uint32_t item = threadIdx.x; item < G * P; item += DIAG_WG) {
-        const uint32_t g = item % G, p = item / G;
-        const uint32_t r_lo = p * plen;
-        const uint32_t r_hi = r_lo + plen < rows ? r_lo + plen : rows;
-        if (r_lo >= r_hi) continue;
-        const uint32_t k0 = 4 * g;
-        uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        uint32_t w0 = t32[(r_lo + k0) / 4];
-        for (uint32_t r = r_lo; r < r_hi; r += 4) {
-            const uint32_t a = t32[r / 4];
-            const uint32_t w1 = t32[(r + k0) / 4 + 1];
-            s0 = __builtin_amdgcn_udot4(a, w0, s0, false);
-            s1 = __builtin_amdgcn_udot4(a, __builtin_amdgcn_alignbyte(w1, w0, 1), s1, false);
-            s2 = __builtin_amdgcn_udot4(a, __builtin_amdgcn_alignbyte(w1, w0, 2), s2, false);
-            s3 = __builtin_amdgcn_udot4(a, __builtin_amdgcn_alignbyte(w1, w0, 3), s3, false);
-            w0 = w1;
+    const uint64_t tiles = (n + AC_TILE - 1) / AC_TILE;
+    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const uint64_t i0 = tile * AC_TILE;
+        __syncthreads();  // the previous tile's reads are done
+        for (uint32_t j = threadIdx.x; j < span; j += DIAG_WG) t[j] = i0 + j < n ? data[i0 + j] : 0;
+        __syncthreads();
+        const uint64_t left = n - i0;
+        const uint32_t rows = left < (uint64_t)AC_TILE ? (uint32_t)((left + 3) & ~3ull) : (uint32_t)AC_TILE;
+        const uint32_t plen = ((rows / 4 + P - 1) / P) * 4;  // rows per run, a multiple of 4
+        for (uint32_t item = threadIdx.x; item < G * P; item += DIAG_WG) {
+            const uint32_t g = item % G, p = item / G;
+            const uint32_t r_lo = p * plen;
+            const uint32_t r_hi = r_lo + plen < rows ? r_lo + plen : rows;
+            if (r_lo >= r_hi) continue;
+            const uint32_t k0 = 4 * g;
+            uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+            uint32_t w0 = t32[(r_lo + k0) / 4];
+            for (uint32_t r = r_lo; r < r_hi; r += 4) {
+                const uint32_t a = t32[r / 4];
+                const uint32_t w1 = t32[(r + k0) / 4 + 1];
+                s0 = __builtin_amdgcn_udot4(a, w0, s0, false);
+                s1 = __builtin_amdgcn_udot4(a, __builtin_amdgcn_alignbyte(w1, w0, 1), s1, false);
+                s2 = __builtin_amdgcn_udot4(a, __builtin_amdgcn_alignbyte(w1, w0, 2), s2, false);
+                s3 = __builtin_amdgcn_udot4(a, __builtin_amdgcn_alignbyte(w1, w0, 3), s3, false);
+                w0 = w1;
+            }
+            const uint32_t sk[4] = {s0, s1, s2, s3};
+            for (int q = 0; q < 4; ++q) {
+                if (k0 + q > L || sk[q] == 0) continue;
+                if (use_acc) atomicAdd(&acc[k0 + q], (unsigned long long)sk[q]);
+                else atomicAdd(&sums[k0 + q], (unsigned long long)sk[q]);
+            }
         }
-        const uint32_t sk[4] = {s0, s1, s2, s3};
-        for (int q = 0; q < 4; ++q)
-            if (k0 + q <= L && sk[q]) atomicAdd(&sums[k0 + q], (unsigned long long)sk[q]);
+    }
+    if (use_acc) {
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k <= L; k += DIAG_WG)
+            if (acc[k]) atomicAdd(&sums[k], acc[k]);
     }
 }
 
@@ -332,10 +359,9 @@ extern "C" int lz_lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t 
     LZ_HIP(hipSetDevice(c->device));
     LZ_HIP(launch_fill_u64(reinterpret_cast<unsigned long long *>(d_sums), (size_t)max_lag + 1, s));
     if (n == 0) return LZ_OK;
-    const uint64_t blocks = (n + AC_TILE - 1) / AC_TILE;
-    if (blocks > 0x7FFFFFFFull) return fail(LZ_E_INVAL, "input too long");
-    const size_t lds = (size_t)AC_TILE + ((max_lag + 3) & ~3u) + 8;
-    hipLaunchKernelGGL(lagsum_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), lds, s, d_data,
+    uint64_t blocks = (n + AC_TILE - 1) / AC_TILE;
+    if (blocks > (uint64_t)c->dev.cus * 2) blocks = (uint64_t)c->dev.cus * 2;
+    hipLaunchKernelGGL(lagsum_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), lagsum_lds_bytes(max_lag), s, d_data,
                        (uint64_t)n, max_lag, reinterpret_cast<unsigned long long *>(d_sums));
     LZ_HIP(hipGetLastError());
     return LZ_OK;

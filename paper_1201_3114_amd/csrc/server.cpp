@@ -134,8 +134,10 @@ struct lz_server {
     uint32_t *h_zero_ids = nullptr;
     TickSlot ts[2];
     int cur = 0;
-    hipStream_t stream = nullptr;       // installs, input copies, ticks
+    hipStream_t stream = nullptr;       // installs, ticks
+    hipStream_t in_stream = nullptr;    // input copies of admitted requests (overlap the running tick)
     hipStream_t copy_stream = nullptr;  // completion reads, zeroing, output copies
+    hipEvent_t ev_in = nullptr;         // orders a tick after its requests' input copies
     Arena arena;
     // host bookkeeping (server thread only)
     std::vector<uint32_t> free_slots;
@@ -302,10 +304,13 @@ int server_step(lz_server *s) {
             t.h_meta[3 * i + 2] = n_idx;
             std::memcpy(t.h_idx + n_idx, r->slots.data(), r->nb * sizeof(uint32_t));
             n_idx += r->nb;
-            if (in_len(*r)) LZ_HIP(hipMemcpyAsync(req_in(s, r), r->src, in_len(*r), hipMemcpyDefault, st));
+            if (in_len(*r))
+                LZ_HIP(hipMemcpyAsync(req_in(s, r), r->src, in_len(*r), hipMemcpyDefault, s->in_stream));
             r->active_idx = s->active.size();
             s->active.push_back(r);
         }
+        LZ_HIP(hipEventRecord(s->ev_in, s->in_stream));
+        LZ_HIP(hipStreamWaitEvent(st, s->ev_in, 0));
         LZ_HIP(hipMemcpyAsync(t.d_req, t.h_req, k * sizeof(ReqDesc), hipMemcpyHostToDevice, st));
         LZ_HIP(hipMemcpyAsync(t.d_meta, t.h_meta, 3 * k * sizeof(uint32_t), hipMemcpyHostToDevice, st));
         LZ_HIP(hipMemcpyAsync(t.d_idx, t.h_idx, n_idx * sizeof(uint32_t), hipMemcpyHostToDevice, st));
@@ -394,6 +399,7 @@ void server_free(lz_server *s) {
     if (!s) return;
     hipSetDevice(s->ctx->device);
     if (s->stream) hipStreamSynchronize(s->stream);
+    if (s->in_stream) hipStreamSynchronize(s->in_stream);
     if (s->copy_stream) hipStreamSynchronize(s->copy_stream);
     hipFree(s->arena_mem);
     hipFree(s->slots);
@@ -415,7 +421,9 @@ void server_free(lz_server *s) {
         if (t.ev_end) hipEventDestroy(t.ev_end);
     }
     if (s->stream) hipStreamDestroy(s->stream);
+    if (s->in_stream) hipStreamDestroy(s->in_stream);
     if (s->copy_stream) hipStreamDestroy(s->copy_stream);
+    if (s->ev_in) hipEventDestroy(s->ev_in);
     while (!s->pending.empty()) {
         delete s->pending.top();
         s->pending.pop();
@@ -483,6 +491,8 @@ extern "C" int lz_server_create(lz_ctx *c, const lz_server_config *cfg, lz_serve
     }
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->in_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming);
     if (e != hipSuccess) {
         int rc = hip_fail(e, "server allocation");
         server_free(s);
