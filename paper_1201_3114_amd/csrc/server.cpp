@@ -135,9 +135,9 @@ struct lz_server {
     TickSlot ts[2];
     int cur = 0;
     hipStream_t stream = nullptr;       // installs, ticks
-    hipStream_t in_stream = nullptr;    // input copies of admitted requests (overlap the running tick)
+    hipStream_t in_stream = nullptr;    // staging of the next tick (overlaps the running tick)
     hipStream_t copy_stream = nullptr;  // completion reads, zeroing, output copies
-    hipEvent_t ev_in = nullptr;         // orders a tick after its requests' input copies
+    hipEvent_t ev_in = nullptr;         // orders a tick after its staging
     Arena arena;
     // host bookkeeping (server thread only)
     std::vector<uint32_t> free_slots;
@@ -272,6 +272,9 @@ int complete_tick(lz_server *s, TickSlot &t) {
 // process the other slot's (previous) tick while the new one runs.
 int server_step(lz_server *s) {
     hipStream_t st = s->stream;
+    // everything a tick needs before it runs (input copies, request records, chain list,
+    // counter reset) goes on the staging stream, overlapping the tick that is running now
+    hipStream_t pre = s->in_stream;
     TickSlot &t = s->ts[s->cur];
     if (t.in_flight)
         if (int rc = complete_tick(s, t)) return rc;
@@ -304,17 +307,14 @@ int server_step(lz_server *s) {
             t.h_meta[3 * i + 2] = n_idx;
             std::memcpy(t.h_idx + n_idx, r->slots.data(), r->nb * sizeof(uint32_t));
             n_idx += r->nb;
-            if (in_len(*r))
-                LZ_HIP(hipMemcpyAsync(req_in(s, r), r->src, in_len(*r), hipMemcpyDefault, s->in_stream));
+            if (in_len(*r)) LZ_HIP(hipMemcpyAsync(req_in(s, r), r->src, in_len(*r), hipMemcpyDefault, pre));
             r->active_idx = s->active.size();
             s->active.push_back(r);
         }
-        LZ_HIP(hipEventRecord(s->ev_in, s->in_stream));
-        LZ_HIP(hipStreamWaitEvent(st, s->ev_in, 0));
-        LZ_HIP(hipMemcpyAsync(t.d_req, t.h_req, k * sizeof(ReqDesc), hipMemcpyHostToDevice, st));
-        LZ_HIP(hipMemcpyAsync(t.d_meta, t.h_meta, 3 * k * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-        LZ_HIP(hipMemcpyAsync(t.d_idx, t.h_idx, n_idx * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-        LZ_HIP(launch_install(s->reqs, s->slots, t.d_req, t.d_meta, t.d_idx, (uint32_t)k, s->ctx->prm.block_len, st));
+        LZ_HIP(hipMemcpyAsync(t.d_req, t.h_req, k * sizeof(ReqDesc), hipMemcpyHostToDevice, pre));
+        LZ_HIP(hipMemcpyAsync(t.d_meta, t.h_meta, 3 * k * sizeof(uint32_t), hipMemcpyHostToDevice, pre));
+        LZ_HIP(hipMemcpyAsync(t.d_idx, t.h_idx, n_idx * sizeof(uint32_t), hipMemcpyHostToDevice, pre));
+        LZ_HIP(launch_install(s->reqs, s->slots, t.d_req, t.d_meta, t.d_idx, (uint32_t)k, s->ctx->prm.block_len, pre));
     }
     // the chains that still have bytes to process: each request's full chains until they end,
     // its last chain until it ends (the tick count of each is known at admission)
@@ -337,8 +337,10 @@ int server_step(lz_server *s) {
         if (tr < r->ticks_full || tr < r->ticks_tail) r->ticks_run++;
     }
     if (n_list) {
-        LZ_HIP(hipMemcpyAsync(t.d_list, t.h_list, n_list * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-        LZ_HIP(launch_fill_u64(reinterpret_cast<unsigned long long *>(t.d_done), 1, st));
+        LZ_HIP(hipMemcpyAsync(t.d_list, t.h_list, n_list * sizeof(uint32_t), hipMemcpyHostToDevice, pre));
+        LZ_HIP(launch_fill_u64(reinterpret_cast<unsigned long long *>(t.d_done), 1, pre));
+        LZ_HIP(hipEventRecord(s->ev_in, pre));
+        LZ_HIP(hipStreamWaitEvent(st, s->ev_in, 0));
         TickDev td;
         td.slots = s->slots;
         td.reqs = s->reqs;
