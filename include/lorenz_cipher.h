@@ -134,7 +134,9 @@ const char *lz_last_error(void);
  * defaults).  The context owns a small device workspace (tag accumulators,
  * statuses) and the tuned launch shape.  Calls that share a context are
  * ordered: a call on a different stream than the previous call first waits
- * for the previous call's work.  LZ_E_HIP if the device is unavailable. */
+ * for the previous call's work.  A context may be used by one host thread at
+ * a time (servers and streams created from it run their own work and may be
+ * used concurrently with it).  LZ_E_HIP if the device is unavailable. */
 int lz_context_create(int device, const lz_params *prm, lz_ctx **out);
 int lz_context_destroy(lz_ctx *ctx);
 
