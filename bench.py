@@ -238,9 +238,11 @@ def bench_diag(lz, torch, reps=5):
     """Section 4 analyses on ciphertext-like (uniform random) bytes: histogram of 64 MiB (HBM-bound),
     the autocorrelation up to lag 256 of 16 MiB, and the 2-D power spectrum and autocorrelation
     matrix of a 1024 x 1024 byte image (two / four DFT passes, binary64 FMA)."""
+    from paper_1201_3114_amd import workloads
+
     ctx = lz.Context(0)
     g = torch.Generator(device="cuda")
-    g.manual_seed(130)
+    g.manual_seed(workloads.SEED["diagnostics"])
     x = torch.randint(0, 256, (64 * MiB,), dtype=torch.uint8, device="cuda", generator=g)
     img = x[:1 << 20].view(1024, 1024)
     stream = torch.cuda.current_stream()

@@ -16,7 +16,8 @@ import numpy as np
 KiB, MiB = 1024, 1024 * 1024
 
 # seeds of the five configurations
-SEED = {"plain_64k": 100, "plain_64m": 101, "batch": 102, "batch_integrity": 103, "serve": 104, "sequential": 105}
+SEED = {"plain_64k": 100, "plain_64m": 101, "batch": 102, "batch_integrity": 103, "serve": 104, "sequential": 105,
+        "serve_data": 106, "serve_sample": 107, "diagnostics": 108}
 
 
 def password(rng: np.random.Generator, n: int) -> bytes:

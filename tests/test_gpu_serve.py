@@ -171,7 +171,7 @@ def test_serve_workload_prefix_vs_batched_and_oracle(lz):
     count = 2000
     tr = workloads.serve_trace(count=count, qps=12000.0)
     sizes = tr.sizes.astype(np.int64)
-    rng = np.random.default_rng(workloads.SEED["serve"] + 1)
+    rng = np.random.default_rng(workloads.SEED["serve_data"])
     P_all = rng.integers(0, 256, int(sizes.sum()), dtype=np.uint8)
     in_off = np.zeros(count, np.int64)
     in_off[1:] = np.cumsum(sizes[:-1])
@@ -207,7 +207,7 @@ def test_serve_workload_prefix_vs_batched_and_oracle(lz):
                 else C_all[c_off[i]:c_off[i] + sizes[i] + 24])
         assert np.array_equal(out[a:a + n], want), i
     pick, total = [], 0
-    for i in np.random.default_rng(workloads.SEED["serve"] + 2).permutation(count):
+    for i in np.random.default_rng(workloads.SEED["serve_sample"]).permutation(count):
         if len(pick) == count // 100:
             break
         if total + sizes[i] <= 1 << 20:
