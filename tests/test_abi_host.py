@@ -143,3 +143,39 @@ def test_sha256_via_key_setup_hashlib(B):
         for i in (1, 2, 3):
             msg = b"".join((i * x).to_bytes(32, "little") for x in a)
             assert key.omega[i - 1] == int.from_bytes(hashlib.sha256(msg).digest(), "big") % 4
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """The header compiles as C99 and C++17 with no HIP or torch headers, and a C program that
+    calls only host-side entry points links against the library and runs (no GPU needed)."""
+    import os
+    import subprocess
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    inc = os.path.join(root, "include")
+    libdir = os.path.join(root, "paper_1201_3114_amd")
+    src = tmp_path / "use.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <string.h>
+#include "lorenz_cipher.h"
+int main(void) {
+    lz_params p;
+    lz_key k;
+    if (lz_params_default(&p) != LZ_OK || lz_params_check(&p) != LZ_OK) return 1;
+    if (lz_ciphertext_len(100) != 100 + LZ_TAG_BYTES) return 2;
+    if (lz_key_setup((const uint8_t *)"123456", 6, &p, &k) != LZ_OK) return 3;
+    if (k.mu[0] != 0 || k.mu[1] != 2 || k.mu[2] != 2) return 4;
+    if (lz_key_setup((const uint8_t *)"", 0, &p, &k) != LZ_E_INVAL || strlen(lz_last_error()) == 0) return 5;
+    printf("ok\n");
+    return 0;
+}
+''')
+    for std, comp, name in (("-std=c99", "gcc", "use.c"), ("-std=c++17", "g++", "use.c")):
+        cmd = [comp, std, "-Wall", "-Werror", "-I", inc, "-fsyntax-only"] + (["-x", "c++"] if comp == "g++" else []) + [str(src)]
+        subprocess.run(cmd, check=True)
+    exe = tmp_path / "use"
+    subprocess.run(["gcc", "-std=c99", "-I", inc, str(src), "-L", libdir, "-llorenz_cipher",
+                    f"-Wl,-rpath,{libdir}", "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", (out.returncode, out.stdout, out.stderr)
