@@ -256,12 +256,13 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
     for (int q = 0; q < 4; ++q) off[q] = (uint32_t)(((uint64_t)rmod * (kq + 4 * q)) % N);
     const uint32_t step = (uint32_t)(((uint64_t)rmod * DFT_K) % N);
     uint32_t base = 0;  // rs * k0 mod N
-    // the next stage's inputs and twiddles, loaded into registers while the current stage computes
-    double2 nx[4], nw[4];
-    auto fetch = [&](uint32_t k0) {
+    double ar[4][4], ai[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) ar[i][j] = ai[i][j] = 0.0;
+    for (uint32_t k0 = 0; k0 < N; k0 += DFT_K) {
         for (int q = 0; q < 4; ++q) {
-            const uint32_t k = k0 + kq + 4 * q, c = c0 + cc;
-            nx[q] = (k < N && c < M) ? dft_load(src, (size_t)k * M + c) : make_double2(0.0, 0.0);
+            const uint32_t kk = kq + 4 * q, k = k0 + kk, c = c0 + cc;
+            s_src[kk][cc] = (k < N && c < M) ? dft_load(src, (size_t)k * M + c) : make_double2(0.0, 0.0);
             uint32_t j = base + off[q];
             if (j >= N) j -= N;
             double2 w = make_double2(0.0, 0.0);
@@ -269,22 +270,11 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
                 w = tw[j];
                 w.y *= sign;
             }
-            nw[q] = w;
+            s_tw[kk][cc] = w;
         }
         base += step;
         if (base >= N) base -= N;
-    };
-    double ar[4][4], ai[4][4];
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) ar[i][j] = ai[i][j] = 0.0;
-    fetch(0);
-    for (uint32_t k0 = 0; k0 < N; k0 += DFT_K) {
-        for (int q = 0; q < 4; ++q) {
-            s_src[kq + 4 * q][cc] = nx[q];
-            s_tw[kq + 4 * q][cc] = nw[q];
-        }
         __syncthreads();
-        if (k0 + DFT_K < N) fetch(k0 + DFT_K);
 #pragma unroll 4
         for (int kk = 0; kk < DFT_K; ++kk) {
             double2 w[4], x[4];
