@@ -237,9 +237,9 @@ __global__ void twiddle_kernel(double2 *tw, uint32_t N) {
     tw[j] = make_double2(c, s);
 }
 
-__device__ __forceinline__ double2 dft_load(const uint8_t *p, size_t i) { return make_double2((double)p[i], 0.0); }
-__device__ __forceinline__ double2 dft_load(const double *p, size_t i) { return make_double2(p[i], 0.0); }
-__device__ __forceinline__ double2 dft_load(const double2 *p, size_t i) { return p[i]; }
+__device__ __forceinline__ double2 dft_value(uint8_t v) { return make_double2((double)v, 0.0); }
+__device__ __forceinline__ double2 dft_value(double v) { return make_double2(v, 0.0); }
+__device__ __forceinline__ double2 dft_value(double2 v) { return v; }
 
 template <typename In>
 __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32_t N, uint32_t M, const double2 *tw,
@@ -252,29 +252,40 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
     const uint32_t cc = threadIdx.x % DFT_T, kq = threadIdx.x / DFT_T;
     const uint32_t rs = r0 + cc;  // the twiddle row this thread stages
     const uint32_t rmod = rs < N ? rs : 0;
+    const uint32_t cs = c0 + cc < M ? c0 + cc : M - 1;  // a valid column to load from
     uint32_t off[4];
     for (int q = 0; q < 4; ++q) off[q] = (uint32_t)(((uint64_t)rmod * (kq + 4 * q)) % N);
     const uint32_t step = (uint32_t)(((uint64_t)rmod * DFT_K) % N);
     uint32_t base = 0;  // rs * k0 mod N
-    double ar[4][4], ai[4][4];
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) ar[i][j] = ai[i][j] = 0.0;
-    for (uint32_t k0 = 0; k0 < N; k0 += DFT_K) {
+    // The next stage's inputs and twiddles are loaded into registers while the current stage
+    // computes.  The loads are unconditional, from valid addresses, so that nothing waits for
+    // them before the stage's products; out-of-range entries are zeroed when stored to LDS.
+    In nx[4];
+    double2 nw[4];
+    auto fetch = [&](uint32_t k0) {
         for (int q = 0; q < 4; ++q) {
-            const uint32_t kk = kq + 4 * q, k = k0 + kk, c = c0 + cc;
-            s_src[kk][cc] = (k < N && c < M) ? dft_load(src, (size_t)k * M + c) : make_double2(0.0, 0.0);
+            const uint32_t k = k0 + kq + 4 * q;
+            nx[q] = src[(size_t)(k < N ? k : N - 1) * M + cs];
             uint32_t j = base + off[q];
             if (j >= N) j -= N;
-            double2 w = make_double2(0.0, 0.0);
-            if (k < N && rs < N) {
-                w = tw[j];
-                w.y *= sign;
-            }
-            s_tw[kk][cc] = w;
+            nw[q] = tw[j];
         }
         base += step;
         if (base >= N) base -= N;
+    };
+    double ar[4][4], ai[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) ar[i][j] = ai[i][j] = 0.0;
+    fetch(0);
+    for (uint32_t k0 = 0; k0 < N; k0 += DFT_K) {
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t k = k0 + kq + 4 * q;
+            const bool vx = k < N && c0 + cc < M, vw = k < N && rs < N;
+            s_src[kq + 4 * q][cc] = vx ? dft_value(nx[q]) : make_double2(0.0, 0.0);
+            s_tw[kq + 4 * q][cc] = vw ? make_double2(nw[q].x, sign * nw[q].y) : make_double2(0.0, 0.0);
+        }
         __syncthreads();
+        if (k0 + DFT_K < N) fetch(k0 + DFT_K);
 #pragma unroll 4
         for (int kk = 0; kk < DFT_K; ++kk) {
             double2 w[4], x[4];
