@@ -116,10 +116,28 @@ def bench_plain(lz, torch, steps, warmup):
     enc_ms = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
     dec_ms = [ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]
     ok = bool(torch.equal(Q, dP)) and int(st.item()) == 0
+    # outside the timed steps: the same round trip from and to pinned host memory, PCIe copies included
+    hP = torch.from_numpy(P).pin_memory()
+    hC = torch.empty(n + 24, dtype=torch.uint8).pin_memory()
+    hQ = torch.empty(n, dtype=torch.uint8).pin_memory()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    e[0].record(stream)
+    dP.copy_(hP, non_blocking=True)
+    ctx.encrypt(dP, pw, out=C)
+    hC.copy_(C, non_blocking=True)
+    C.copy_(hC, non_blocking=True)
+    ctx.decrypt(C, pw, out=Q, status=st)
+    hQ.copy_(Q, non_blocking=True)
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    pcie_ms = e[0].elapsed_time(e[1])
+    ok = ok and bool(torch.equal(hQ, hP))
     shape = ctx.get_launch()
     n_it = ctx.params.n_it
     ctx.close()
-    return dict(n=n, wall_s=wall, enc_ms=enc_ms, dec_ms=dec_ms, roundtrip_ok=ok, shape=shape, n_it=n_it)
+    return dict(n=n, wall_s=wall, enc_ms=enc_ms, dec_ms=dec_ms, roundtrip_ok=ok, shape=shape, n_it=n_it,
+                pcie_ms=pcie_ms)
 
 
 def bench_cpu_baseline(target_s: float = 12.0):
@@ -545,6 +563,7 @@ def main():
                                       "tile": sh.tile}},
                    encrypt_GBps=n / (t_enc / args.steps / 1e3) / GB, decrypt_GBps=n / (t_dec / args.steps / 1e3) / GB,
                    wall_s=plain["wall_s"], roundtrip_exact=plain["roundtrip_ok"],
+                   host_buffers_GBps=2 * n / (plain["pcie_ms"] / 1e3) / GB,
                    roofline={"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_OPS_PEAK / 1e12,
                              "unit": "TFLOP/s", "frac": achieved / FP64_VALU_OPS_PEAK, "traffic": profiled_traffic(),
                              "traffic_unit": "bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)",
