@@ -190,3 +190,54 @@ def test_plain_64m_sampled(lz):
         bad[off] ^= 0x10
         with pytest.raises(lz.IntegrityError):
             ctx.decrypt(bad, pw)
+
+
+def test_maximum_message_size(lz):
+    """The largest message the format allows, 2^32 bytes (16,777,216 blocks; the last block's initial
+    condition is r0 + (2^24 - 1) 2^-24): sampled blocks including the first and last equal the oracle,
+    the round trip is exact, a flipped last byte or tag byte is detected, and one byte more is rejected
+    before any work is queued."""
+    import ctypes
+
+    import torch
+
+    from paper_1201_3114_amd import binding as B
+
+    n = 1 << 32
+    Bsz = 256
+    nb = n // Bsz
+    pw = b"maximum size"
+    g = torch.Generator(device="cuda")
+    g.manual_seed(109)
+    say("max size: generating", n, "bytes")
+    dP = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda", generator=g)
+    ctx = _ctx(lz)
+    say("max size: encrypt")
+    C = ctx.encrypt(dP, pw)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(110)
+    blocks = sorted(set([0, 1, nb // 2, nb - 2, nb - 1] + [int(b) for b in rng.integers(0, nb, 11)]))
+    for b in blocks:
+        seg = host(dP[b * Bsz:(b + 1) * Bsz])
+        out, _ = oracle.crypt_block(pw, b, seg)
+        assert np.array_equal(host(C[b * Bsz:(b + 1) * Bsz]), out), b
+    say("max size: decrypt")
+    Q = torch.empty(n, dtype=torch.uint8, device="cuda")
+    st = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    ctx.decrypt(C, pw, out=Q, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and torch.equal(Q, dP)
+    for off in (n - 1, n + 23):
+        C[off] ^= 0x01
+        ctx.decrypt(C, pw, out=Q, status=st)
+        torch.cuda.synchronize()
+        assert int(st.item()) == -2, off
+        assert int(Q[:1 << 20].count_nonzero().item()) == 0 and int(Q[-(1 << 20):].count_nonzero().item()) == 0
+        C[off] ^= 0x01
+    # n = 2^32 + 1 is rejected on the host, before anything is queued
+    pbuf, npw = B.pw_buf(pw)
+    rc = B.lib.lz_encrypt(ctx.handle, pbuf, npw, ctypes.c_void_p(dP.data_ptr()), n + 1,
+                          ctypes.c_void_p(C.data_ptr()), None)
+    assert rc == -1
+    del dP, C, Q
+    torch.cuda.empty_cache()
