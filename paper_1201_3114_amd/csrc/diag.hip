@@ -241,31 +241,37 @@ __device__ __forceinline__ double2 dft_value(uint8_t v) { return make_double2((d
 __device__ __forceinline__ double2 dft_value(double v) { return make_double2(v, 0.0); }
 __device__ __forceinline__ double2 dft_value(double2 v) { return v; }
 
-template <typename In>
+template <typename In, int TR>
 __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32_t N, uint32_t M, const double2 *tw,
                                                             double sign, double2 *dst) {
+    // output tile: TR values of r by DFT_T values of c; a lane holds TR/16 x 4 complex sums
+    constexpr int RI = TR / 16;
+    constexpr int TWQ = TR * DFT_K / DIAG_WG;  // twiddles each thread stages per k stage
     __shared__ double2 s_src[DFT_K][DFT_T];  // [k][c]
-    __shared__ double2 s_tw[DFT_K][DFT_T];   // [k][r]
-    const uint32_t r0 = blockIdx.x * DFT_T, c0 = blockIdx.y * DFT_T;
+    __shared__ double2 s_tw[DFT_K][TR];      // [k][r]
+    const uint32_t r0 = blockIdx.x * TR, c0 = blockIdx.y * DFT_T;
     const uint32_t tr = threadIdx.x % 16, tc = threadIdx.x / 16;  // consecutive lanes: consecutive r
-    // staging role: column cc of the tile, k rows kq + 4q (q = 0..3)
+    // staging roles: column cc of the input tile for k rows kq + 4q; twiddle row tr_s for k rows kt + (DFT_K/TWQ) q
     const uint32_t cc = threadIdx.x % DFT_T, kq = threadIdx.x / DFT_T;
-    const uint32_t rs = r0 + cc;  // the twiddle row this thread stages
+    const uint32_t tr_s = threadIdx.x % TR, kt = threadIdx.x / TR;
+    const uint32_t rs = r0 + tr_s;  // the twiddle row this thread stages
     const uint32_t rmod = rs < N ? rs : 0;
     const uint32_t cs = c0 + cc < M ? c0 + cc : M - 1;  // a valid column to load from
-    uint32_t off[4];
-    for (int q = 0; q < 4; ++q) off[q] = (uint32_t)(((uint64_t)rmod * (kq + 4 * q)) % N);
+    uint32_t off[TWQ];
+    for (int q = 0; q < TWQ; ++q) off[q] = (uint32_t)(((uint64_t)rmod * (kt + (DFT_K / TWQ) * q)) % N);
     const uint32_t step = (uint32_t)(((uint64_t)rmod * DFT_K) % N);
     uint32_t base = 0;  // rs * k0 mod N
     // The next stage's inputs and twiddles are loaded into registers while the current stage
     // computes.  The loads are unconditional, from valid addresses, so that nothing waits for
     // them before the stage's products; out-of-range entries are zeroed when stored to LDS.
     In nx[4];
-    double2 nw[4];
+    double2 nw[TWQ];
     auto fetch = [&](uint32_t k0) {
         for (int q = 0; q < 4; ++q) {
             const uint32_t k = k0 + kq + 4 * q;
             nx[q] = src[(size_t)(k < N ? k : N - 1) * M + cs];
+        }
+        for (int q = 0; q < TWQ; ++q) {
             uint32_t j = base + off[q];
             if (j >= N) j -= N;
             nw[q] = tw[j];
@@ -273,25 +279,27 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
         base += step;
         if (base >= N) base -= N;
     };
-    double ar[4][4], ai[4][4];
-    for (int i = 0; i < 4; ++i)
+    double ar[RI][4], ai[RI][4];
+    for (int i = 0; i < RI; ++i)
         for (int j = 0; j < 4; ++j) ar[i][j] = ai[i][j] = 0.0;
     fetch(0);
     for (uint32_t k0 = 0; k0 < N; k0 += DFT_K) {
         for (int q = 0; q < 4; ++q) {
             const uint32_t k = k0 + kq + 4 * q;
-            const bool vx = k < N && c0 + cc < M, vw = k < N && rs < N;
-            s_src[kq + 4 * q][cc] = vx ? dft_value(nx[q]) : make_double2(0.0, 0.0);
-            s_tw[kq + 4 * q][cc] = vw ? make_double2(nw[q].x, sign * nw[q].y) : make_double2(0.0, 0.0);
+            s_src[kq + 4 * q][cc] = (k < N && c0 + cc < M) ? dft_value(nx[q]) : make_double2(0.0, 0.0);
+        }
+        for (int q = 0; q < TWQ; ++q) {
+            const uint32_t kk = kt + (DFT_K / TWQ) * q, k = k0 + kk;
+            s_tw[kk][tr_s] = (k < N && rs < N) ? make_double2(nw[q].x, sign * nw[q].y) : make_double2(0.0, 0.0);
         }
         __syncthreads();
         if (k0 + DFT_K < N) fetch(k0 + DFT_K);
 #pragma unroll 4
         for (int kk = 0; kk < DFT_K; ++kk) {
-            double2 w[4], x[4];
-            for (int i = 0; i < 4; ++i) w[i] = s_tw[kk][tr + 16 * i];
+            double2 w[RI], x[4];
+            for (int i = 0; i < RI; ++i) w[i] = s_tw[kk][tr + 16 * i];
             for (int j = 0; j < 4; ++j) x[j] = s_src[kk][tc + 16 * j];
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < RI; ++i)
                 for (int j = 0; j < 4; ++j) {
                     ar[i][j] = __builtin_fma(w[i].x, x[j].x, __builtin_fma(-w[i].y, x[j].y, ar[i][j]));
                     ai[i][j] = __builtin_fma(w[i].x, x[j].y, __builtin_fma(w[i].y, x[j].x, ai[i][j]));
@@ -302,7 +310,7 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
     for (int j = 0; j < 4; ++j) {
         const uint32_t c = c0 + tc + 16 * j;
         if (c >= M) continue;
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < RI; ++i) {
             const uint32_t r = r0 + tr + 16 * i;
             if (r < N) dst[(size_t)c * N + r] = make_double2(ar[i][j], ai[i][j]);
         }
@@ -448,12 +456,19 @@ int launch_twiddles(const Dft2 &d, uint32_t h, uint32_t w, hipStream_t s) {
     return LZ_OK;
 }
 
-// dst (M x N) = transpose of (DFT_N along the rows of src (N x M))
+// dst (M x N) = transpose of (DFT_N along the rows of src (N x M)).  Tiles of 64 x 64 outputs, or
+// 32 x 64 when that would leave fewer than two workgroups per CU (more waves to hide latency).
 template <typename In>
-int launch_dft_pass(const In *src, uint32_t N, uint32_t M, const double2 *tw, double sign, double2 *dst,
-                    hipStream_t s) {
-    const dim3 grid((N + DFT_T - 1) / DFT_T, (M + DFT_T - 1) / DFT_T);
-    hipLaunchKernelGGL((dft_pass_kernel<In>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, dst);
+int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, const double2 *tw, double sign,
+                    double2 *dst, hipStream_t s) {
+    const uint64_t tiles64 = (uint64_t)((N + 63) / 64) * ((M + DFT_T - 1) / DFT_T);
+    if (tiles64 < 2 * (uint64_t)c->dev.cus) {
+        const dim3 grid((N + 31) / 32, (M + DFT_T - 1) / DFT_T);
+        hipLaunchKernelGGL((dft_pass_kernel<In, 32>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, dst);
+    } else {
+        const dim3 grid((N + 63) / 64, (M + DFT_T - 1) / DFT_T);
+        hipLaunchKernelGGL((dft_pass_kernel<In, 64>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, dst);
+    }
     LZ_HIP(hipGetLastError());
     return LZ_OK;
 }
@@ -504,8 +519,8 @@ extern "C" int lz_power_spectrum_2d(lz_ctx *c, const uint8_t *d_img, uint32_t h,
     if (int rc = diag_begin(c, s, dft2_bytes(h, w, 0), &ws)) return rc;
     const Dft2 d = dft2_layout(ws, h, w, 0);
     if (int rc = launch_twiddles(d, h, w, s)) return rc;
-    if (int rc = launch_dft_pass<uint8_t>(d_img, h, w, d.tw_h, -1.0, d.a, s)) return rc;  // a: w x h
-    if (int rc = launch_dft_pass<double2>(d.a, w, h, d.tw_w, -1.0, d.b, s)) return rc;   // b: h x w = Z
+    if (int rc = launch_dft_pass<uint8_t>(c, d_img, h, w, d.tw_h, -1.0, d.a, s)) return rc;  // a: w x h
+    if (int rc = launch_dft_pass<double2>(c, d.a, w, h, d.tw_w, -1.0, d.b, s)) return rc;   // b: h x w = Z
     const size_t n = (size_t)h * w;
     hipLaunchKernelGGL(power_kernel, dim3(grid_for(n, c)), dim3(256), 0, s, d.b, n, d_power, 0);
     LZ_HIP(hipGetLastError());
@@ -529,13 +544,13 @@ extern "C" int lz_autocorrelation_2d(lz_ctx *c, const uint8_t *d_img, uint32_t h
                        reinterpret_cast<const unsigned long long *>(hist), (uint64_t)n, den);
     LZ_HIP(hipGetLastError());
     if (int rc = launch_twiddles(d, h, w, s)) return rc;
-    if (int rc = launch_dft_pass<uint8_t>(d_img, h, w, d.tw_h, -1.0, d.a, s)) return rc;  // a: w x h
-    if (int rc = launch_dft_pass<double2>(d.a, w, h, d.tw_w, -1.0, d.b, s)) return rc;   // b: Z, h x w
+    if (int rc = launch_dft_pass<uint8_t>(c, d_img, h, w, d.tw_h, -1.0, d.a, s)) return rc;  // a: w x h
+    if (int rc = launch_dft_pass<double2>(c, d.a, w, h, d.tw_w, -1.0, d.b, s)) return rc;   // b: Z, h x w
     double *pm = reinterpret_cast<double *>(d.a);                                         // a: |Z|^2, DC = 0
     hipLaunchKernelGGL(power_kernel, dim3(grid_for(n, c)), dim3(256), 0, s, d.b, n, pm, 1);
     LZ_HIP(hipGetLastError());
-    if (int rc = launch_dft_pass<double>(pm, h, w, d.tw_h, 1.0, d.b, s)) return rc;       // b: w x h
-    if (int rc = launch_dft_pass<double2>(d.b, w, h, d.tw_w, 1.0, d.a, s)) return rc;     // a: G, h x w
+    if (int rc = launch_dft_pass<double>(c, pm, h, w, d.tw_h, 1.0, d.b, s)) return rc;       // b: w x h
+    if (int rc = launch_dft_pass<double2>(c, d.b, w, h, d.tw_w, 1.0, d.a, s)) return rc;     // a: G, h x w
     hipLaunchKernelGGL(acf2_norm_kernel, dim3(grid_for(n, c)), dim3(256), 0, s, d.a, n, den, d_acf);
     LZ_HIP(hipGetLastError());
     return diag_end(c, s);

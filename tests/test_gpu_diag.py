@@ -114,8 +114,10 @@ def _power_tol(x):
 
 
 @pytest.mark.parametrize("h,w", [(1, 1), (1, 37), (29, 1), (8, 8), (64, 64), (67, 131), (128, 200), (512, 512),
-                                 (3, 4096)])
+                                 (3, 4096), (2048, 2048)])
 def test_power_spectrum_2d(lz, ctx, h, w):
+    """(2048, 2048) has 1,024 tiles of 64 x 64 outputs per pass, so it runs the 64-row tile variant of the
+    DFT pass on a 256-CU device; the smaller sizes run the 32-row variant."""
     rng = np.random.default_rng(100 + h * 7 + w)
     x = rng.integers(0, 256, (h, w), dtype=np.uint8)
     say("power spectrum", h, w)
