@@ -252,6 +252,45 @@ def bench_sequential(lz, torch, count=4096):
 
 
 # ---------------------------------------------------------------------------------------------
+def bench_streaming(lz, torch):
+    """The 64 MiB workload fed through a stream in chunks (one byte more than a power of two, so every
+    update has a partial head and tail block), against the one-shot encrypt, both bit-exact."""
+    from paper_1201_3114_amd import workloads
+
+    P, pw = workloads.plain("plain_64m")
+    n = len(P)
+    dP = torch.from_numpy(P).cuda()
+    ctx = lz.Context(0)
+    stream = torch.cuda.current_stream()
+    one = ctx.encrypt(dP, pw)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    e[0].record(stream)
+    ctx.encrypt(dP, pw, out=one)
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    res = {"one_shot": dict(ms=e[0].elapsed_time(e[1]), encrypt_GBps=n / e[0].elapsed_time(e[1]) / 1e6)}
+    out = torch.empty(n + 24, dtype=torch.uint8, device="cuda")
+    for chunk in ((16 << 20) + 1, (4 << 20) + 1, (1 << 20) + 1):
+        out.zero_()
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        st = lz.Stream(ctx, False, pw)
+        for a in range(0, n, chunk):
+            b = min(a + chunk, n)
+            st.update(dP[a:b], out=out[a:b])
+        out[n:] = st.finish()
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        st.close()
+        ms = e[0].elapsed_time(e[1])
+        res[f"chunks_of_{chunk}"] = dict(updates=(n + chunk - 1) // chunk, ms=ms, encrypt_GBps=n / ms / 1e6,
+                                         equals_one_shot=bool(torch.equal(out, one)))
+    ctx.close()
+    return res
+
+
+# ---------------------------------------------------------------------------------------------
 def bench_diag(lz, torch, reps=5):
     """Section 4 analyses on ciphertext-like (uniform random) bytes: histogram of 64 MiB (HBM-bound),
     the autocorrelation up to lag 256 of 16 MiB, and the 2-D power spectrum and autocorrelation
@@ -504,7 +543,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--only", choices=["all", "plain", "batch", "serve", "variants", "diag", "copycal"], default="all")
+    ap.add_argument("--only", choices=["all", "plain", "batch", "serve", "variants", "stream", "diag", "copycal"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200_000)
     ap.add_argument("--serve-qps", type=float, default=0.0, help="0 = 0.7 x plain-path capacity")
@@ -582,6 +621,9 @@ def main():
         log("integrator formats and sequential version ...")
         out["integrator_formats"] = bench_variants(lz, torch)
         out["sequential_version"] = bench_sequential(lz, torch)
+    if args.only in ("all", "stream"):
+        log("streaming ...")
+        out["streaming"] = bench_streaming(lz, torch)
     if args.only in ("all", "diag"):
         log("diagnostics ...")
         out["diagnostics"] = bench_diag(lz, torch)

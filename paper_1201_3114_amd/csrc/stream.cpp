@@ -4,7 +4,10 @@
 // Each chunk is cut at block boundaries of the parallel version (Section 5):
 // the pending partial block continues from its device-resident checkpoint
 // (r, alpha, mu, Omega), the full blocks run as one plain launch at the right
-// block index, and the remainder starts the next partial block.
+// block index, and the remainder starts the next partial block.  The partial
+// blocks (one chain each, as slow as a whole block) run on an internal stream
+// beside the full blocks, which are independent of them; the caller's stream
+// waits for both before the update's work counts as done.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -28,6 +31,8 @@ struct lz_stream {
     hipEvent_t ev;
     hipStream_t last;
     bool has_last;
+    hipStream_t aux;      // partial blocks (checkpoint chain), ordered among themselves
+    hipEvent_t ev_in, ev_aux;
 };
 
 namespace {
@@ -36,9 +41,13 @@ void stream_free(lz_stream *st) {
     if (!st) return;
     hipSetDevice(st->ctx->device);
     if (st->has_last) hipEventSynchronize(st->ev);
+    if (st->aux) hipStreamSynchronize(st->aux);
     if (st->dmem) hipFree(st->dmem);
     if (st->h_status) hipHostFree(st->h_status);
     if (st->ev) hipEventDestroy(st->ev);
+    if (st->ev_in) hipEventDestroy(st->ev_in);
+    if (st->ev_aux) hipEventDestroy(st->ev_aux);
+    if (st->aux) hipStreamDestroy(st->aux);
     delete st;
 }
 
@@ -74,6 +83,9 @@ extern "C" int lz_stream_open(lz_ctx *c, int decrypt, const uint8_t *pw, size_t 
     if (e == hipSuccess) e = hipMemset(st->dmem, 0, bytes);
     if (e == hipSuccess) e = hipHostMalloc(&st->h_status, sizeof(int32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_aux, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st->aux, hipStreamNonBlocking);
     if (e != hipSuccess) {
         int rc = hip_fail(e, "stream allocation");
         stream_free(st);
@@ -98,31 +110,32 @@ extern "C" int lz_stream_update(lz_stream *st, const uint8_t *d_in, size_t n, ui
     LZ_HIP(hipSetDevice(c->device));
     if (int rc = stream_order(st, s)) return rc;
     const uint64_t B = c->prm.block_len;
-    uint64_t off = 0;
-    // head: continue the pending partial block
     const uint64_t r = st->pos % B;
-    if (r != 0) {
-        const uint64_t h = n < B - r ? n : B - r;
-        LZ_HIP(launch_resume(st->key, c->prm, st->decrypt, st->slot, st->pos / B, d_in, d_out, (uint32_t)h, 0,
-                             r + h == B, st->tag, s));
-        off += h;
-        st->pos += h;
+    const uint64_t h = r == 0 ? 0 : (n < B - r ? n : B - r);  // head: finishes the pending partial block
+    const uint64_t full = (n - h) / B;                          // body: whole blocks
+    const uint64_t rem = n - h - full * B;                      // tail: starts the next partial block
+    const uint64_t pos0 = st->pos;
+    const bool partial = h > 0 || rem > 0;
+    if (partial) {
+        LZ_HIP(hipEventRecord(st->ev_in, s));
+        LZ_HIP(hipStreamWaitEvent(st->aux, st->ev_in, 0));
     }
-    // body: whole blocks in one plain launch starting at block pos / B
-    const uint64_t full = (n - off) / B;
-    if (full > 0) {
-        LZ_HIP(launch_plain(c->shape, st->key, c->prm, st->decrypt, d_in + off, d_out + off, full * B, st->tag, s,
-                            st->pos / B));
-        off += full * B;
-        st->pos += full * B;
-    }
-    // tail: start the next partial block and keep its checkpoint
-    const uint64_t rem = n - off;
+    if (h > 0)
+        LZ_HIP(launch_resume(st->key, c->prm, st->decrypt, st->slot, pos0 / B, d_in, d_out, (uint32_t)h, 0,
+                             r + h == B, st->tag, st->aux));
+    if (full > 0)
+        LZ_HIP(launch_plain(c->shape, st->key, c->prm, st->decrypt, d_in + h, d_out + h, full * B, st->tag, s,
+                            (pos0 + h) / B));
     if (rem > 0) {
-        LZ_HIP(launch_resume(st->key, c->prm, st->decrypt, st->slot, st->pos / B, d_in + off, d_out + off,
-                             (uint32_t)rem, 1, 0, st->tag, s));
-        st->pos += rem;
+        const uint64_t o = h + full * B;
+        LZ_HIP(launch_resume(st->key, c->prm, st->decrypt, st->slot, (pos0 + o) / B, d_in + o, d_out + o,
+                             (uint32_t)rem, 1, 0, st->tag, st->aux));
     }
+    if (partial) {
+        LZ_HIP(hipEventRecord(st->ev_aux, st->aux));
+        LZ_HIP(hipStreamWaitEvent(s, st->ev_aux, 0));
+    }
+    st->pos = pos0 + n;
     return stream_record(st, s);
 }
 
