@@ -4,10 +4,12 @@
 // Each chunk is cut at block boundaries of the parallel version (Section 5):
 // the pending partial block continues from its device-resident checkpoint
 // (r, alpha, mu, Omega), the full blocks run as one plain launch at the right
-// block index, and the remainder starts the next partial block.  The partial
-// blocks (one chain each, as slow as a whole block) run on an internal stream
-// beside the full blocks, which are independent of them; the caller's stream
-// waits for both before the update's work counts as done.
+// block index, and the remainder starts the next partial block.  The two
+// partial blocks (one chain each, as slow as a whole block) run on internal
+// streams beside the full blocks: they are independent of the full blocks and
+// of each other, since the new partial block keeps its checkpoint in a second
+// slot.  The caller's stream waits for all three before the update's work
+// counts as done.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -23,16 +25,17 @@ struct lz_stream {
     lz_key key;
     uint64_t pos;        // bytes consumed so far
     bool finished;
-    void *dmem;          // ChainSlot, then 3 tag words, then the status word
-    ChainSlot *slot;
+    void *dmem;          // two ChainSlots, then 3 tag words (+1 pad), then the status word
+    ChainSlot *slot[2];  // slot[cur] holds the pending partial block's checkpoint
+    int cur;
     unsigned long long *tag;
     int32_t *status;
     int32_t *h_status;   // pinned
     hipEvent_t ev;
     hipStream_t last;
     bool has_last;
-    hipStream_t aux;      // partial blocks (checkpoint chain), ordered among themselves
-    hipEvent_t ev_in, ev_aux;
+    hipStream_t aux[2];   // the head (continues slot[cur]) and the tail (starts slot[cur ^ 1]) of an update
+    hipEvent_t ev_in, ev_aux[2];
 };
 
 namespace {
@@ -41,13 +44,16 @@ void stream_free(lz_stream *st) {
     if (!st) return;
     hipSetDevice(st->ctx->device);
     if (st->has_last) hipEventSynchronize(st->ev);
-    if (st->aux) hipStreamSynchronize(st->aux);
+    for (hipStream_t a : st->aux)
+        if (a) hipStreamSynchronize(a);
     if (st->dmem) hipFree(st->dmem);
     if (st->h_status) hipHostFree(st->h_status);
     if (st->ev) hipEventDestroy(st->ev);
     if (st->ev_in) hipEventDestroy(st->ev_in);
-    if (st->ev_aux) hipEventDestroy(st->ev_aux);
-    if (st->aux) hipStreamDestroy(st->aux);
+    for (int i = 0; i < 2; ++i) {
+        if (st->ev_aux[i]) hipEventDestroy(st->ev_aux[i]);
+        if (st->aux[i]) hipStreamDestroy(st->aux[i]);
+    }
     delete st;
 }
 
@@ -78,23 +84,27 @@ extern "C" int lz_stream_open(lz_ctx *c, int decrypt, const uint8_t *pw, size_t 
         delete st;
         return rc;
     }
-    const size_t bytes = sizeof(ChainSlot) + 4 * sizeof(unsigned long long) + sizeof(int32_t);
+    const size_t bytes = 2 * sizeof(ChainSlot) + 4 * sizeof(unsigned long long) + sizeof(int32_t);
     hipError_t e = hipMalloc(&st->dmem, bytes);
     if (e == hipSuccess) e = hipMemset(st->dmem, 0, bytes);
     if (e == hipSuccess) e = hipHostMalloc(&st->h_status, sizeof(int32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_in, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_aux, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st->aux, hipStreamNonBlocking);
+    for (int i = 0; i < 2; ++i) {
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_aux[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&st->aux[i], hipStreamNonBlocking);
+    }
     if (e != hipSuccess) {
         int rc = hip_fail(e, "stream allocation");
         stream_free(st);
         return rc;
     }
     char *base = static_cast<char *>(st->dmem);
-    st->slot = reinterpret_cast<ChainSlot *>(base);
-    st->tag = reinterpret_cast<unsigned long long *>(base + sizeof(ChainSlot));
-    st->status = reinterpret_cast<int32_t *>(base + sizeof(ChainSlot) + 4 * sizeof(unsigned long long));
+    st->slot[0] = reinterpret_cast<ChainSlot *>(base);
+    st->slot[1] = reinterpret_cast<ChainSlot *>(base + sizeof(ChainSlot));
+    st->cur = 0;
+    st->tag = reinterpret_cast<unsigned long long *>(base + 2 * sizeof(ChainSlot));
+    st->status = reinterpret_cast<int32_t *>(base + 2 * sizeof(ChainSlot) + 4 * sizeof(unsigned long long));
     *out = st;
     return LZ_OK;
 }
@@ -115,25 +125,28 @@ extern "C" int lz_stream_update(lz_stream *st, const uint8_t *d_in, size_t n, ui
     const uint64_t full = (n - h) / B;                          // body: whole blocks
     const uint64_t rem = n - h - full * B;                      // tail: starts the next partial block
     const uint64_t pos0 = st->pos;
-    const bool partial = h > 0 || rem > 0;
-    if (partial) {
-        LZ_HIP(hipEventRecord(st->ev_in, s));
-        LZ_HIP(hipStreamWaitEvent(st->aux, st->ev_in, 0));
+    if (h > 0 || rem > 0) LZ_HIP(hipEventRecord(st->ev_in, s));
+    if (h > 0) {
+        LZ_HIP(hipStreamWaitEvent(st->aux[0], st->ev_in, 0));
+        LZ_HIP(launch_resume(st->key, c->prm, st->decrypt, st->slot[st->cur], pos0 / B, d_in, d_out, (uint32_t)h,
+                             0, r + h == B, st->tag, st->aux[0]));
+        LZ_HIP(hipEventRecord(st->ev_aux[0], st->aux[0]));
     }
-    if (h > 0)
-        LZ_HIP(launch_resume(st->key, c->prm, st->decrypt, st->slot, pos0 / B, d_in, d_out, (uint32_t)h, 0,
-                             r + h == B, st->tag, st->aux));
     if (full > 0)
         LZ_HIP(launch_plain(c->shape, st->key, c->prm, st->decrypt, d_in + h, d_out + h, full * B, st->tag, s,
                             (pos0 + h) / B));
     if (rem > 0) {
+        // a new chain in the other slot, independent of the head's
         const uint64_t o = h + full * B;
-        LZ_HIP(launch_resume(st->key, c->prm, st->decrypt, st->slot, (pos0 + o) / B, d_in + o, d_out + o,
-                             (uint32_t)rem, 1, 0, st->tag, st->aux));
+        LZ_HIP(hipStreamWaitEvent(st->aux[1], st->ev_in, 0));
+        LZ_HIP(launch_resume(st->key, c->prm, st->decrypt, st->slot[st->cur ^ 1], (pos0 + o) / B, d_in + o,
+                             d_out + o, (uint32_t)rem, 1, 0, st->tag, st->aux[1]));
+        LZ_HIP(hipEventRecord(st->ev_aux[1], st->aux[1]));
     }
-    if (partial) {
-        LZ_HIP(hipEventRecord(st->ev_aux, st->aux));
-        LZ_HIP(hipStreamWaitEvent(s, st->ev_aux, 0));
+    if (h > 0) LZ_HIP(hipStreamWaitEvent(s, st->ev_aux[0], 0));
+    if (rem > 0) {
+        LZ_HIP(hipStreamWaitEvent(s, st->ev_aux[1], 0));
+        st->cur ^= 1;
     }
     st->pos = pos0 + n;
     return stream_record(st, s);
@@ -149,7 +162,7 @@ extern "C" int lz_stream_finish(lz_stream *st, uint8_t *d_tag, int32_t *d_status
     const int pending = st->pos % c->prm.block_len != 0;
     const int empty = st->pos == 0;
     int32_t *status = d_status ? d_status : st->status;
-    LZ_HIP(launch_stream_finish(st->slot, pending, empty, st->key, st->tag, st->decrypt, d_tag, status, s));
+    LZ_HIP(launch_stream_finish(st->slot[st->cur], pending, empty, st->key, st->tag, st->decrypt, d_tag, status, s));
     st->finished = true;
     if (!st->decrypt || d_status) return stream_record(st, s);
     LZ_HIP(hipMemcpyAsync(st->h_status, st->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
