@@ -286,6 +286,33 @@ def bench_streaming(lz, torch):
         ms = e[0].elapsed_time(e[1])
         res[f"chunks_of_{chunk}"] = dict(updates=(n + chunk - 1) // chunk, ms=ms, encrypt_GBps=n / ms / 1e6,
                                          equals_one_shot=bool(torch.equal(out, one)))
+    # a 256 MiB message (uniform bytes from torch's device generator) in chunks of 64 MiB + 1 byte
+    g = torch.Generator(device="cuda")
+    g.manual_seed(workloads.SEED["plain_64m"])
+    big = torch.randint(0, 256, (256 << 20,), dtype=torch.uint8, device="cuda", generator=g)
+    nb = big.numel()
+    one = ctx.encrypt(big, pw)
+    torch.cuda.synchronize()
+    e[0].record(stream)
+    ctx.encrypt(big, pw, out=one)
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    ms1 = e[0].elapsed_time(e[1])
+    out = torch.empty(nb + 24, dtype=torch.uint8, device="cuda")
+    chunk = (64 << 20) + 1
+    e[0].record(stream)
+    st = lz.Stream(ctx, False, pw)
+    for a in range(0, nb, chunk):
+        b = min(a + chunk, nb)
+        st.update(big[a:b], out=out[a:b])
+    out[nb:] = st.finish()
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    st.close()
+    ms = e[0].elapsed_time(e[1])
+    res["256MiB_one_shot"] = dict(ms=ms1, encrypt_GBps=nb / ms1 / 1e6)
+    res[f"256MiB_chunks_of_{chunk}"] = dict(updates=(nb + chunk - 1) // chunk, ms=ms, encrypt_GBps=nb / ms / 1e6,
+                                           equals_one_shot=bool(torch.equal(out, one)))
     ctx.close()
     return res
 
