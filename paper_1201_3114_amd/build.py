@@ -32,16 +32,20 @@ def _run(cmd):
 
 def build(verbose: bool = False) -> str:
     """Compiles every source and links the shared library; returns its path."""
+    from concurrent.futures import ThreadPoolExecutor
+
     with tempfile.TemporaryDirectory(prefix="lzbuild") as tmp:
-        objs = []
+        cmds, objs = [], []
         for src in SOURCES:
             obj = os.path.join(tmp, src + ".o")
             lang = ["-x", "hip"] + DEVICE if src.endswith(".hip") else ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
-            cmd = [HIPCC, *COMMON, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
-            if verbose:
-                print(" ".join(cmd))
-            _run(cmd)
+            cmds.append([HIPCC, *COMMON, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
             objs.append(obj)
+            if verbose:
+                print(" ".join(cmds[-1]))
+        workers = max(1, min(len(cmds), os.cpu_count() or 1, 6))
+        with ThreadPoolExecutor(max_workers=workers) as pool:
+            list(pool.map(_run, cmds))  # re-raises the first failure
         tmp_lib = LIB + ".tmp"
         _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp_lib, "-lpthread"])
         os.replace(tmp_lib, LIB)
