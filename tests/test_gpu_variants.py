@@ -108,3 +108,28 @@ def test_sequential_version_plain_and_batch(lz, block_len):
     for i in range(len(sizes)):
         want = oracle.encrypt(pws[i], plains[i], n_it=30, block_len=block_len)
         assert np.array_equal(C[int(out_off[i]):int(out_off[i]) + sizes[i] + 24], want), i
+
+
+def test_sequential_version_full_parameters(lz):
+    """The benchmark's sequential-version workload (4,096 messages of 256 B..4 KiB, block_len 2^32 - 1,
+    n_it 3000) run as one batch; the first eight messages and the longest one equal the oracle."""
+    import torch
+
+    from paper_1201_3114_amd import workloads
+
+    wl = workloads.batch(count=4096, seed=workloads.SEED["sequential"], lo=256, hi=4096)
+    bl = (1 << 32) - 1
+    ctx = lz.Context(0, lz.params(block_len=bl))
+    sizes = wl.sizes
+    out_off, out_tot = lz.packed_offsets(sizes, 24)
+    d_out = torch.zeros(out_tot, dtype=torch.uint8, device="cuda")
+    b = lz.Batch(ctx, False, sizes, wl.passwords, to_dev(wl.data), wl.offsets, d_out, out_off)
+    b.launch()
+    C = host(d_out)
+    b.close()
+    pick = list(range(8)) + [int(np.argmax(sizes))]
+    say("sequential messages", [int(sizes[i]) for i in pick])
+    for i in pick:
+        P = wl.data[int(wl.offsets[i]):int(wl.offsets[i]) + int(sizes[i])]
+        want = oracle.encrypt(wl.passwords[i], P, block_len=bl)
+        assert np.array_equal(C[int(out_off[i]):int(out_off[i]) + int(sizes[i]) + 24], want), i
