@@ -607,7 +607,10 @@ def main():
 
     out = {"metric": "encrypt+decrypt GB/s at 64 MiB; batched/served GB/s + p50/p99 vs plain", "unit": "GB/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded uniform random bytes, printable passwords)"}
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded uniform random bytes, printable passwords)",
+           "paper_context": {"parallel_version_MBps": {"GeForce 8800 GT": 2.5, "GTX 285": 4.3},
+                             "note": "the paper's own figures (Section 5), another computation on other hardware: "
+                                     "context only, not a baseline for this metric"}}
     plain = None
     if args.only in ("all", "plain", "serve"):
         log("plain 64 MiB ...")
