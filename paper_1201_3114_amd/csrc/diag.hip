@@ -68,7 +68,8 @@ __global__ __launch_bounds__(DIAG_WG) void histogram_kernel(const uint8_t *data,
 // four consecutive lags 4g..4g+3 over a run of rows: per four rows it reads one
 // aligned word of x_i and one new aligned word of the shifted window, forms the
 // three byte-shifted windows with alignbyte, and accumulates four-byte dot
-// products (v_dot4_u32_u8) in 32-bit sums (at most AC_TILE * 255^2 < 2^32).
+// products (v_dot4_u32_u8) in 32-bit sums (at most AC_TILE * 255^2 < 2^32);
+// runs are multiples of 16 rows, read four words at a time.
 // For L < AC_LDS_LAGS the sums of all items and tiles meet in 64-bit LDS
 // counters, so a workgroup issues one global atomic per lag; beyond that each
 // item adds its sums to the global counters directly.
@@ -100,8 +101,8 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_kernel(const uint8_t *data, ui
         for (uint32_t j = threadIdx.x; j < span; j += DIAG_WG) t[j] = i0 + j < n ? data[i0 + j] : 0;
         __syncthreads();
         const uint64_t left = n - i0;
-        const uint32_t rows = left < (uint64_t)AC_TILE ? (uint32_t)((left + 3) & ~3ull) : (uint32_t)AC_TILE;
-        const uint32_t plen = ((rows / 4 + P - 1) / P) * 4;  // rows per run, a multiple of 4
+        const uint32_t rows = left < (uint64_t)AC_TILE ? (uint32_t)((left + 15) & ~15ull) : (uint32_t)AC_TILE;
+        const uint32_t plen = ((rows / 16 + P - 1) / P) * 16;  // rows per run, a multiple of 16
         for (uint32_t item = threadIdx.x; item < G * P; item += DIAG_WG) {
             const uint32_t g = item % G, p = item / G;
             const uint32_t r_lo = p * plen;
@@ -110,14 +111,22 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_kernel(const uint8_t *data, ui
             const uint32_t k0 = 4 * g;
             uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
             uint32_t w0 = t32[(r_lo + k0) / 4];
-            for (uint32_t r = r_lo; r < r_hi; r += 4) {
-                const uint32_t a = t32[r / 4];
-                const uint32_t w1 = t32[(r + k0) / 4 + 1];
-                s0 = __builtin_amdgcn_udot4(a, w0, s0, false);
-                s1 = __builtin_amdgcn_udot4(a, __builtin_amdgcn_alignbyte(w1, w0, 1), s1, false);
-                s2 = __builtin_amdgcn_udot4(a, __builtin_amdgcn_alignbyte(w1, w0, 2), s2, false);
-                s3 = __builtin_amdgcn_udot4(a, __builtin_amdgcn_alignbyte(w1, w0, 3), s3, false);
-                w0 = w1;
+            for (uint32_t r = r_lo; r < r_hi; r += 16) {  // 16 rows: eight LDS words in flight
+                uint32_t a[4], w[5];
+                w[0] = w0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    a[q] = t32[r / 4 + q];
+                    w[q + 1] = t32[(r + k0) / 4 + q + 1];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    s0 = __builtin_amdgcn_udot4(a[q], w[q], s0, false);
+                    s1 = __builtin_amdgcn_udot4(a[q], __builtin_amdgcn_alignbyte(w[q + 1], w[q], 1), s1, false);
+                    s2 = __builtin_amdgcn_udot4(a[q], __builtin_amdgcn_alignbyte(w[q + 1], w[q], 2), s2, false);
+                    s3 = __builtin_amdgcn_udot4(a[q], __builtin_amdgcn_alignbyte(w[q + 1], w[q], 3), s3, false);
+                }
+                w0 = w[4];
             }
             const uint32_t sk[4] = {s0, s1, s2, s3};
             for (int q = 0; q < 4; ++q) {
