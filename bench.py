@@ -487,11 +487,13 @@ def bench_serve(lz, torch, qps, count, plain_prefix, budget, tick_bytes=16):
     src_all = np.where(dec, dC.data_ptr() + c_off, dP.data_ptr() + p_off).astype(np.uint64)
     dst_all = (dOut.data_ptr() + c_off).astype(np.uint64)
 
-    def run_server(ids):
+    def run_server(ids, all_at_once=False):
         srv = lz.Server(ctx, hbm_budget=budget, tick_bytes=tick_bytes)
         lead_ns = int(1.0e9) + 10_000 * len(ids)
         base = lz.now_ns() + lead_ns
         arr = (base + np.round((tr.arrival_s[ids] - tr.arrival_s[ids[0]]) * 1e9)).astype(np.uint64)
+        if all_at_once:
+            arr[:] = base
         t_sub = time.perf_counter()
         srv.submit_many(ids, dec[ids], [tr.passwords[i] for i in ids], src_all[ids], sizes[ids], dst_all[ids], arr)
         submit_s = time.perf_counter() - t_sub
@@ -508,7 +510,7 @@ def bench_serve(lz, torch, qps, count, plain_prefix, budget, tick_bytes=16):
         srv.close()
         span = (last_done - first_arr) / 1e9
         nbytes = int(sizes[ids].sum())
-        trace_s = float(tr.arrival_s[ids[-1]] - tr.arrival_s[ids[0]])
+        trace_s = 0.0 if all_at_once else float(tr.arrival_s[ids[-1]] - tr.arrival_s[ids[0]])
         return dict(requests=len(ids), bytes=nbytes, GBps=nbytes / span / GB, offered_GBps=nbytes / max(trace_s, 1e-9) / GB,
                     makespan_s=span, p50_ms=percentile(lat, 50), p99_ms=percentile(lat, 99), max_ms=float(np.max(lat)),
                     all_ok=all(s == 0 for s in status), ticks=stats["ticks"], device_busy_ms=stats["busy_ms"],
@@ -527,6 +529,14 @@ def bench_serve(lz, torch, qps, count, plain_prefix, budget, tick_bytes=16):
         E[o:o + n] = dP[po:po + n]
         E[o + n:o + n + 24] = 0
     served["bit_exact_vs_plain"] = bool(torch.equal(E, dOut))
+    # saturation: the first quarter of the requests all offered at once (the engine's peak rate)
+    sat_ids = ids[:max(1, count // 4)]
+    dOut.zero_()
+    saturated = run_server(sat_ids, all_at_once=True)
+    torch.cuda.synchronize()
+    last = int(c_off[sat_ids[-1]]) + int(sizes[sat_ids[-1]]) + 24
+    saturated["bit_exact_vs_plain"] = bool(torch.equal(E[:last], dOut[:last]))
+    del saturated["offered_GBps"]
     del E
     # plain path, one request at a time in arrival order, on a prefix of the trace
     k = min(plain_prefix, count)
@@ -562,7 +572,7 @@ def bench_serve(lz, torch, qps, count, plain_prefix, budget, tick_bytes=16):
     served_prefix = run_server(pre)
     ctx.close()
     return dict(qps=qps, requests=count, bytes=tot, mean_request_bytes=tot / count, prep_s=prep_s,
-                hbm_budget_GB=budget / GB, continuous=served, plain_per_request_prefix=plain,
+                hbm_budget_GB=budget / GB, continuous=served, saturated=saturated, plain_per_request_prefix=plain,
                 continuous_same_prefix=served_prefix,
                 p99_speedup_vs_plain_on_prefix=plain["p99_ms"] / served_prefix["p99_ms"])
 

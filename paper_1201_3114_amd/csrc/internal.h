@@ -115,6 +115,15 @@ hipError_t launch_install(ReqDesc *reqs, ChainSlot *slots, const ReqDesc *staged
                           const uint32_t *idx, uint32_t n_new, uint32_t block_len, hipStream_t s);
 hipError_t launch_req_zero(const ReqDesc *reqs, const uint32_t *req_ids, uint32_t n, hipStream_t s);
 
+// One piece of a batched device-to-device copy (the serving loop's request inputs and outputs).
+struct CopyPiece {
+    const uint8_t *src;
+    uint8_t *dst;
+    uint64_t len;
+};
+constexpr uint64_t COPY_PIECE_BYTES = 1ull << 20;  // requests are cut into pieces of at most this size
+hipError_t launch_copy_many(const CopyPiece *pieces, uint32_t n, hipStream_t s);
+
 // Streaming: continue (or start) one chain for cnt bytes from/to its checkpoint in *slot.
 hipError_t launch_resume(const lz_key &key, const lz_params &prm, int decrypt, ChainSlot *slot, uint64_t block,
                          const uint8_t *in, uint8_t *out, uint32_t cnt, int fresh, int complete,

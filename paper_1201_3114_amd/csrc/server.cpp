@@ -83,6 +83,7 @@ struct Request {
     lz_key key;
     const void *src;
     void *dst;
+    bool src_dev = false, dst_dev = false;  // device memory: copied by the batched copy kernel
     uint64_t n;          // plaintext length
     uint64_t arrival_ns;
     uint64_t admit_ns = 0;
@@ -105,6 +106,39 @@ struct ArrivalLater {
 uint64_t in_len(const Request &r) { return r.decrypt ? r.n + LZ_TAG_BYTES : r.n; }
 uint64_t out_len(const Request &r) { return r.decrypt ? r.n : r.n + LZ_TAG_BYTES; }
 
+uint64_t pieces_of(uint64_t bytes) { return (bytes + COPY_PIECE_BYTES - 1) / COPY_PIECE_BYTES; }
+
+// Device memory of any device is copied by kernels; everything else (pageable or
+// pinned host memory) by hipMemcpyAsync.
+bool is_device_ptr(const void *p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    const hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // pageable memory is not known to the runtime
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
+
+// Appends the pieces of one copy to a staging array.
+void add_pieces(CopyPiece *arr, uint32_t &n, const void *src, void *dst, uint64_t len) {
+    for (uint64_t o = 0; o < len; o += COPY_PIECE_BYTES) {
+        CopyPiece &p = arr[n++];
+        p.src = static_cast<const uint8_t *>(src) + o;
+        p.dst = static_cast<uint8_t *>(dst) + o;
+        p.len = len - o < COPY_PIECE_BYTES ? len - o : COPY_PIECE_BYTES;
+    }
+}
+
+constexpr uint32_t PIECES_MAX = 4096;  // copy pieces staged per tick (inputs) and per batch (outputs)
+constexpr uint64_t DEV_COPY_MAX = (PIECES_MAX / 2) * COPY_PIECE_BYTES;  // larger copies use hipMemcpyAsync
+
+void classify(Request *r) {
+    r->src_dev = in_len(*r) <= DEV_COPY_MAX && is_device_ptr(r->src);
+    r->dst_dev = out_len(*r) <= DEV_COPY_MAX && is_device_ptr(r->dst);
+}
+
 }  // namespace
 
 // Buffers of one tick.  Two of them alternate so that the host prepares and
@@ -116,6 +150,7 @@ struct TickSlot {
     ReqDesc *h_req = nullptr, *d_req = nullptr;     // records of the requests admitted for this tick
     uint32_t *h_meta = nullptr, *d_meta = nullptr;  // 3 words per admitted request
     uint32_t *h_idx = nullptr, *d_idx = nullptr;    // chain slots of the admitted requests
+    CopyPiece *h_in = nullptr, *d_in = nullptr;     // input copies of admitted requests in device memory
     hipEvent_t ev_start = nullptr, ev_end = nullptr;
     bool in_flight = false;
     uint64_t bytes = 0;
@@ -132,6 +167,7 @@ struct lz_server {
     ReqDesc *reqs = nullptr;
     uint32_t *d_zero_ids = nullptr;
     uint32_t *h_zero_ids = nullptr;
+    CopyPiece *h_out = nullptr, *d_out = nullptr;  // output copies to device memory
     TickSlot ts[2];
     int cur = 0;
     hipStream_t stream = nullptr;       // installs, ticks
@@ -179,7 +215,7 @@ void finish(lz_server *s, Request *r, int32_t status, uint64_t done_ns) {
 // Admits waiting requests in FIFO order while slots, memory and staging room allow.
 void admit(lz_server *s, std::vector<Request *> &admitted) {
     const uint32_t B = s->ctx->prm.block_len;
-    uint64_t staged_chains = 0;
+    uint64_t staged_chains = 0, staged_pieces = 0;
     while (!s->waiting.empty() && admitted.size() < s->max_new) {
         Request *r = s->waiting.front();
         const uint64_t nb64 = r->n == 0 ? 1 : (r->n + B - 1) / B;
@@ -190,13 +226,17 @@ void admit(lz_server *s, std::vector<Request *> &admitted) {
             continue;
         }
         const uint32_t nb = (uint32_t)nb64;
-        if (s->free_reqs.empty() || s->free_slots.size() < nb || staged_chains + nb > s->max_chains) break;
+        const uint64_t np = r->src_dev ? pieces_of(in_len(*r)) : 0;
+        if (s->free_reqs.empty() || s->free_slots.size() < nb || staged_chains + nb > s->max_chains ||
+            staged_pieces + np > PIECES_MAX)
+            break;
         uint64_t off;
         if (!s->arena.alloc(bytes, off)) break;
         s->waiting.pop_front();
         r->slots.assign(s->free_slots.end() - nb, s->free_slots.end());
         s->free_slots.resize(s->free_slots.size() - nb);
         staged_chains += nb;
+        staged_pieces += np;
         r->nb = nb;
         r->arena_off = off;
         r->arena_bytes = bytes;
@@ -244,13 +284,30 @@ int complete_tick(lz_server *s, TickSlot &t) {
     }
     std::vector<std::pair<Request *, int32_t>> fin;
     fin.reserve(nd);
+    uint32_t n_out = 0;
+    auto flush_out = [&]() -> int {  // one launch for the staged device-to-device output copies
+        if (!n_out) return LZ_OK;
+        LZ_HIP(hipMemcpyAsync(s->d_out, s->h_out, n_out * sizeof(CopyPiece), hipMemcpyHostToDevice, cs));
+        LZ_HIP(launch_copy_many(s->d_out, n_out, cs));
+        LZ_HIP(hipStreamSynchronize(cs));  // the staging array is reused
+        n_out = 0;
+        return LZ_OK;
+    };
     for (uint32_t i = 0; i < nd; ++i) {
         Request *r = s->by_slot[t.h_done[2 + i] >> 1];
         if (!r) return fail(LZ_E_HIP, "server: completion for an empty request slot");
         const int32_t status = (t.h_done[2 + i] & 1u) ? LZ_E_INTEGRITY : LZ_OK;
-        if (out_len(*r)) LZ_HIP(hipMemcpyAsync(r->dst, req_out(s, r), out_len(*r), hipMemcpyDefault, cs));
+        const uint64_t len = out_len(*r);
+        if (len && r->dst_dev) {
+            if (n_out + pieces_of(len) > PIECES_MAX)
+                if (int rc = flush_out()) return rc;
+            add_pieces(s->h_out, n_out, req_out(s, r), r->dst, len);
+        } else if (len) {
+            LZ_HIP(hipMemcpyAsync(r->dst, req_out(s, r), len, hipMemcpyDefault, cs));
+        }
         fin.emplace_back(r, status);
     }
+    if (int rc = flush_out()) return rc;
     LZ_HIP(hipStreamSynchronize(cs));
     const uint64_t now = lz_now_ns();
     for (auto &f : fin) {
@@ -282,7 +339,7 @@ int server_step(lz_server *s) {
     admit(s, admitted);
     if (!admitted.empty()) {
         const size_t k = admitted.size();
-        uint32_t n_idx = 0;
+        uint32_t n_idx = 0, n_in = 0;
         for (size_t i = 0; i < k; ++i) {
             Request *r = admitted[i];
             ReqDesc &d = t.h_req[i];
@@ -307,9 +364,14 @@ int server_step(lz_server *s) {
             t.h_meta[3 * i + 2] = n_idx;
             std::memcpy(t.h_idx + n_idx, r->slots.data(), r->nb * sizeof(uint32_t));
             n_idx += r->nb;
-            if (in_len(*r)) LZ_HIP(hipMemcpyAsync(req_in(s, r), r->src, in_len(*r), hipMemcpyDefault, pre));
+            if (in_len(*r) && r->src_dev) add_pieces(t.h_in, n_in, r->src, req_in(s, r), in_len(*r));
+            else if (in_len(*r)) LZ_HIP(hipMemcpyAsync(req_in(s, r), r->src, in_len(*r), hipMemcpyDefault, pre));
             r->active_idx = s->active.size();
             s->active.push_back(r);
+        }
+        if (n_in) {
+            LZ_HIP(hipMemcpyAsync(t.d_in, t.h_in, n_in * sizeof(CopyPiece), hipMemcpyHostToDevice, pre));
+            LZ_HIP(launch_copy_many(t.d_in, n_in, pre));
         }
         LZ_HIP(hipMemcpyAsync(t.d_req, t.h_req, k * sizeof(ReqDesc), hipMemcpyHostToDevice, pre));
         LZ_HIP(hipMemcpyAsync(t.d_meta, t.h_meta, 3 * k * sizeof(uint32_t), hipMemcpyHostToDevice, pre));
@@ -408,12 +470,16 @@ void server_free(lz_server *s) {
     hipFree(s->reqs);
     hipFree(s->d_zero_ids);
     hipHostFree(s->h_zero_ids);
+    hipFree(s->d_out);
+    hipHostFree(s->h_out);
     for (TickSlot &t : s->ts) {
         hipFree(t.d_list);
         hipFree(t.d_done);
         hipFree(t.d_req);
         hipFree(t.d_meta);
         hipFree(t.d_idx);
+        hipFree(t.d_in);
+        hipHostFree(t.h_in);
         hipHostFree(t.h_list);
         hipHostFree(t.h_done);
         hipHostFree(t.h_req);
@@ -461,9 +527,9 @@ extern "C" int lz_server_create(lz_ctx *c, const lz_server_config *cfg, lz_serve
     // fixed device memory: chain slots, request records, and per tick slot the list, the
     // completion queue and the staging of admitted requests
     const uint64_t per_tick = (uint64_t)s->max_chains * 4 * 2 + ((uint64_t)s->max_reqs + 2) * 4 +
-                              (uint64_t)s->max_new * (sizeof(ReqDesc) + 12);
+                              (uint64_t)s->max_new * (sizeof(ReqDesc) + 12) + PIECES_MAX * sizeof(CopyPiece);
     const uint64_t fixed = (uint64_t)s->max_chains * sizeof(ChainSlot) + (uint64_t)s->max_reqs * sizeof(ReqDesc) +
-                           (uint64_t)s->max_reqs * 4 + 2 * per_tick + (1u << 20);
+                           (uint64_t)s->max_reqs * 4 + 2 * per_tick + PIECES_MAX * sizeof(CopyPiece) + (1u << 20);
     if (cfg->hbm_budget <= fixed + 4096) {
         delete s;
         return fail(LZ_E_INVAL, "hbm_budget too small for the chain slots");
@@ -475,12 +541,16 @@ extern "C" int lz_server_create(lz_ctx *c, const lz_server_config *cfg, lz_serve
     if (e == hipSuccess) e = hipMalloc(&s->reqs, (size_t)s->max_reqs * sizeof(ReqDesc));
     if (e == hipSuccess) e = hipMalloc(&s->d_zero_ids, (size_t)s->max_reqs * sizeof(uint32_t));
     if (e == hipSuccess) e = hipHostMalloc(&s->h_zero_ids, (size_t)s->max_reqs * sizeof(uint32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(&s->d_out, PIECES_MAX * sizeof(CopyPiece));
+    if (e == hipSuccess) e = hipHostMalloc(&s->h_out, PIECES_MAX * sizeof(CopyPiece), hipHostMallocDefault);
     for (TickSlot &t : s->ts) {
         if (e == hipSuccess) e = hipMalloc(&t.d_list, (size_t)s->max_chains * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(&t.d_done, ((size_t)s->max_reqs + 2) * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(&t.d_req, (size_t)s->max_new * sizeof(ReqDesc));
         if (e == hipSuccess) e = hipMalloc(&t.d_meta, 3 * (size_t)s->max_new * sizeof(uint32_t));
         if (e == hipSuccess) e = hipMalloc(&t.d_idx, (size_t)s->max_chains * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&t.d_in, PIECES_MAX * sizeof(CopyPiece));
+        if (e == hipSuccess) e = hipHostMalloc(&t.h_in, PIECES_MAX * sizeof(CopyPiece), hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc(&t.h_list, (size_t)s->max_chains * sizeof(uint32_t), hipHostMallocDefault);
         if (e == hipSuccess)
             e = hipHostMalloc(&t.h_done, ((size_t)s->max_reqs + 2) * sizeof(uint32_t), hipHostMallocDefault);
@@ -528,6 +598,7 @@ extern "C" int lz_server_submit(lz_server *s, uint64_t id, int decrypt, const ui
     r->src = src;
     r->dst = dst;
     r->n = n;
+    classify(r);
     r->arrival_ns = arrival_ns ? arrival_ns : lz_now_ns();
     {
         std::lock_guard<std::mutex> g(s->mu);
@@ -580,6 +651,7 @@ extern "C" int lz_server_submit_many(lz_server *s, size_t count, const uint64_t 
         r->src = src[i];
         r->dst = dst[i];
         r->n = n[i];
+        classify(r);
         r->arrival_ns = arrival_ns[i] ? arrival_ns[i] : now;
     }
     {
