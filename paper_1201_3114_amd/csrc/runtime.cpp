@@ -304,6 +304,7 @@ extern "C" int lz_batch_create(lz_ctx *c, int decrypt, size_t n_msg, const uint6
     std::vector<uint32_t> tails;
     for (size_t i = 0; i < n_msg; ++i) {
         if (lens[i] > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+        if ((lens[i] + B - 1) / B > 0xFFFFFFFFull) return fail(LZ_E_INVAL, "message has 2^32 blocks or more");
         lz_key key;
         if (int rc = lz_key_setup(pw + pw_off[i], pw_len[i], &c->prm, &key)) return rc;
         MsgDesc &m = md[i];
