@@ -179,3 +179,34 @@ def test_batch_and_integrity_full_config(lz):
     for i in [int(j) for j in idx if sizes[j] <= 4096][:3]:
         ct = C[int(out_off[i]):int(out_off[i]) + int(sizes[i]) + 24]
         assert not oracle.decrypt(wl.passwords[i], ct, nthreads=ORACLE_THREADS)[1]
+
+
+def test_autotune_picks_a_valid_shape_and_keeps_results(lz):
+    """The autotuner (with a small n_it so the sweep is quick) stores a valid shape in the context; a batch
+    launched with it gives the same bytes as the plain path and the oracle."""
+    import torch
+
+    rng = np.random.default_rng(31)
+    ctx = lz.Context(0, lz.params(n_it=20))
+    before = ctx.get_launch()
+    best = ctx.autotune()
+    assert ctx.get_launch() == best
+    assert best.chains_per_lane in (1, 2, 4) and best.wg_size in (64, 128, 256) and best.tile in (16, 32, 64, 128)
+    say("autotune", before, "->", best)
+    sizes = [int(x) for x in rng.integers(0, 5000, 60)]
+    pws = [bytes(rng.integers(32, 127, int(rng.integers(8, 65)), dtype=np.uint8)) for _ in sizes]
+    data = rng.integers(0, 256, int(sum(sizes)), dtype=np.uint8)
+    in_off, _ = lz.packed_offsets(sizes, 0)
+    out_off, out_tot = lz.packed_offsets(sizes, 24)
+    d_out = torch.zeros(out_tot, dtype=torch.uint8, device="cuda")
+    d_in = to_dev(data) if len(data) else torch.zeros(1, dtype=torch.uint8, device="cuda")
+    b = lz.Batch(ctx, False, sizes, pws, d_in, in_off, d_out, out_off)
+    b.launch()
+    C = host(d_out)
+    b.close()
+    for i in range(0, len(sizes), 7):
+        P = data[int(in_off[i]):int(in_off[i]) + sizes[i]]
+        want = oracle.encrypt(pws[i], P, n_it=20)
+        assert np.array_equal(C[int(out_off[i]):int(out_off[i]) + sizes[i] + 24], want), i
+        if sizes[i]:
+            assert np.array_equal(host(ctx.encrypt(to_dev(P), pws[i])), want), i
