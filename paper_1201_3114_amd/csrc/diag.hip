@@ -250,29 +250,38 @@ __device__ __forceinline__ double2 dft_value(uint8_t v) { return make_double2((d
 __device__ __forceinline__ double2 dft_value(double v) { return make_double2(v, 0.0); }
 __device__ __forceinline__ double2 dft_value(double2 v) { return v; }
 
-template <typename In, int TR>
+// The pass runs on the matrix cores: binary64 MFMA 16x16x4 (v_mfma_f64_16x16x4f64), operand
+// layout: lane i holds A[i % 16][i / 16] and B[i / 16][i % 16] of the 16x4 and 4x16 operands,
+// and D[4 j + i / 16][i % 16] in its j-th accumulator.  A complex product takes four real
+// products: re += wr xr - wi xi, im += wr xi + wi xr.  The inputs and twiddles of the next
+// 16-deep k stage are loaded into registers while the current stage computes; the loads are
+// unconditional, from valid addresses, so nothing waits for them before the stage's products,
+// and out-of-range entries are zeroed when stored to LDS.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename In>
 __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32_t N, uint32_t M, const double2 *tw,
                                                             double sign, double2 *dst) {
-    // output tile: TR values of r by DFT_T values of c; a lane holds TR/16 x 4 complex sums
-    constexpr int RI = TR / 16;
-    constexpr int TWQ = TR * DFT_K / DIAG_WG;  // twiddles each thread stages per k stage
+    // 64 x 64 outputs per workgroup; each wave takes a 32 x 32 block as 2 x 2 tiles of 16 x 16
+    constexpr int TR = DFT_T;
+    constexpr int TB = 2;                            // column tiles per wave
+    constexpr int TWQ = TR * DFT_K / DIAG_WG;        // twiddles each thread stages per k stage
     __shared__ double2 s_src[DFT_K][DFT_T];  // [k][c]
     __shared__ double2 s_tw[DFT_K][TR];      // [k][r]
     const uint32_t r0 = blockIdx.x * TR, c0 = blockIdx.y * DFT_T;
-    const uint32_t tr = threadIdx.x % 16, tc = threadIdx.x / 16;  // consecutive lanes: consecutive r
-    // staging roles: column cc of the input tile for k rows kq + 4q; twiddle row tr_s for k rows kt + (DFT_K/TWQ) q
+    const uint32_t lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    const uint32_t wr = (wave / 2) * 32, wc = (wave % 2) * 32;
+    const uint32_t li = lane % 16, lk = lane / 16;
+    // staging: column cc of the input tile for k rows kq + 4q; twiddle row tr_s for k rows kt + (DFT_K/TWQ) q
     const uint32_t cc = threadIdx.x % DFT_T, kq = threadIdx.x / DFT_T;
     const uint32_t tr_s = threadIdx.x % TR, kt = threadIdx.x / TR;
-    const uint32_t rs = r0 + tr_s;  // the twiddle row this thread stages
+    const uint32_t rs = r0 + tr_s;
     const uint32_t rmod = rs < N ? rs : 0;
-    const uint32_t cs = c0 + cc < M ? c0 + cc : M - 1;  // a valid column to load from
+    const uint32_t cs = c0 + cc < M ? c0 + cc : M - 1;
     uint32_t off[TWQ];
     for (int q = 0; q < TWQ; ++q) off[q] = (uint32_t)(((uint64_t)rmod * (kt + (DFT_K / TWQ) * q)) % N);
     const uint32_t step = (uint32_t)(((uint64_t)rmod * DFT_K) % N);
-    uint32_t base = 0;  // rs * k0 mod N
-    // The next stage's inputs and twiddles are loaded into registers while the current stage
-    // computes.  The loads are unconditional, from valid addresses, so that nothing waits for
-    // them before the stage's products; out-of-range entries are zeroed when stored to LDS.
+    uint32_t base = 0;
     In nx[4];
     double2 nw[TWQ];
     auto fetch = [&](uint32_t k0) {
@@ -288,9 +297,9 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
         base += step;
         if (base >= N) base -= N;
     };
-    double ar[RI][4], ai[RI][4];
-    for (int i = 0; i < RI; ++i)
-        for (int j = 0; j < 4; ++j) ar[i][j] = ai[i][j] = 0.0;
+    v4d re[2][TB], im[2][TB];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < TB; ++b) re[a][b] = im[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
     fetch(0);
     for (uint32_t k0 = 0; k0 < N; k0 += DFT_K) {
         for (int q = 0; q < 4; ++q) {
@@ -303,27 +312,28 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
         }
         __syncthreads();
         if (k0 + DFT_K < N) fetch(k0 + DFT_K);
-#pragma unroll 4
-        for (int kk = 0; kk < DFT_K; ++kk) {
-            double2 w[RI], x[4];
-            for (int i = 0; i < RI; ++i) w[i] = s_tw[kk][tr + 16 * i];
-            for (int j = 0; j < 4; ++j) x[j] = s_src[kk][tc + 16 * j];
-            for (int i = 0; i < RI; ++i)
-                for (int j = 0; j < 4; ++j) {
-                    ar[i][j] = __builtin_fma(w[i].x, x[j].x, __builtin_fma(-w[i].y, x[j].y, ar[i][j]));
-                    ai[i][j] = __builtin_fma(w[i].x, x[j].y, __builtin_fma(w[i].y, x[j].x, ai[i][j]));
+#pragma unroll
+        for (int k4 = 0; k4 < DFT_K / 4; ++k4) {
+            const int k = 4 * k4 + (int)lk;
+            double2 w[2], x[TB];
+            for (int t = 0; t < 2; ++t) w[t] = s_tw[k][wr + 16 * t + li];
+            for (int t = 0; t < TB; ++t) x[t] = s_src[k][wc + 16 * t + li];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < TB; ++b) {
+                    re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[a].x, x[b].x, re[a][b], 0, 0, 0);
+                    re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-w[a].y, x[b].y, re[a][b], 0, 0, 0);
+                    im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[a].x, x[b].y, im[a][b], 0, 0, 0);
+                    im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[a].y, x[b].x, im[a][b], 0, 0, 0);
                 }
         }
         __syncthreads();
     }
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t c = c0 + tc + 16 * j;
-        if (c >= M) continue;
-        for (int i = 0; i < RI; ++i) {
-            const uint32_t r = r0 + tr + 16 * i;
-            if (r < N) dst[(size_t)c * N + r] = make_double2(ar[i][j], ai[i][j]);
-        }
-    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < TB; ++b)
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t r = r0 + wr + 16 * a + 4 * j + lk, c = c0 + wc + 16 * b + li;
+                if (r < N && c < M) dst[(size_t)c * N + r] = make_double2(re[a][b][j], im[a][b][j]);
+            }
 }
 
 // |Z|^2 element by element; with zero_dc the (0, 0) entry is set to 0 (the
@@ -465,19 +475,12 @@ int launch_twiddles(const Dft2 &d, uint32_t h, uint32_t w, hipStream_t s) {
     return LZ_OK;
 }
 
-// dst (M x N) = transpose of (DFT_N along the rows of src (N x M)).  Tiles of 64 x 64 outputs, or
-// 32 x 64 when that would leave fewer than two workgroups per CU (more waves to hide latency).
+// dst (M x N) = transpose of (DFT_N along the rows of src (N x M)), 64 x 64 outputs per workgroup.
 template <typename In>
-int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, const double2 *tw, double sign,
-                    double2 *dst, hipStream_t s) {
-    const uint64_t tiles64 = (uint64_t)((N + 63) / 64) * ((M + DFT_T - 1) / DFT_T);
-    if (tiles64 < 2 * (uint64_t)c->dev.cus) {
-        const dim3 grid((N + 31) / 32, (M + DFT_T - 1) / DFT_T);
-        hipLaunchKernelGGL((dft_pass_kernel<In, 32>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, dst);
-    } else {
-        const dim3 grid((N + 63) / 64, (M + DFT_T - 1) / DFT_T);
-        hipLaunchKernelGGL((dft_pass_kernel<In, 64>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, dst);
-    }
+int launch_dft_pass(const In *src, uint32_t N, uint32_t M, const double2 *tw, double sign, double2 *dst,
+                    hipStream_t s) {
+    const dim3 grid((N + DFT_T - 1) / DFT_T, (M + DFT_T - 1) / DFT_T);
+    hipLaunchKernelGGL((dft_pass_kernel<In>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, dst);
     LZ_HIP(hipGetLastError());
     return LZ_OK;
 }
@@ -528,8 +531,8 @@ extern "C" int lz_power_spectrum_2d(lz_ctx *c, const uint8_t *d_img, uint32_t h,
     if (int rc = diag_begin(c, s, dft2_bytes(h, w, 0), &ws)) return rc;
     const Dft2 d = dft2_layout(ws, h, w, 0);
     if (int rc = launch_twiddles(d, h, w, s)) return rc;
-    if (int rc = launch_dft_pass<uint8_t>(c, d_img, h, w, d.tw_h, -1.0, d.a, s)) return rc;  // a: w x h
-    if (int rc = launch_dft_pass<double2>(c, d.a, w, h, d.tw_w, -1.0, d.b, s)) return rc;   // b: h x w = Z
+    if (int rc = launch_dft_pass<uint8_t>(d_img, h, w, d.tw_h, -1.0, d.a, s)) return rc;  // a: w x h
+    if (int rc = launch_dft_pass<double2>(d.a, w, h, d.tw_w, -1.0, d.b, s)) return rc;   // b: h x w = Z
     const size_t n = (size_t)h * w;
     hipLaunchKernelGGL(power_kernel, dim3(grid_for(n, c)), dim3(256), 0, s, d.b, n, d_power, 0);
     LZ_HIP(hipGetLastError());
@@ -553,13 +556,13 @@ extern "C" int lz_autocorrelation_2d(lz_ctx *c, const uint8_t *d_img, uint32_t h
                        reinterpret_cast<const unsigned long long *>(hist), (uint64_t)n, den);
     LZ_HIP(hipGetLastError());
     if (int rc = launch_twiddles(d, h, w, s)) return rc;
-    if (int rc = launch_dft_pass<uint8_t>(c, d_img, h, w, d.tw_h, -1.0, d.a, s)) return rc;  // a: w x h
-    if (int rc = launch_dft_pass<double2>(c, d.a, w, h, d.tw_w, -1.0, d.b, s)) return rc;   // b: Z, h x w
+    if (int rc = launch_dft_pass<uint8_t>(d_img, h, w, d.tw_h, -1.0, d.a, s)) return rc;  // a: w x h
+    if (int rc = launch_dft_pass<double2>(d.a, w, h, d.tw_w, -1.0, d.b, s)) return rc;   // b: Z, h x w
     double *pm = reinterpret_cast<double *>(d.a);                                         // a: |Z|^2, DC = 0
     hipLaunchKernelGGL(power_kernel, dim3(grid_for(n, c)), dim3(256), 0, s, d.b, n, pm, 1);
     LZ_HIP(hipGetLastError());
-    if (int rc = launch_dft_pass<double>(c, pm, h, w, d.tw_h, 1.0, d.b, s)) return rc;       // b: w x h
-    if (int rc = launch_dft_pass<double2>(c, d.b, w, h, d.tw_w, 1.0, d.a, s)) return rc;     // a: G, h x w
+    if (int rc = launch_dft_pass<double>(pm, h, w, d.tw_h, 1.0, d.b, s)) return rc;       // b: w x h
+    if (int rc = launch_dft_pass<double2>(d.b, w, h, d.tw_w, 1.0, d.a, s)) return rc;     // a: G, h x w
     hipLaunchKernelGGL(acf2_norm_kernel, dim3(grid_for(n, c)), dim3(256), 0, s, d.a, n, den, d_acf);
     LZ_HIP(hipGetLastError());
     return diag_end(c, s);
