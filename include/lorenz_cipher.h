@@ -211,8 +211,10 @@ int lz_autotune(lz_ctx *ctx, double budget_ms, lz_launch *best);
  * chunk.  Decrypted chunks are NOT authenticated until lz_stream_finish
  * reports LZ_OK; the caller must not release them before that.
  *
- * lz_stream_open: pw host pointer, 1..64 bytes; the stream owns ~128 bytes
- * of device memory.  Synchronous. */
+ * lz_stream_open: pw host pointer, 1..64 bytes; the stream owns about 200
+ * bytes of device memory (two chain checkpoints and the running tag) and two
+ * internal HIP streams on which the partial blocks of an update run beside its
+ * full blocks.  Synchronous. */
 int lz_stream_open(lz_ctx *ctx, int decrypt, const uint8_t *pw, size_t n_pw, lz_stream **out);
 
 /* Processes the next n bytes: d_in and d_out device pointers of n bytes
