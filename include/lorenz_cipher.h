@@ -257,7 +257,12 @@ typedef struct {
     uint64_t done_ns;    /* when its output was complete in the caller's buffer   */
 } lz_completion;
 
-/* Creates the server and starts its thread. */
+/* Creates the server and starts its thread.  The budget covers everything the
+ * server allocates on the device: chain slots (80 bytes each), request records,
+ * the two tick slots' staging and a first-fit arena for request buffers (the
+ * rest).  LZ_E_INVAL if the budget does not exceed the fixed part, or
+ * tick_bytes > 2^20.  Request buffers in device memory are moved by a batched
+ * copy kernel, host buffers (pageable or pinned) by hipMemcpyAsync. */
 int lz_server_create(lz_ctx *ctx, const lz_server_config *cfg, lz_server **out);
 
 /* Queues a request.  decrypt = 0: src holds n bytes of plaintext, dst
