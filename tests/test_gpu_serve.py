@@ -223,3 +223,36 @@ def test_serve_workload_prefix_vs_batched_and_oracle(lz):
             assert ok and np.array_equal(back, P) and np.array_equal(out[a:a + n], back), i
         else:
             assert np.array_equal(out[a:a + n + 24], oracle.encrypt(pw, P, nthreads=8)), i
+
+
+def test_server_and_stream_argument_errors(lz):
+    """Bad configurations and arguments are rejected on the host with LZ_E_INVAL, before any work."""
+    import torch
+
+    ctx = lz.Context(0, lz.params(n_it=5))
+    with pytest.raises(lz.LorenzError):
+        lz.Server(ctx, hbm_budget=1 << 16)                    # smaller than the fixed part
+    with pytest.raises(lz.LorenzError):
+        lz.Server(ctx, hbm_budget=1 << 30, tick_bytes=(1 << 20) + 1)
+    srv = lz.Server(ctx, hbm_budget=1 << 28, max_chains=1024, tick_bytes=16)
+    buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(lz.LorenzError):
+        srv.submit(1, False, b"", buf.data_ptr(), 10, buf.data_ptr())           # empty password
+    with pytest.raises(lz.LorenzError):
+        srv.submit(2, False, b"x" * 65, buf.data_ptr(), 10, buf.data_ptr())     # password over 64 bytes
+    with pytest.raises(lz.LorenzError):
+        srv.submit(3, False, b"pw", 0, 10, buf.data_ptr())                      # NULL source
+    with pytest.raises(lz.LorenzError):
+        srv.submit(4, True, b"pw", buf.data_ptr(), (1 << 32) + 1, buf.data_ptr())  # over 2^32 bytes
+    srv.submit(5, False, b"pw", buf.data_ptr(), 10, buf.data_ptr() + 32)      # a valid one still completes
+    got = _drain(srv, 1)
+    assert got[5][1] == 0
+    srv.close()
+    with pytest.raises(lz.LorenzError):
+        lz.Stream(ctx, False, b"")
+    st = lz.Stream(ctx, False, b"pw")
+    st.update(buf[:10], out=torch.empty(10, dtype=torch.uint8, device="cuda"))
+    st.finish()
+    with pytest.raises(lz.LorenzError):
+        st.finish()                                                            # finished twice
+    st.close()
