@@ -256,3 +256,26 @@ def test_server_and_stream_argument_errors(lz):
     with pytest.raises(lz.LorenzError):
         st.finish()                                                            # finished twice
     st.close()
+
+
+@pytest.mark.parametrize("max_chains,budget,tick", [(64, 1 << 22, 1), (256, 6 << 20, 7), (1024, 1 << 24, 100)])
+def test_serve_slot_reuse_stress(lz, max_chains, budget, tick):
+    """Few chain slots and a small arena force constant reuse of slots, request records and memory while
+    ticks overlap (two in flight); every result must still equal the plain path."""
+    rng = np.random.default_rng(45 + max_chains)
+    ctx = lz.Context(0, lz.params(n_it=12))
+    reqs = _requests(lz, ctx, rng, 400, 6000, 12)
+    srv = lz.Server(ctx, hbm_budget=budget, max_chains=max_chains, tick_bytes=tick)
+    base = lz.now_ns() + 50_000_000
+    arr = [base + int(x) for x in np.cumsum(rng.exponential(20_000, len(reqs)))]
+    srv.submit_many([r["id"] for r in reqs], [r["dec"] for r in reqs], [r["pw"] for r in reqs],
+                    [r["src"].data_ptr() for r in reqs], [r["n"] for r in reqs], [r["dst"].data_ptr() for r in reqs],
+                    arr)
+    got = _drain(srv, len(reqs), timeout_s=240)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs) and st["peak_hbm"] <= budget
+    for r in reqs:
+        assert got[r["id"]][1] == 0, r["id"]
+        n_out = r["n"] if r["dec"] else r["n"] + 24
+        assert np.array_equal(host(r["dst"])[:n_out], _expected(ctx, r)), (r["id"], r["n"], r["dec"])
