@@ -131,3 +131,49 @@ def test_two_streams_interleaved_on_two_streams(lz):
         got = np.concatenate([host(outs[i]), host(tags[i])])
         assert np.array_equal(got, oracle.encrypt(pw, Ps[i], n_it=20))
         sts[i].close()
+
+
+def test_many_streams_random_chunks(lz):
+    """Eight messages streamed at once on four HIP streams, chunk sizes drawn at random (including empty
+    and one-byte chunks), encrypt and then decrypt; every ciphertext and tag equals the oracle's."""
+    import torch
+
+    rng = np.random.default_rng(73)
+    ctx = lz.Context(0, lz.params(n_it=15))
+    sizes = [int(x) for x in rng.integers(0, 30000, 8)]
+    pws = [bytes(rng.integers(32, 127, int(rng.integers(1, 65)), dtype=np.uint8)) for _ in sizes]
+    Ps = [rng.integers(0, 256, n, dtype=np.uint8) for n in sizes]
+    devs = [to_dev(p) if len(p) else torch.zeros(0, dtype=torch.uint8, device="cuda") for p in Ps]
+    hs = [torch.cuda.Stream() for _ in range(4)]
+    outs = [torch.empty(n + 24, dtype=torch.uint8, device="cuda") for n in sizes]
+    sts = [lz.Stream(ctx, False, pw) for pw in pws]
+    cuts = [_chunks(rng, n) for n in sizes]
+    torch.cuda.synchronize()
+    for step in range(max(len(c) for c in cuts)):
+        for i in range(8):
+            if step < len(cuts[i]):
+                a, b = cuts[i][step]
+                sts[i].update(devs[i][a:b], out=outs[i][a:b], stream=hs[i % 4])
+    for i in range(8):
+        sts[i].finish(tag=outs[i][sizes[i]:], stream=hs[i % 4])
+    torch.cuda.synchronize()
+    for i in range(8):
+        sts[i].close()
+        assert np.array_equal(host(outs[i]), oracle.encrypt(pws[i], Ps[i], n_it=15)), i
+    # decrypt every message as a stream with another random chunking, status written asynchronously
+    backs = [torch.empty(max(n, 1), dtype=torch.uint8, device="cuda") for n in sizes]
+    status = torch.full((8,), 9, dtype=torch.int32, device="cuda")
+    # the received tags, kept alive until the asynchronous finishes have read them
+    tags = [outs[i][sizes[i]:].clone() for i in range(8)]
+    torch.cuda.synchronize()
+    dsts = [lz.Stream(ctx, True, pw) for pw in pws]
+    for i in range(8):
+        for a, b in _chunks(rng, sizes[i]):
+            if b > a:
+                dsts[i].update(outs[i][a:b], out=backs[i][a:b], stream=hs[(i + 1) % 4])
+        dsts[i].finish(tag=tags[i], status=status[i:i + 1], stream=hs[(i + 1) % 4])
+    torch.cuda.synchronize()
+    assert host(status).tolist() == [0] * 8
+    for i in range(8):
+        dsts[i].close()
+        assert np.array_equal(host(backs[i])[:sizes[i]], Ps[i]), i
