@@ -116,6 +116,22 @@ def bench_plain(lz, torch, steps, warmup):
     enc_ms = [ev[k][0].elapsed_time(ev[k][1]) for k in range(steps)]
     dec_ms = [ev[k][1].elapsed_time(ev[k][2]) for k in range(steps)]
     ok = bool(torch.equal(Q, dP)) and int(st.item()) == 0
+    # outside the timed steps: latency of the 64 KiB workload (256 blocks: four waves, one block's serial time)
+    P64, pw64 = workloads.plain("plain_64k")
+    d64 = torch.from_numpy(P64).cuda()
+    C64 = ctx.encrypt(d64, pw64)
+    Q64 = torch.empty_like(d64)
+    ctx.decrypt(C64, pw64, out=Q64, status=st)
+    e3 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    e3[0].record(stream)
+    ctx.encrypt(d64, pw64, out=C64)
+    e3[1].record(stream)
+    ctx.decrypt(C64, pw64, out=Q64, status=st)
+    e3[2].record(stream)
+    torch.cuda.synchronize()
+    lat64 = (e3[0].elapsed_time(e3[1]), e3[1].elapsed_time(e3[2]))
+    ok = ok and bool(torch.equal(Q64, d64)) and int(st.item()) == 0
     # outside the timed steps: the same round trip from and to pinned host memory, PCIe copies included
     hP = torch.from_numpy(P).pin_memory()
     hC = torch.empty(n + 24, dtype=torch.uint8).pin_memory()
@@ -137,7 +153,7 @@ def bench_plain(lz, torch, steps, warmup):
     n_it = ctx.params.n_it
     ctx.close()
     return dict(n=n, wall_s=wall, enc_ms=enc_ms, dec_ms=dec_ms, roundtrip_ok=ok, shape=shape, n_it=n_it,
-                pcie_ms=pcie_ms)
+                pcie_ms=pcie_ms, lat64=lat64)
 
 
 def bench_cpu_baseline(target_s: float = 12.0):
@@ -646,6 +662,7 @@ def main():
                    encrypt_GBps=n / (t_enc / args.steps / 1e3) / GB, decrypt_GBps=n / (t_dec / args.steps / 1e3) / GB,
                    wall_s=plain["wall_s"], roundtrip_exact=plain["roundtrip_ok"],
                    host_buffers_GBps=2 * n / (plain["pcie_ms"] / 1e3) / GB,
+                   latency_64KiB_ms={"encrypt": plain["lat64"][0], "decrypt": plain["lat64"][1]},
                    roofline={"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_OPS_PEAK / 1e12,
                              "unit": "TFLOP/s", "frac": achieved / FP64_VALU_OPS_PEAK, "traffic": profiled_traffic(),
                              "traffic_unit": "bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)",
