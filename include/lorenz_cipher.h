@@ -53,7 +53,7 @@ enum {
 };
 
 /* Integrator of the dynamical system F (Section 3.1 uses forward Euler and
- * notes that other numerical methods could be considered).  Each value is a
+ * leaves the integrator open to other schemes).  Each value is a
  * distinct ciphertext format.
  *  LZ_INTEGRATOR_EULER      forward Euler, 14 separately rounded operations per
  *                           step (the method; the default);

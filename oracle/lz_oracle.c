@@ -51,8 +51,8 @@ typedef struct {
     uint32_t block_len; /* bytes per independent block (parallel version)     */
     uint32_t k[3];      /* moduli of the byte indices Omega, 2 < k_i <= 4     */
     uint32_t integrator; /* 0 Euler (the method), 1 Euler with fused multiply-add,
-                            2 classical Runge-Kutta 4 ("other numerical methods
-                            could be considered", Section 3.1)                 */
+                            2 classical Runge-Kutta 4 (Section 3.1 leaves the
+                            integrator open to other schemes)                  */
 } orc_params;
 
 /* Output of the password stage of Section 3.1. */

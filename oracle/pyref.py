@@ -92,7 +92,7 @@ def _field(x, y, z):
 
 
 def rk4(r, dt, steps):
-    """Classical Runge-Kutta 4 of the Lorenz system ("other numerical methods", Section 3.1)."""
+    """Classical Runge-Kutta 4 of the Lorenz system (a format variant; Section 3.1 leaves the integrator open)."""
     x, y, z = r
     h2, h6 = dt * 0.5, dt / 6.0
     for _ in range(steps):

@@ -339,7 +339,7 @@ def test_threads_do_not_change_output():
     assert np.array_equal(a, b)
 
 
-# ---- integrator variants (Section 3.1: "other numerical methods could be considered") --------
+# ---- integrator variants (Section 3.1 leaves the integrator open to other schemes) --------
 
 def test_variant_fixed_points():
     c = math.sqrt(72.0)
