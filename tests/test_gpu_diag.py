@@ -62,8 +62,11 @@ def test_entropy(lz, ctx, kind):
         assert S == 1.0
 
 
-@pytest.mark.parametrize("n,L", [(0, 5), (1, 0), (10, 20), (5000, 300), (200_003, 256), (1_000_000, 1000)])
+@pytest.mark.parametrize("n,L", [(0, 5), (1, 0), (10, 20), (5000, 300), (200_003, 256), (1_000_000, 1000),
+                                 (50_000, 4095), (50_000, 4096), (30_001, 16384), (3, 16384)])
 def test_lag_sums_exact(lz, ctx, n, L):
+    """Lags below 4096 meet in LDS counters per workgroup; from 4096 up to the limit 16384 each work item
+    adds to the global counters directly: both paths, and lags beyond n, are compared exactly."""
     rng = np.random.default_rng(90 + n)
     x = rng.integers(0, 256, n, dtype=np.uint8)
     got = host(lz.lag_sums(ctx, _dev(x), L)).astype(np.int64)
