@@ -75,7 +75,7 @@ def test_lag_sums_exact(lz, ctx, n, L):
 
 @pytest.mark.parametrize("n,L,kind", [(0, 4, "rand"), (1, 3, "rand"), (7, 12, "rand"), (40, 6, "alt"),
                                       (5000, 300, "rand"), (100_000, 700, "text"), (1000, 5, "const"),
-                                      (300_001, 2000, "rand")])
+                                      (300_001, 2000, "rand"), (20_000, 16384, "rand")])
 def test_autocorrelation_1d(lz, ctx, n, L, kind):
     rng = np.random.default_rng(91 + n)
     if kind == "alt":
