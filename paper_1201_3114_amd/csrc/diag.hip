@@ -15,32 +15,36 @@ namespace {
 
 constexpr int DIAG_WG = 256;
 
-// Byte histogram: each wave counts into its own LDS sub-histogram (fewer
-// same-address collisions), reading 16 bytes per lane and keeping HIST_U loads
-// in flight; the workgroup's sub-histograms are summed and merged into the 256
-// global counters with one atomic per occupied bin.  Block 0 also counts the
-// unaligned head and the tail that does not fill 16 bytes.
+// Byte histogram.  The workgroup's LDS counters hold HIST_COPIES copies of each
+// bin, interleaved (bin * HIST_COPIES + copy, copy = lane mod HIST_COPIES): lanes
+// that see the same byte value hit different addresses in different banks, so
+// skewed input (text, constant runs) does not serialise the LDS atomics, and
+// random input spreads over the banks more evenly.  Each lane reads 16 bytes
+// per load with HIST_U loads in flight; the copies are summed at the end and
+// merged into the 256 global counters with one atomic per occupied bin.
+// Block 0 also counts the unaligned head and the tail that does not fill 16 bytes.
 constexpr int HIST_U = 4;
+constexpr int HIST_COPIES = 16;
 
 __device__ __forceinline__ void count_word(uint32_t *h, uint32_t w) {
-    atomicAdd(&h[w & 0xFF], 1u);
-    atomicAdd(&h[(w >> 8) & 0xFF], 1u);
-    atomicAdd(&h[(w >> 16) & 0xFF], 1u);
-    atomicAdd(&h[w >> 24], 1u);
+    atomicAdd(&h[(w & 0xFF) * HIST_COPIES], 1u);
+    atomicAdd(&h[((w >> 8) & 0xFF) * HIST_COPIES], 1u);
+    atomicAdd(&h[((w >> 16) & 0xFF) * HIST_COPIES], 1u);
+    atomicAdd(&h[(w >> 24) * HIST_COPIES], 1u);
 }
 
 __global__ __launch_bounds__(DIAG_WG) void histogram_kernel(const uint8_t *data, uint64_t n,
                                                              unsigned long long *hist) {
-    __shared__ uint32_t h[DIAG_WG / 64][256];
-    for (int i = threadIdx.x; i < DIAG_WG / 64 * 256; i += DIAG_WG) (&h[0][0])[i] = 0;
+    __shared__ uint32_t h[256 * HIST_COPIES];
+    for (int i = threadIdx.x; i < 256 * HIST_COPIES; i += DIAG_WG) h[i] = 0;
     __syncthreads();
-    uint32_t *hw = h[threadIdx.x / 64];
+    uint32_t *hc = h + threadIdx.x % HIST_COPIES;  // this lane's copy
     const uint64_t head = ((16 - ((uintptr_t)data & 15)) & 15) < n ? ((16 - ((uintptr_t)data & 15)) & 15) : n;
     const uint64_t nv = (n - head) / 16;
     const uint4 *v = reinterpret_cast<const uint4 *>(data + head);
     if (blockIdx.x == 0) {
-        for (uint64_t j = threadIdx.x; j < head; j += DIAG_WG) atomicAdd(&hw[data[j]], 1u);
-        for (uint64_t j = head + nv * 16 + threadIdx.x; j < n; j += DIAG_WG) atomicAdd(&hw[data[j]], 1u);
+        for (uint64_t j = threadIdx.x; j < head; j += DIAG_WG) atomicAdd(&hc[data[j] * HIST_COPIES], 1u);
+        for (uint64_t j = head + nv * 16 + threadIdx.x; j < n; j += DIAG_WG) atomicAdd(&hc[data[j] * HIST_COPIES], 1u);
     }
     const uint64_t stride = (uint64_t)gridDim.x * DIAG_WG;
     for (uint64_t i = (uint64_t)blockIdx.x * DIAG_WG + threadIdx.x; i < nv; i += stride * HIST_U) {
@@ -50,15 +54,15 @@ __global__ __launch_bounds__(DIAG_WG) void histogram_kernel(const uint8_t *data,
 #pragma unroll
         for (int u = 0; u < HIST_U; ++u) {
             if (i + u * stride >= nv) break;
-            count_word(hw, q[u].x);
-            count_word(hw, q[u].y);
-            count_word(hw, q[u].z);
-            count_word(hw, q[u].w);
+            count_word(hc, q[u].x);
+            count_word(hc, q[u].y);
+            count_word(hc, q[u].z);
+            count_word(hc, q[u].w);
         }
     }
     __syncthreads();
     unsigned long long c = 0;
-    for (int w = 0; w < DIAG_WG / 64; ++w) c += h[w][threadIdx.x];
+    for (int k = 0; k < HIST_COPIES; ++k) c += h[threadIdx.x * HIST_COPIES + k];
     if (c) atomicAdd(&hist[threadIdx.x], c);
 }
 
@@ -377,11 +381,11 @@ extern "C" int lz_histogram(lz_ctx *c, const uint8_t *d_data, size_t n, uint64_t
     LZ_HIP(hipSetDevice(c->device));
     LZ_HIP(launch_fill_u64(reinterpret_cast<unsigned long long *>(d_hist), 256, s));
     if (n == 0) return LZ_OK;
-    // about 16 KiB per workgroup at least, at most 2 workgroups per CU; a wave's counters
-    // stay below 2^32 while each workgroup covers fewer than 2^33 bytes
+    // about 16 KiB per workgroup at least, at most 2 workgroups per CU; the 32-bit LDS counters
+    // stay below 2^32 while each workgroup covers fewer than 2^32 bytes
     uint64_t blocks = (n + 16383) / 16384;
     if (blocks > (uint64_t)c->dev.cus * 2) blocks = (uint64_t)c->dev.cus * 2;
-    if (n / blocks >= (1ull << 33)) blocks = (n >> 33) + 1;
+    if (n / blocks >= (1ull << 32) - 1024) blocks = (n >> 31) + 1;
     if (blocks > 0x7FFFFFFFull) return fail(LZ_E_INVAL, "input too long");
     hipLaunchKernelGGL(histogram_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n,
                        reinterpret_cast<unsigned long long *>(d_hist));

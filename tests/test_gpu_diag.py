@@ -45,6 +45,22 @@ def test_histogram_exact(lz, ctx, n):
         assert np.array_equal(host(lz.histogram(ctx, d[1:])).astype(np.int64), dg.histogram(x[1:]))
 
 
+@pytest.mark.parametrize("kind", ["constant", "text", "two_values"])
+def test_histogram_skewed_exact(lz, ctx, kind):
+    """Inputs where many lanes see the same byte value (the case the interleaved LDS copies are for)."""
+    rng = np.random.default_rng(82)
+    n = 5_000_003
+    if kind == "constant":
+        x = np.full(n, 32, np.uint8)
+    elif kind == "text":
+        x = rng.choice(np.frombuffer(b"       eeeetttaaoinshrdlu.,\n", np.uint8), n)
+    else:
+        x = rng.choice(np.array([0, 255], np.uint8), n, p=[0.9, 0.1])
+    d = _dev(x)
+    assert np.array_equal(host(lz.histogram(ctx, d)).astype(np.int64), dg.histogram(x))
+    assert np.array_equal(host(lz.histogram(ctx, d[7:])).astype(np.int64), dg.histogram(x[7:]))
+
+
 @pytest.mark.parametrize("kind", ["empty", "one", "two", "uniform", "skewed", "all"])
 def test_entropy(lz, ctx, kind):
     rng = np.random.default_rng(81)
