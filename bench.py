@@ -363,6 +363,15 @@ def bench_diag(lz, torch, reps=5):
     big = x.repeat(16)
     ms = timed(lambda: lz.histogram(ctx, big))
     res["histogram_1GiB"] = dict(ms=ms, GBps=big.numel() / ms / 1e6, frac_of_hbm=big.numel() / ms * 1e3 / HBM_PEAK)
+    # skewed inputs put equal bytes in many lanes of a wave: English-like text (a 28-symbol alphabet
+    # with spaces and frequent letters repeated) and one constant byte
+    alpha = torch.tensor(list(b"       eeeetttaaoinshrdlu.,\n"), dtype=torch.uint8, device="cuda")
+    big = alpha[(big.to(torch.int32) * len(alpha)) >> 8]
+    ms = timed(lambda: lz.histogram(ctx, big))
+    res["histogram_1GiB_text"] = dict(ms=ms, GBps=big.numel() / ms / 1e6)
+    big.fill_(32)
+    ms = timed(lambda: lz.histogram(ctx, big))
+    res["histogram_1GiB_constant"] = dict(ms=ms, GBps=big.numel() / ms / 1e6)
     del big
     h = lz.histogram(ctx, x)
     res["entropy_bits"] = lz.entropy(ctx, h)
