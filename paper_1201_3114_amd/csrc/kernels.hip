@@ -99,7 +99,9 @@ template <int M, int I>
 __device__ __forceinline__ void lorenz_steps(double (&x)[M], double (&y)[M], double (&z)[M], double dt,
                                              uint32_t n_it) {
     const double h2 = dt * 0.5, h6 = I == LZ_INTEGRATOR_RK4 ? dt / 6.0 : 0.0;
-    constexpr int U = I == LZ_INTEGRATOR_RK4 ? 2 : 8;
+    // Steps per loop iteration: 60 Euler steps for one chain (a divisor of the default 3000, about 6.7 KB
+    // of code), fewer per iteration with more chains; RK4's 68-operation step gains nothing from more.
+    constexpr int U = I == LZ_INTEGRATOR_RK4 ? 2 : 60 / M;
     const uint32_t q = n_it / U;
     for (uint32_t i = 0; i < q; ++i) {
 #pragma unroll
