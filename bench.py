@@ -336,8 +336,9 @@ def bench_streaming(lz, torch):
 # ---------------------------------------------------------------------------------------------
 def bench_diag(lz, torch, reps=5):
     """Section 4 analyses on ciphertext-like (uniform random) bytes: histogram of 1 GiB (HBM-bound),
-    the autocorrelation up to lag 256 of 16 MiB, and the 2-D power spectrum and autocorrelation
-    matrix of a 1024 x 1024 byte image (two / four DFT passes on the binary64 matrix cores)."""
+    the autocorrelation up to lag 256 of 16 MiB, the 2-D power spectrum and autocorrelation matrix
+    of a 1024 x 1024 byte image (two / four FFT passes), and the power spectrum of a 1000 x 1000
+    image (two direct DFT passes on the binary64 matrix cores)."""
     from paper_1201_3114_amd import workloads
 
     ctx = lz.Context(0)
@@ -378,15 +379,22 @@ def bench_diag(lz, torch, reps=5):
     n16, L = 16 * MiB, 256
     ms = timed(lambda: lz.autocorrelation(ctx, x[:n16], L))
     res["autocorrelation_16MiB_lag256"] = dict(ms=ms, int_MAC_per_s=n16 * (L + 1) / ms * 1e3)
+    # power-of-two sides: two FFT passes, bound by HBM; algorithmic bytes: the image (1 B per value)
+    # in, 16 B complex out and in again, 8 B |Z|^2 out
     N = 1024
-    flops_pass = N * N * N * 8  # complex multiply-add = 4 FMA = 8 flops, N x N outputs of N terms
     ms = timed(lambda: lz.power_spectrum_2d(ctx, img))
-    res["power_spectrum_1024x1024"] = dict(ms=ms, TFLOPs=2 * flops_pass / ms / 1e9,
-                                           frac_of_fp64_matrix_peak=2 * flops_pass / ms * 1e3 / FP64_FMA_COUNTED_PEAK)
+    res["power_spectrum_1024x1024"] = dict(ms=ms, route="fft", hbm_GBps=41 * N * N / ms / 1e6)
     ms = timed(lambda: lz.autocorrelation_2d(ctx, img))
-    res["autocorrelation_2d_1024x1024"] = dict(ms=ms, TFLOPs=4 * flops_pass / ms / 1e9)
+    res["autocorrelation_2d_1024x1024"] = dict(ms=ms, route="fft")
     a = lz.autocorrelation_2d(ctx, img)
     res["max_abs_offzero_acf2"] = float(a.flatten()[1:].abs().max())
+    # other sides: the direct DFT, a dense complex matrix product on the binary64 matrix cores
+    N = 1000
+    img_d = x[:N * N].view(N, N)
+    flops_pass = N * N * N * 8  # complex multiply-add = 4 FMA = 8 flops, N x N outputs of N terms
+    ms = timed(lambda: lz.power_spectrum_2d(ctx, img_d))
+    res["power_spectrum_1000x1000"] = dict(ms=ms, route="direct", TFLOPs=2 * flops_pass / ms / 1e9,
+                                           frac_of_fp64_matrix_peak=2 * flops_pass / ms * 1e3 / FP64_FMA_COUNTED_PEAK)
     ctx.close()
     return res
 

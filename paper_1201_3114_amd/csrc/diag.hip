@@ -263,9 +263,31 @@ __device__ __forceinline__ double2 dft_value(double2 v) { return v; }
 // and out-of-range entries are zeroed when stored to LDS.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <typename In>
+// What a pass writes for output value i (row-major in the pass's M x N output): the
+// complex value, |Z|^2, |Z|^2 with entry 0 (the zero frequency of the second pass)
+// set to 0, or Re Z / den (the normalised autocorrelation; NaN when den is).
+enum : int { EPI_COMPLEX = 0, EPI_POWER = 1, EPI_POWER_NODC = 2, EPI_ACF = 3 };
+struct PassOut {
+    double2 *z;
+    double *p;
+    const double *den;
+};
+
+template <int E>
+__device__ __forceinline__ void pass_store(const PassOut &o, size_t i, double re, double im) {
+    if constexpr (E == EPI_COMPLEX) {
+        o.z[i] = make_double2(re, im);
+    } else if constexpr (E == EPI_ACF) {
+        const double d = o.den[0];
+        o.p[i] = d != d ? d : re / d;
+    } else {
+        o.p[i] = (E == EPI_POWER_NODC && i == 0) ? 0.0 : re * re + im * im;
+    }
+}
+
+template <typename In, int E>
 __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32_t N, uint32_t M, const double2 *tw,
-                                                            double sign, double2 *dst) {
+                                                            double sign, PassOut dst) {
     // 64 x 64 outputs per workgroup; each wave takes a 32 x 32 block as 2 x 2 tiles of 16 x 16
     constexpr int TR = DFT_T;
     constexpr int TB = 2;                            // column tiles per wave
@@ -336,16 +358,152 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
         for (int b = 0; b < TB; ++b)
             for (int j = 0; j < 4; ++j) {
                 const uint32_t r = r0 + wr + 16 * a + 4 * j + lk, c = c0 + wc + 16 * b + li;
-                if (r < N && c < M) dst[(size_t)c * N + r] = make_double2(re[a][b][j], im[a][b][j]);
+                if (r < N && c < M) pass_store<E>(dst, (size_t)c * N + r, re[a][b][j], im[a][b][j]);
             }
 }
 
-// |Z|^2 element by element; with zero_dc the (0, 0) entry is set to 0 (the
-// spectrum of the mean-removed image differs from the image's only there).
-__global__ void power_kernel(const double2 *Z, size_t n, double *P, int zero_dc) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const double2 z = Z[i];
-        P[i] = (zero_dc && i == 0) ? 0.0 : z.x * z.x + z.y * z.y;
+// ---- the same pass by FFT, for power-of-two lengths -------------------------------------
+//
+// For N = 2^p <= FFT_MAX the pass uses Stockham autosort stages (the self-sorting
+// FFT): with stride s and n = N / s, a radix-r stage reads the r values
+// x[q + s (j + l n / r)], l < r, takes their r-point DFT, multiplies output k by
+// W_n^{j k} and writes it to x[q + s (r j + k)], so the result ends in natural
+// order.  Radix-4 stages, after one radix-2 stage when p is odd.  A workgroup
+// transforms C adjacent columns in LDS: each input row is read as C contiguous
+// elements and each output row (one column's transform) is written contiguously.
+// Each workgroup computes W^b, b < N/4 (W = e^{sign 2 pi i / N}), into LDS while its
+// input loads are in flight; the stages' other twiddles follow exactly, as
+// W^{a N/4 + b} = (sign i)^a W^b.  About 2.1 p flops per value instead of the
+// direct pass's 8 N.
+constexpr uint32_t FFT_MAX = 4096;
+constexpr uint32_t FFT_WG_ELEMS = 1024;           // complex values per workgroup when N <= 1024 (16 KB of LDS)
+constexpr int FFT_EPT = FFT_MAX / DIAG_WG;        // values per thread, at most
+constexpr int FFT_B2 = FFT_MAX / 2 / DIAG_WG;     // radix-2 butterflies per thread, at most
+constexpr int FFT_B4 = FFT_MAX / 4 / DIAG_WG;     // radix-4 butterflies per thread per stage, at most
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 w) {
+    return make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+}
+
+__host__ __device__ constexpr uint32_t fft_twiddles(uint32_t N) { return N < 4 ? 1 : N / 4; }
+
+// W^j for j < 3N/4 from the quarter table q[b] = W^b: multiplying by W^{N/4} = sign i is exact.
+__device__ __forceinline__ double2 fft_twiddle(const double2 *q, uint32_t j, uint32_t logN, double sign) {
+    if (logN < 2) return make_double2(1.0, 0.0);  // N <= 2 uses j = 0 only
+    const double2 w = q[j & ((1u << (logN - 2)) - 1)];
+    switch (j >> (logN - 2)) {
+        case 0: return w;
+        case 1: return make_double2(-sign * w.y, sign * w.x);
+        default: return make_double2(-w.x, -w.y);
+    }
+}
+
+template <typename In, int E>
+__global__ __launch_bounds__(DIAG_WG) void fft_pass_kernel(const In *src, uint32_t N, uint32_t M, uint32_t logN,
+                                                            uint32_t C, double sign, PassOut dst) {
+    extern __shared__ double2 fbuf[];  // C columns of N values, then the twiddles
+    double2 *ftw = fbuf + (size_t)C * N;
+    // consecutive column groups on the same XCD (workgroups are dealt to the 8 XCDs in turn),
+    // so the partly shared cache lines of neighbouring groups meet in one L2
+    uint32_t g = blockIdx.x;
+    if (gridDim.x % 8 == 0) g = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    const uint32_t c0 = g * C;
+    const uint32_t cols = M - c0 < C ? M - c0 : C;
+    const uint32_t total = cols * N;
+    {
+        // all of a thread's loads are issued before the first is stored, and the twiddles
+        // (the values the table kernel computes: sincospi of 2j / N) are made meanwhile
+        In v[FFT_EPT];
+#pragma unroll
+        for (int i = 0; i < FFT_EPT; ++i) {
+            const uint32_t e = threadIdx.x + i * DIAG_WG;
+            if (e < total) {
+                const uint32_t k = e / cols, cl = e - k * cols;
+                v[i] = src[(size_t)k * M + c0 + cl];
+            }
+        }
+        for (uint32_t j = threadIdx.x; j < fft_twiddles(N); j += DIAG_WG) {
+            double sn, cs;
+            sincospi(2.0 * (double)j / (double)N, &sn, &cs);
+            ftw[j] = make_double2(cs, sign * sn);
+        }
+#pragma unroll
+        for (int i = 0; i < FFT_EPT; ++i) {
+            const uint32_t e = threadIdx.x + i * DIAG_WG;
+            if (e < total) {
+                const uint32_t k = e / cols, cl = e - k * cols;
+                fbuf[cl * N + k] = dft_value(v[i]);
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t st = 0;  // log2 of the stride s
+    if (logN & 1) {
+        // radix-2 stage, s = 1: x[j], x[j + N/2] -> x[2j], x[2j + 1]
+        const uint32_t half = N >> 1, nb = cols * half;
+        double2 a[FFT_B2], b[FFT_B2];
+#pragma unroll
+        for (int i = 0; i < FFT_B2; ++i) {
+            const uint32_t u = threadIdx.x + i * DIAG_WG;
+            if (u < nb) {
+                const double2 *x = fbuf + (u >> (logN - 1)) * N;
+                const uint32_t j = u & (half - 1);
+                a[i] = x[j];
+                b[i] = x[j + half];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < FFT_B2; ++i) {
+            const uint32_t u = threadIdx.x + i * DIAG_WG;
+            if (u < nb) {
+                double2 *x = fbuf + (u >> (logN - 1)) * N;
+                const uint32_t j = u & (half - 1);
+                x[2 * j] = cadd(a[i], b[i]);
+                x[2 * j + 1] = cmul(csub(a[i], b[i]), fft_twiddle(ftw, j, logN, sign));
+            }
+        }
+        __syncthreads();
+        st = 1;
+    }
+    const uint32_t quarter = N >> 2, nb4 = cols * quarter;
+    for (; st < logN; st += 2) {
+        const uint32_t s = 1u << st, m = N >> (st + 2);
+        double2 a[FFT_B4][4];
+#pragma unroll
+        for (int i = 0; i < FFT_B4; ++i) {
+            const uint32_t u = threadIdx.x + i * DIAG_WG;
+            if (u < nb4) {
+                const double2 *x = fbuf + (u >> (logN - 2)) * N;
+                const uint32_t t = u & (quarter - 1), q = t & (s - 1), j = t >> st;
+#pragma unroll
+                for (int l = 0; l < 4; ++l) a[i][l] = x[q + s * (j + l * m)];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < FFT_B4; ++i) {
+            const uint32_t u = threadIdx.x + i * DIAG_WG;
+            if (u < nb4) {
+                double2 *x = fbuf + (u >> (logN - 2)) * N;
+                const uint32_t t = u & (quarter - 1), q = t & (s - 1), j = t >> st;
+                const double2 t0 = cadd(a[i][0], a[i][2]), t1 = csub(a[i][0], a[i][2]);
+                const double2 t2 = cadd(a[i][1], a[i][3]), t3 = csub(a[i][1], a[i][3]);
+                const double2 rt3 = make_double2(-sign * t3.y, sign * t3.x);  // W_4 t3, W_4 = sign i
+                const uint32_t w = t - q;                                    // j s: W_n^{j k} = table[j s k]
+                x[q + s * (4 * j)] = cadd(t0, t2);
+                x[q + s * (4 * j + 1)] = cmul(cadd(t1, rt3), fft_twiddle(ftw, w, logN, sign));
+                x[q + s * (4 * j + 2)] = cmul(csub(t0, t2), fft_twiddle(ftw, 2 * w, logN, sign));
+                x[q + s * (4 * j + 3)] = cmul(csub(t1, rt3), fft_twiddle(ftw, 3 * w, logN, sign));
+            }
+        }
+        __syncthreads();
+    }
+    for (uint32_t e = threadIdx.x; e < total; e += DIAG_WG) {
+        const double2 v = fbuf[e];
+        pass_store<E>(dst, (size_t)c0 * N + e, v.x, v.y);
     }
 }
 
@@ -361,13 +519,6 @@ __global__ __launch_bounds__(DIAG_WG) void acf2_den_kernel(const unsigned long l
         const unsigned long long d = (unsigned long long)n * s2 - s1 * s1;
         den[0] = d == 0 ? __builtin_nan("") : (double)d;
     }
-}
-
-// A = Re(G) / (n S2 - S1^2), G the unnormalised inverse DFT of the mean-removed power spectrum.
-__global__ void acf2_norm_kernel(const double2 *G, size_t n, const double *den, double *A) {
-    const double d = den[0];
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        A[i] = d != d ? d : G[i].x / d;
 }
 
 }  // namespace
@@ -472,28 +623,50 @@ size_t dft2_bytes(uint32_t h, uint32_t w, size_t extra) {
            2 * align256((size_t)h * w * sizeof(double2));
 }
 
-int launch_twiddles(const Dft2 &d, uint32_t h, uint32_t w, hipStream_t s) {
-    hipLaunchKernelGGL(twiddle_kernel, dim3((h + 255) / 256), dim3(256), 0, s, d.tw_h, h);
-    hipLaunchKernelGGL(twiddle_kernel, dim3((w + 255) / 256), dim3(256), 0, s, d.tw_w, w);
+bool fft_ok(const lz_ctx *c, uint32_t N);
+
+// The twiddle tables of the lengths the direct pass transforms (the FFT makes its own).
+int launch_twiddles(const lz_ctx *c, const Dft2 &d, uint32_t h, uint32_t w, hipStream_t s) {
+    if (!fft_ok(c, h)) hipLaunchKernelGGL(twiddle_kernel, dim3((h + 255) / 256), dim3(256), 0, s, d.tw_h, h);
+    if (!fft_ok(c, w)) hipLaunchKernelGGL(twiddle_kernel, dim3((w + 255) / 256), dim3(256), 0, s, d.tw_w, w);
     LZ_HIP(hipGetLastError());
     return LZ_OK;
 }
 
-// dst (M x N) = transpose of (DFT_N along the rows of src (N x M)), 64 x 64 outputs per workgroup.
-template <typename In>
-int launch_dft_pass(const In *src, uint32_t N, uint32_t M, const double2 *tw, double sign, double2 *dst,
-                    hipStream_t s) {
-    const dim3 grid((N + DFT_T - 1) / DFT_T, (M + DFT_T - 1) / DFT_T);
-    hipLaunchKernelGGL((dft_pass_kernel<In>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, dst);
+bool fft_ok(const lz_ctx *c, uint32_t N) {
+    const uint32_t per_wg = N > FFT_WG_ELEMS ? N : FFT_WG_ELEMS;
+    const size_t lds = ((size_t)per_wg + fft_twiddles(N)) * sizeof(double2);
+    return (N & (N - 1)) == 0 && N <= FFT_MAX && lds <= (size_t)c->dev.lds_per_wg_max;
+}
+
+// Output (M x N) = transpose of (DFT_N along the rows of src (N x M)), stored by epilogue E:
+// by FFT when N is a power of two up to FFT_MAX, otherwise directly on the matrix cores with
+// 64 x 64 outputs per workgroup (tw: the N-entry table, needed only then).
+template <typename In, int E>
+int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, const double2 *tw, double sign,
+                    PassOut out, hipStream_t s) {
+    if (fft_ok(c, N)) {
+        uint32_t logN = 0;
+        while ((1u << logN) < N) ++logN;
+        const uint32_t per_wg = N > FFT_WG_ELEMS ? N : FFT_WG_ELEMS;
+        const uint32_t C = per_wg / N;
+        const uint32_t groups = (M + C - 1) / C;
+        const size_t lds = ((size_t)per_wg + fft_twiddles(N)) * sizeof(double2);
+        if (lds > 65536)
+            LZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_pass_kernel<In, E>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL((fft_pass_kernel<In, E>), dim3(groups), dim3(DIAG_WG), lds, s, src, N, M, logN, C, sign,
+                           out);
+    } else {
+        const dim3 grid((N + DFT_T - 1) / DFT_T, (M + DFT_T - 1) / DFT_T);
+        hipLaunchKernelGGL((dft_pass_kernel<In, E>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, out);
+    }
     LZ_HIP(hipGetLastError());
     return LZ_OK;
 }
 
-unsigned grid_for(size_t n, const lz_ctx *c) {
-    size_t b = (n + 255) / 256;
-    const size_t cap = (size_t)c->dev.cus * 8;
-    return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
-}
+PassOut complex_out(double2 *z) { return PassOut{z, nullptr, nullptr}; }
+PassOut real_out(double *p, const double *den = nullptr) { return PassOut{nullptr, p, den}; }
 
 }  // namespace
 
@@ -534,12 +707,10 @@ extern "C" int lz_power_spectrum_2d(lz_ctx *c, const uint8_t *d_img, uint32_t h,
     char *ws;
     if (int rc = diag_begin(c, s, dft2_bytes(h, w, 0), &ws)) return rc;
     const Dft2 d = dft2_layout(ws, h, w, 0);
-    if (int rc = launch_twiddles(d, h, w, s)) return rc;
-    if (int rc = launch_dft_pass<uint8_t>(d_img, h, w, d.tw_h, -1.0, d.a, s)) return rc;  // a: w x h
-    if (int rc = launch_dft_pass<double2>(d.a, w, h, d.tw_w, -1.0, d.b, s)) return rc;   // b: h x w = Z
-    const size_t n = (size_t)h * w;
-    hipLaunchKernelGGL(power_kernel, dim3(grid_for(n, c)), dim3(256), 0, s, d.b, n, d_power, 0);
-    LZ_HIP(hipGetLastError());
+    if (int rc = launch_twiddles(c, d, h, w, s)) return rc;
+    // a: w x h; then |Z|^2 of the second pass (h x w) straight into the output
+    if (int rc = launch_dft_pass<uint8_t, EPI_COMPLEX>(c, d_img, h, w, d.tw_h, -1.0, complex_out(d.a), s)) return rc;
+    if (int rc = launch_dft_pass<double2, EPI_POWER>(c, d.a, w, h, d.tw_w, -1.0, real_out(d_power), s)) return rc;
     return diag_end(c, s);
 }
 
@@ -559,15 +730,12 @@ extern "C" int lz_autocorrelation_2d(lz_ctx *c, const uint8_t *d_img, uint32_t h
     hipLaunchKernelGGL(acf2_den_kernel, dim3(1), dim3(DIAG_WG), 0, s,
                        reinterpret_cast<const unsigned long long *>(hist), (uint64_t)n, den);
     LZ_HIP(hipGetLastError());
-    if (int rc = launch_twiddles(d, h, w, s)) return rc;
-    if (int rc = launch_dft_pass<uint8_t>(d_img, h, w, d.tw_h, -1.0, d.a, s)) return rc;  // a: w x h
-    if (int rc = launch_dft_pass<double2>(d.a, w, h, d.tw_w, -1.0, d.b, s)) return rc;   // b: Z, h x w
-    double *pm = reinterpret_cast<double *>(d.a);                                         // a: |Z|^2, DC = 0
-    hipLaunchKernelGGL(power_kernel, dim3(grid_for(n, c)), dim3(256), 0, s, d.b, n, pm, 1);
-    LZ_HIP(hipGetLastError());
-    if (int rc = launch_dft_pass<double>(pm, h, w, d.tw_h, 1.0, d.b, s)) return rc;       // b: w x h
-    if (int rc = launch_dft_pass<double2>(d.b, w, h, d.tw_w, 1.0, d.a, s)) return rc;     // a: G, h x w
-    hipLaunchKernelGGL(acf2_norm_kernel, dim3(grid_for(n, c)), dim3(256), 0, s, d.a, n, den, d_acf);
-    LZ_HIP(hipGetLastError());
+    if (int rc = launch_twiddles(c, d, h, w, s)) return rc;
+    // a: w x h; b: |Z|^2 with the zero frequency removed (h x w); a: w x h; then Re G / den
+    double *pm = reinterpret_cast<double *>(d.b);
+    if (int rc = launch_dft_pass<uint8_t, EPI_COMPLEX>(c, d_img, h, w, d.tw_h, -1.0, complex_out(d.a), s)) return rc;
+    if (int rc = launch_dft_pass<double2, EPI_POWER_NODC>(c, d.a, w, h, d.tw_w, -1.0, real_out(pm), s)) return rc;
+    if (int rc = launch_dft_pass<double, EPI_COMPLEX>(c, pm, h, w, d.tw_h, 1.0, complex_out(d.a), s)) return rc;
+    if (int rc = launch_dft_pass<double2, EPI_ACF>(c, d.a, w, h, d.tw_w, 1.0, real_out(d_acf, den), s)) return rc;
     return diag_end(c, s);
 }

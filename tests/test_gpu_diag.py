@@ -117,10 +117,13 @@ def test_autocorrelation_1d(lz, ctx, n, L, kind):
 
 
 def _dz_max(x):
-    """Bound on the error of each DFT value Z[u][v] after the two passes.  A pass sums N complex
-    products w x with |w| = 1 in fused multiply-adds, 2N roundings per real component, so each
-    component is off by at most 2N eps sum|x| (twiddle errors add a few eps more); the complex
-    magnitude adds sqrt 2 twice over.  Both passes: |dZ| <= 4 (h + w + 4) eps S1, S1 = sum x."""
+    """Bound on the error of each DFT value Z[u][v] after the two passes.  A direct pass sums N
+    complex products w x with |w| = 1 in fused multiply-adds, 2N roundings per real component, so
+    each component is off by at most 2N eps sum|x| (twiddle errors add a few eps more); the complex
+    magnitude adds sqrt 2 twice over.  Both passes: |dZ| <= 4 (h + w + 4) eps S1, S1 = sum x.
+    A radix-2 FFT pass (power-of-two lengths) is within the same bound: each of its log2 N stages
+    adds at most about 6 eps times the magnitude of partial sums whose moduli add up to at most
+    sum|x|, so |dZ| <= 6 (log2 h + log2 w) eps S1 < 4 (h + w + 4) eps S1."""
     h, w = x.shape
     return 4 * (h + w + 4) * EPS * float(x.astype(np.float64).sum())
 
@@ -132,11 +135,12 @@ def _power_tol(x):
     return 2 * S1 * dz + dz * dz + 2 * EPS * S1 * S1
 
 
-@pytest.mark.parametrize("h,w", [(1, 1), (1, 37), (29, 1), (8, 8), (64, 64), (67, 131), (128, 200), (512, 512),
-                                 (3, 4096), (2048, 2048)])
+@pytest.mark.parametrize("h,w", [(1, 1), (1, 37), (29, 1), (2, 2), (8, 8), (64, 64), (67, 131), (128, 200),
+                                 (512, 512), (3, 4096), (4096, 3), (2048, 2048), (2, 8192), (1000, 24)])
 def test_power_spectrum_2d(lz, ctx, h, w):
-    """(2048, 2048) has 1,024 tiles of 64 x 64 outputs per pass, so it runs the 64-row tile variant of the
-    DFT pass on a 256-CU device; the smaller sizes run the 32-row variant."""
+    """Both routes of a pass: FFT for power-of-two lengths up to 4096 (8, 64, 512, 2048, 4096, and
+    the 1 x 1 identity), the direct DFT on the matrix cores for the others (37, 29, 67, 131, 200,
+    1000, 24, 3) and for 8192, above the FFT's limit; (3, 4096), (2, 8192) and (1000, 24) mix them."""
     rng = np.random.default_rng(100 + h * 7 + w)
     x = rng.integers(0, 256, (h, w), dtype=np.uint8)
     say("power spectrum", h, w)
@@ -215,6 +219,21 @@ def test_autocorrelation_2d_sampled_large(lz, ctx):
         want = dg.autocorrelation_2d_at(img, int(dx), int(dy))
         assert abs(got[dx, dy] - want) <= tol, (dx, dy, got[dx, dy], want, tol)
     assert abs(got[0, 0] - 1.0) <= tol
+
+
+def test_autocorrelation_2d_sampled_fft_sizes(lz, ctx):
+    """1024 x 1024 (all four passes by FFT), checked at sampled lags against exact ratios."""
+    rng = np.random.default_rng(121)
+    H = W = 1024
+    img = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    img[::3, ::5] = 0  # some structure, so the coefficients are not all near zero
+    got = host(lz.autocorrelation_2d(ctx, to_dev(img.ravel()).view(H, W)))
+    tol = _acf2_tol(img)
+    lags = [(0, 0), (1, 0), (0, 1), (3, 5), (6, 10), (512, 512), (H - 1, W - 1)]
+    lags += [tuple(v) for v in rng.integers(0, [H, W], (6, 2))]
+    for dx, dy in lags:
+        want = dg.autocorrelation_2d_at(img, int(dx), int(dy))
+        assert abs(got[dx, dy] - want) <= tol, (dx, dy, got[dx, dy], want, tol)
 
 
 def test_diagnostics_of_a_ciphertext(lz, ctx):
