@@ -147,8 +147,6 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_kernel(const uint8_t *data, ui
     }
 }
 
-// ---- entropy and the normalised 1-D autocorrelation -------------------------------------
-
 // Block-wide sum over 256 threads (LDS tree, fixed order, so the result is deterministic).
 template <typename T>
 __device__ T block_sum(T v, T *red) {
@@ -162,6 +160,209 @@ __device__ T block_sum(T v, T *red) {
     __syncthreads();
     return r;
 }
+
+// ---- the lag sums on the matrix cores, for L < AC_LDS_LAGS ---------------------------------
+//
+// With the bytes laid out as rows of 16, S_k is a sum along the diagonals of
+// G[c][j] = sum_r x[16 r + c] x[16 r + j] (c < 16, j < L + 16; lag k = j - c):
+// an integer matrix product with the rows as its inner dimension, which runs on
+// v_mfma_i32_16x16x64_i8 (64 rows per instruction).  The matrix cores take signed
+// bytes, so the kernel works with x - 128 (byte XOR 0x80; 0 past n) and
+//   S_k = S'_k + 256 T - 128 (P_k + Q_k) - 16384 max(n - k, 0),
+// T the byte total, P_k and Q_k the sums of the first and the last min(k, n)
+// bytes: each workgroup adds 256 times its bytes' total into its one atomic per
+// lag, and lagsum_fix_kernel applies the rest.
+//
+// A task is a chunk of MC_ROWS rows, staged in LDS column by column (lt[c][r],
+// row stride a multiple of 16) together with the rows the shifted operands reach
+// past it.  Matrix-core operands (lane l, g = l / 16, byte t < 16): A = x'[row
+// rb + 16g + t, column l % 16], B = x'[row rb + jt + 16g + t, column l % 16] for
+// column tile jt, both 16 consecutive bytes of one LDS column; the result holds
+// G[4g + i][16 jt + l % 16] in its i-th register.  A lane reads 24 bytes of its
+// column once per row block and tile group and forms the B operands of the
+// group's eight tiles (shifts 0..7) with alignbyte; all eight run (a group past
+// the last tile reads the same in-range bytes) and the extra tiles are dropped.
+// A work item is one tile group over all the chunk's rows, or over a half or a
+// quarter of them when there are two groups or one (so that four waves have work).  At its end the lanes whose
+// results lie on the same diagonals (lane l and l + 20: column + 4, row + 4) add
+// theirs up in two shuffle steps, and the 28 chain heads add the 32-bit sums (at
+// most 4 lanes x 2048 rows x 16384 < 2^31) into 64-bit LDS lag counters, no two
+// of them on one lag.
+constexpr uint32_t MC_ROWS = 2048;
+
+struct McShape {
+    uint32_t nt, ntg, rs, stride;  // column tiles, tile groups of 8, row splits, LDS column stride (bytes)
+};
+
+__host__ __device__ inline McShape mc_shape(uint32_t L) {
+    McShape m;
+    m.nt = (L + 15) / 16 + 1;
+    m.ntg = (m.nt + 7) / 8;
+    m.rs = m.ntg >= 3 ? 1 : 4 / m.ntg;
+    m.stride = MC_ROWS + 16 * ((m.ntg + 1) / 2);
+    return m;
+}
+
+size_t lagsum_mc_lds_bytes(uint32_t L) {
+    const McShape m = mc_shape(L);
+    return ((size_t)(L + 1) * 8 + 15) / 16 * 16 + (size_t)16 * m.stride;
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(DIAG_WG) void lagsum_mc_kernel(const uint8_t *data, uint64_t n, uint32_t L,
+                                                             unsigned long long *sums) {
+    extern __shared__ uint32_t lds[];
+    const McShape ms = mc_shape(L);
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(lds);
+    uint8_t *lt = reinterpret_cast<uint8_t *>(lds) + ((size_t)(L + 1) * 8 + 15) / 16 * 16;
+    for (uint32_t k = threadIdx.x; k <= L; k += DIAG_WG) acc[k] = 0;
+    const uint32_t lane = threadIdx.x % 64;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // uniform: scalar branches
+    const uint32_t col = lane % 16, g = lane / 16;
+    const uint64_t nrows = (n + 15) / 16;
+    const uint64_t tasks = (nrows + MC_ROWS - 1) / MC_ROWS;
+    const uint32_t items = ms.ntg * ms.rs, rows_per_item = MC_ROWS / ms.rs;
+    const bool aligned16 = (reinterpret_cast<uintptr_t>(data) & 15) == 0;
+    unsigned long long tsum = 0;  // this thread's share of the bytes of the tasks' own rows
+    for (uint64_t task = blockIdx.x; task < tasks; task += gridDim.x) {
+        const uint64_t row0 = task * MC_ROWS;
+        __syncthreads();  // the previous task's operand reads are done
+        // stage: a thread takes rows 4e..4e+3 (four 16-byte loads), and each column's four bytes of
+        // them become one LDS word lt[c][4e .. 4e+3]
+        for (uint32_t e = threadIdx.x; e < ms.stride / 4; e += DIAG_WG) {
+            uint32_t w[4][4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint64_t i0 = (row0 + 4 * e + j) * 16;
+                if (aligned16 && i0 + 16 <= n) {
+                    const uint4 v = *reinterpret_cast<const uint4 *>(data + i0);
+                    w[j][0] = v.x, w[j][1] = v.y, w[j][2] = v.z, w[j][3] = v.w;
+                    if (4 * e + j < MC_ROWS)
+                        for (int q = 0; q < 4; ++q) tsum += __builtin_amdgcn_udot4(w[j][q], 0x01010101u, 0u, false);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) w[j][q] ^= 0x80808080u;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        uint32_t v = 0;
+                        for (int b = 0; b < 4; ++b) {
+                            const uint64_t i = i0 + 4 * q + b;
+                            if (i < n) {
+                                const uint32_t x = data[i];
+                                if (4 * e + j < MC_ROWS) tsum += x;
+                                v |= (x ^ 0x80u) << (8 * b);
+                            }
+                        }
+                        w[j][q] = v;
+                    }
+                }
+            }
+            uint32_t *lt32 = reinterpret_cast<uint32_t *>(lt);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int q = c / 4, sh = 8 * (c % 4);
+                lt32[(c * ms.stride) / 4 + e] = ((w[0][q] >> sh) & 0xFFu) | (((w[1][q] >> sh) & 0xFFu) << 8) |
+                                                (((w[2][q] >> sh) & 0xFFu) << 16) | (((w[3][q] >> sh) & 0xFFu) << 24);
+            }
+        }
+        __syncthreads();
+        for (uint32_t item = wave; item < items; item += DIAG_WG / 64) {
+            const uint32_t tg = item / ms.rs, rsub = item % ms.rs;
+            v4i d[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) d[t] = (v4i){0, 0, 0, 0};
+            const uint32_t r_end = (rsub + 1) * rows_per_item;
+            for (uint32_t rb = rsub * rows_per_item; rb < r_end; rb += 64) {
+                const uint8_t *colp = lt + (size_t)col * ms.stride;
+                const uint4 av = *reinterpret_cast<const uint4 *>(colp + rb + 16 * g);
+                const v4i a = (v4i){(int)av.x, (int)av.y, (int)av.z, (int)av.w};
+                const uint8_t *bp = colp + rb + 8 * tg + 16 * g;
+                const uint2 w01 = *reinterpret_cast<const uint2 *>(bp);
+                const uint2 w23 = *reinterpret_cast<const uint2 *>(bp + 8);
+                const uint2 w45 = *reinterpret_cast<const uint2 *>(bp + 16);
+                const uint32_t w[6] = {w01.x, w01.y, w23.x, w23.y, w45.x, w45.y};
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    v4i b;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        b[j] = (int)__builtin_amdgcn_alignbyte(w[t / 4 + j + 1], w[t / 4 + j], t % 4);
+                    d[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, d[t], 0, 0, 0);
+                }
+            }
+            // lane l holds lags 16 jt + (l % 16) - 4 (l / 16) - i; lanes l, l + 20, l + 40, l + 60 hold the same
+            const bool has20 = g < 3 && col < 12, has40 = g < 2 && col < 8;
+            const bool head = g == 0 || col < 4;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const uint32_t jt = 8 * tg + t;
+                if (jt >= ms.nt) continue;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    int v = d[t][i];
+                    const int v20 = __shfl(v, (int)lane + 20 < 64 ? (int)lane + 20 : (int)lane, 64);
+                    v += has20 ? v20 : 0;
+                    const int v40 = __shfl(v, (int)lane + 40 < 64 ? (int)lane + 40 : (int)lane, 64);
+                    v += has40 ? v40 : 0;
+                    const int k = (int)(16 * jt + col) - (int)(4 * g + i);
+                    if (head && k >= 0 && k <= (int)L && v != 0) atomicAdd(&acc[k], (unsigned long long)(long long)v);
+                }
+            }
+        }
+    }
+    // 256 T: the block's byte total, added to every lag with the block's sums
+    __shared__ unsigned long long tred[DIAG_WG];
+    const unsigned long long tot = block_sum<unsigned long long>(tsum, tred);
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k <= L; k += DIAG_WG) {
+        const unsigned long long v = acc[k] + 256ull * tot;
+        if (v) atomicAdd(&sums[k], v);
+    }
+}
+
+// S_k = raw_k - 128 (P_k + Q_k) - 16384 max(n - k, 0) for k <= L < AC_LDS_LAGS, with
+// P_k and Q_k the sums of the first and the last min(k, n) bytes (one workgroup:
+// thread t holds values 16t .. 16t+15 of both ends, then a block-wide scan).
+__global__ __launch_bounds__(DIAG_WG) void lagsum_fix_kernel(const uint8_t *data, uint64_t n, uint32_t L,
+                                                             unsigned long long *sums) {
+    constexpr uint32_t SEG = AC_LDS_LAGS / DIAG_WG;  // 16
+    __shared__ uint32_t scan[2][DIAG_WG];
+    const uint32_t t = threadIdx.x;
+    uint32_t v[2][SEG], tot[2] = {0, 0};
+#pragma unroll
+    for (uint32_t u = 0; u < SEG; ++u) {
+        const uint64_t j = (uint64_t)t * SEG + u;
+        v[0][u] = j < n ? data[j] : 0u;          // x_0, x_1, ...
+        v[1][u] = j < n ? data[n - 1 - j] : 0u;  // x_{n-1}, x_{n-2}, ...
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < SEG; ++u) tot[0] += v[0][u], tot[1] += v[1][u];
+    scan[0][t] = tot[0];
+    scan[1][t] = tot[1];
+    __syncthreads();
+    for (uint32_t d = 1; d < DIAG_WG; d <<= 1) {  // inclusive scan (Hillis-Steele)
+        const uint32_t a0 = t >= d ? scan[0][t - d] : 0u, a1 = t >= d ? scan[1][t - d] : 0u;
+        __syncthreads();
+        scan[0][t] += a0;
+        scan[1][t] += a1;
+        __syncthreads();
+    }
+    uint32_t p0 = scan[0][t] - tot[0], p1 = scan[1][t] - tot[1];  // sums of the first 16t values
+#pragma unroll
+    for (uint32_t u = 0; u < SEG; ++u) {
+        const uint32_t k = t * SEG + u;
+        if (k <= L) {
+            const unsigned long long m = k < n ? n - k : 0;
+            sums[k] = sums[k] - 128ull * ((unsigned long long)p0 + p1) - 16384ull * m;
+        }
+        p0 += v[0][u];
+        p1 += v[1][u];
+    }
+}
+
+// ---- entropy and the normalised 1-D autocorrelation -------------------------------------
+
 
 // S = -sum p_i log2 p_i with p_i = h_i / n over the occupied byte values; S = 0 when n = 0.
 __global__ __launch_bounds__(DIAG_WG) void entropy_kernel(const unsigned long long *hist, double *out) {
@@ -552,10 +753,23 @@ extern "C" int lz_lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t 
     LZ_HIP(hipSetDevice(c->device));
     LZ_HIP(launch_fill_u64(reinterpret_cast<unsigned long long *>(d_sums), (size_t)max_lag + 1, s));
     if (n == 0) return LZ_OK;
-    uint64_t blocks = (n + AC_TILE - 1) / AC_TILE;
-    if (blocks > (uint64_t)c->dev.cus * 2) blocks = (uint64_t)c->dev.cus * 2;
-    hipLaunchKernelGGL(lagsum_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), lagsum_lds_bytes(max_lag), s, d_data,
-                       (uint64_t)n, max_lag, reinterpret_cast<unsigned long long *>(d_sums));
+    unsigned long long *sums = reinterpret_cast<unsigned long long *>(d_sums);
+    const size_t mc_lds = lagsum_mc_lds_bytes(max_lag);
+    if (max_lag < AC_LDS_LAGS && mc_lds <= (size_t)c->dev.lds_per_wg_max) {
+        const uint64_t tasks = ((n + 15) / 16 + MC_ROWS - 1) / MC_ROWS;
+        const uint64_t blocks = tasks < (uint64_t)c->dev.cus * 2 ? tasks : (uint64_t)c->dev.cus * 2;
+        if (mc_lds > 65536)
+            LZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&lagsum_mc_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)mc_lds));
+        hipLaunchKernelGGL(lagsum_mc_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), mc_lds, s, d_data, (uint64_t)n,
+                           max_lag, sums);
+        hipLaunchKernelGGL(lagsum_fix_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag, sums);
+    } else {
+        uint64_t blocks = (n + AC_TILE - 1) / AC_TILE;
+        if (blocks > (uint64_t)c->dev.cus * 2) blocks = (uint64_t)c->dev.cus * 2;
+        hipLaunchKernelGGL(lagsum_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), lagsum_lds_bytes(max_lag), s, d_data,
+                           (uint64_t)n, max_lag, sums);
+    }
     LZ_HIP(hipGetLastError());
     return LZ_OK;
 }

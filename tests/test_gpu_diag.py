@@ -79,14 +79,37 @@ def test_entropy(lz, ctx, kind):
 
 
 @pytest.mark.parametrize("n,L", [(0, 5), (1, 0), (10, 20), (5000, 300), (200_003, 256), (1_000_000, 1000),
-                                 (50_000, 4095), (50_000, 4096), (30_001, 16384), (3, 16384)])
+                                 (50_000, 4095), (50_000, 4096), (30_001, 16384), (3, 16384), (15, 1), (16, 16),
+                                 (65_537, 127), (98_309, 511)])
 def test_lag_sums_exact(lz, ctx, n, L):
-    """Lags below 4096 meet in LDS counters per workgroup; from 4096 up to the limit 16384 each work item
-    adds to the global counters directly: both paths, and lags beyond n, are compared exactly."""
+    """Lags below 4096 run on the matrix cores (bytes offset by -128, then corrected exactly); from 4096 up
+    to the limit 16384 on the four-byte dot products, each work item adding to the global counters
+    directly: both paths, lags beyond n and partial 16-byte rows are compared exactly."""
     rng = np.random.default_rng(90 + n)
     x = rng.integers(0, 256, n, dtype=np.uint8)
     got = host(lz.lag_sums(ctx, _dev(x), L)).astype(np.int64)
     assert np.array_equal(got, dg.lag_sums(x, L))
+
+
+@pytest.mark.parametrize("L", [0, 100, 4095])
+def test_lag_sums_unaligned_and_many_tasks(lz, ctx, L):
+    """A data pointer off 4-byte alignment (byte loads when staging), and 40 MiB + 3 bytes: more
+    2048-row tasks than workgroups on a 256-CU device, so workgroups take several tasks in turn.
+    The large case is checked exactly at sampled lags (a lag sum is a plain dot product)."""
+    import torch
+
+    rng = np.random.default_rng(95 + L)
+    x = rng.integers(0, 256, 300_001, dtype=np.uint8)
+    d = _dev(x)
+    got = host(lz.lag_sums(ctx, d[3:], L)).astype(np.int64)
+    assert np.array_equal(got, dg.lag_sums(x[3:], L))
+    n = 40 * (1 << 20) + 3
+    big = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda",
+                        generator=torch.Generator(device="cuda").manual_seed(96 + L))
+    got = host(lz.lag_sums(ctx, big, L)).astype(np.int64)
+    xb = host(big).astype(np.int64)
+    for k in sorted({0, min(1, L), L // 2, L}):
+        assert got[k] == int(np.dot(xb[: n - k], xb[k:])), k
 
 
 @pytest.mark.parametrize("n,L,kind", [(0, 4, "rand"), (1, 3, "rand"), (7, 12, "rand"), (40, 6, "alt"),
