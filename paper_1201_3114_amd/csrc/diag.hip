@@ -3,7 +3,10 @@
 // sequence, and, for a byte matrix (a text or an image laid out row by row),
 // the circular autocorrelation matrix and the 2-D Fourier power spectrum.
 // Integer sums are exact (the results do not depend on the reduction order);
-// the floating-point results are binary64.
+// the floating-point results are binary64.  The lag sums (below 4096 lags) are
+// int8 matrix products and the 2-D transforms of sides that are not powers of
+// two are binary64 matrix products, both on the matrix cores; power-of-two sides
+// are transformed by FFT.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -183,11 +186,11 @@ __device__ T block_sum(T v, T *red) {
 // group's eight tiles (shifts 0..7) with alignbyte; all eight run (a group past
 // the last tile reads the same in-range bytes) and the extra tiles are dropped.
 // A work item is one tile group over all the chunk's rows, or over a half or a
-// quarter of them when there are two groups or one (so that four waves have work).  At its end the lanes whose
-// results lie on the same diagonals (lane l and l + 20: column + 4, row + 4) add
-// theirs up in two shuffle steps, and the 28 chain heads add the 32-bit sums (at
-// most 4 lanes x 2048 rows x 16384 < 2^31) into 64-bit LDS lag counters, no two
-// of them on one lag.
+// quarter of them when there are two groups or one (so that four waves have
+// work).  At its end the lanes whose results lie on the same diagonals (lane l
+// and l + 20: column + 4, row + 4) add theirs up in two shuffle steps, and the 28
+// chain heads add the 32-bit sums (at most 4 lanes x 2048 rows x 16384 < 2^31)
+// into 64-bit LDS lag counters, no two of them on one lag.
 constexpr uint32_t MC_ROWS = 2048;
 
 struct McShape {
