@@ -212,15 +212,15 @@ int lz_autotune(lz_ctx *ctx, double budget_ms, lz_launch *best);
  * reports LZ_OK; the caller must not release them before that.
  *
  * lz_stream_open: pw host pointer, 1..64 bytes; the stream owns about 200
- * bytes of device memory (two chain checkpoints and the running tag) and two
- * internal HIP streams on which the partial blocks of an update run beside its
- * full blocks.  Synchronous. */
+ * bytes of device memory (two chain checkpoints and the running tag) and one
+ * event.  Synchronous. */
 int lz_stream_open(lz_ctx *ctx, int decrypt, const uint8_t *pw, size_t n_pw, lz_stream **out);
 
 /* Processes the next n bytes: d_in and d_out device pointers of n bytes
  * (plaintext in / ciphertext body out, or the reverse; no tag).  Asynchronous
- * on stream; calls are ordered among themselves even across streams.
- * LZ_E_INVAL after lz_stream_finish or past 2^32 bytes in total. */
+ * on stream, as one kernel launch (the update's whole blocks and the chains
+ * of its partial blocks); calls are ordered among themselves even across
+ * streams.  LZ_E_INVAL after lz_stream_finish or past 2^32 bytes in total. */
 int lz_stream_update(lz_stream *st, const uint8_t *d_in, size_t n, uint8_t *d_out, void *stream);
 
 /* Ends the message.  Encrypt: writes the 24-byte tag to d_tag (device).

@@ -53,6 +53,25 @@ struct ChainSlot {
     uint32_t pad2;
 };
 
+// The two partial-block chains of a stream update, carried by a plain launch as the
+// lanes after its nb whole blocks: the head finishes the pending partial block from
+// its checkpoint (its digest joins the tag when it completes the block, else the
+// checkpoint is saved back), the tail starts the next partial block and saves its
+// checkpoint.  Running them in the same launch keeps them from adding a wave to a
+// SIMD that already runs whole-block waves, which would make that SIMD, and so the
+// launch, take longer.
+struct StreamExtra {
+    ChainSlot *head_slot;  // null: no head chain
+    const uint8_t *head_in;
+    uint8_t *head_out;
+    uint32_t head_cnt, head_complete;
+    ChainSlot *tail_slot;  // null: no tail chain
+    const uint8_t *tail_in;
+    uint8_t *tail_out;
+    uint32_t tail_cnt;
+    uint64_t tail_block;
+};
+
 // Per-request record of the served path (device memory).
 struct ReqDesc {
     MsgDesc m;
@@ -79,6 +98,11 @@ hipError_t launch_fill_u64(unsigned long long *p, size_t n, hipStream_t s);
 hipError_t launch_plain(const KernelShape &sh, const lz_key &key, const lz_params &prm, int decrypt,
                         const uint8_t *in, uint8_t *out, uint64_t n, unsigned long long *tag_acc,
                         hipStream_t s, uint64_t block_base = 0);
+// One stream update: its full whole blocks from in / out at global block index
+// block_base, plus x's head and tail chains, in one launch of one chain per lane.
+hipError_t launch_stream_step(const KernelShape &shape, const lz_key &key, const lz_params &prm, int decrypt,
+                              const uint8_t *in, uint8_t *out, uint64_t full, uint64_t block_base,
+                              const StreamExtra &x, unsigned long long *tag_acc, hipStream_t s);
 hipError_t launch_plain_finalize(int decrypt, const unsigned long long *tag_acc, const uint8_t *stored_tag,
                                  uint8_t *tag_out, int32_t *status, uint8_t *body, uint64_t n,
                                  hipStream_t s);
@@ -124,10 +148,7 @@ struct CopyPiece {
 constexpr uint64_t COPY_PIECE_BYTES = 1ull << 20;  // requests are cut into pieces of at most this size
 hipError_t launch_copy_many(const CopyPiece *pieces, uint32_t n, hipStream_t s);
 
-// Streaming: continue (or start) one chain for cnt bytes from/to its checkpoint in *slot.
-hipError_t launch_resume(const lz_key &key, const lz_params &prm, int decrypt, ChainSlot *slot, uint64_t block,
-                         const uint8_t *in, uint8_t *out, uint32_t cnt, int fresh, int complete,
-                         unsigned long long *tag_acc, hipStream_t s);
+// Streaming: fold the pending partial block into the tag, then write or check the tag.
 hipError_t launch_stream_finish(const ChainSlot *slot, int pending, int empty, const lz_key &key,
                                 unsigned long long *tag_acc, int decrypt, uint8_t *tag, int32_t *status,
                                 hipStream_t s);

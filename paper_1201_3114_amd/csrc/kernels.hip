@@ -325,10 +325,31 @@ struct PlainArgs {
     uint64_t n, nb;
     uint64_t block_base;  // index of the first block (0 for a whole message)
     unsigned long long *tag_acc;
+    StreamExtra x;        // read only by the stream instance (X = true)
 };
 
-template <int M, int I>
+__device__ __forceinline__ void load_slot(Chains<1> &c, const ChainSlot &s, const double (&ap)[3],
+                                          const uint8_t (&k)[3], uint32_t dec) {
+    c.x[0] = s.r[0]; c.y[0] = s.r[1]; c.z[0] = s.r[2];
+    c.a0[0] = s.al[0]; c.a1[0] = s.al[1]; c.a2[0] = s.al[2];
+    c.mu0[0] = s.mu[0]; c.mu1[0] = s.mu[1]; c.mu2[0] = s.mu[2];
+    c.om0[0] = s.om[0]; c.om1[0] = s.om[1]; c.om2[0] = s.om[2];
+    c.ap0[0] = ap[0]; c.ap1[0] = ap[1]; c.ap2[0] = ap[2];
+    c.k0[0] = k[0]; c.k1[0] = k[1]; c.k2[0] = k[2];
+    c.dec[0] = dec;
+}
+
+__device__ __forceinline__ void save_slot(ChainSlot &s, const Chains<1> &c) {
+    s.r[0] = c.x[0]; s.r[1] = c.y[0]; s.r[2] = c.z[0];
+    s.al[0] = c.a0[0]; s.al[1] = c.a1[0]; s.al[2] = c.a2[0];
+    s.mu[0] = (uint8_t)c.mu0[0]; s.mu[1] = (uint8_t)c.mu1[0]; s.mu[2] = (uint8_t)c.mu2[0];
+    s.om[0] = (uint8_t)c.om0[0]; s.om[1] = (uint8_t)c.om1[0]; s.om[2] = (uint8_t)c.om2[0];
+}
+
+// X: the stream instance (M = 1), whose lanes nb and nb + 1 may carry a.x's head and tail.
+template <int M, int I, bool X>
 __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
+    static_assert(!X || M == 1, "the stream instance runs one chain per lane");
     extern __shared__ char lds[];
     const int lane = threadIdx.x % WAVE;
     const int wid = threadIdx.x / WAVE;
@@ -345,6 +366,10 @@ __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
     double r0[3] = {a.r0[0], a.r0[1], a.r0[2]}, ap[3] = {a.ap[0], a.ap[1], a.ap[2]};
     uint8_t mu[3] = {a.mu[0], a.mu[1], a.mu[2]}, om[3] = {a.om[0], a.om[1], a.om[2]},
             k[3] = {a.k[0], a.k[1], a.k[2]};
+    // stream instance: 1 = this lane is the head chain, 2 = the tail chain
+    const uint32_t n_head = X && a.x.head_slot ? 1u : 0u;
+    const uint64_t g0 = base + lane;
+    const uint32_t role = !X || g0 < a.nb ? 0u : (g0 == a.nb && n_head ? 1u : (g0 == a.nb + n_head && a.x.tail_slot ? 2u : 0u));
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const uint64_t g = base + (uint64_t)m * WAVE + lane;
@@ -356,7 +381,27 @@ __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
         init_chain<M>(c, m, r0, ap, mu, om, k, a.block_base + (valid[m] ? g : 0), a.decrypt);
         d0[m] = d1[m] = d2[m] = 0;
     }
+    if constexpr (X) {
+        if (role == 1) {
+            load_slot(c, *a.x.head_slot, ap, k, a.decrypt);
+            valid[0] = a.x.head_complete != 0;
+            cnt[0] = a.x.head_cnt;
+            in[0] = a.x.head_in;
+            out[0] = a.x.head_out;
+        } else if (role == 2) {
+            init_chain<1>(c, 0, r0, ap, mu, om, k, a.x.tail_block, a.decrypt);
+            cnt[0] = a.x.tail_cnt;
+            in[0] = a.x.tail_in;
+            out[0] = a.x.tail_out;
+        }
+    }
     wave_run<M, I>(c, w, (int)a.tile, in, out, cnt, a.dt, a.n_it, lane, [&](int m) __attribute__((always_inline)) {
+        if constexpr (X) {
+            if (role == 2 || (role == 1 && !a.x.head_complete)) {
+                save_slot(role == 2 ? *a.x.tail_slot : *a.x.head_slot, c);
+                return;
+            }
+        }
         d0[m] = digest_word(c.x[m]);
         d1[m] = digest_word(c.y[m]);
         d2[m] = digest_word(c.z[m]);
@@ -368,7 +413,7 @@ __global__ __launch_bounds__(256) void plain_kernel(PlainArgs a) {
     t0 = wave_xor_u64(t0);
     t1 = wave_xor_u64(t1);
     t2 = wave_xor_u64(t2);
-    if (lane == 0 && base < a.nb) {
+    if (lane == 0 && base < a.nb + (X ? 2 : 0)) {
         atomicXor(&a.tag_acc[0], t0);
         atomicXor(&a.tag_acc[1], t1);
         atomicXor(&a.tag_acc[2], t2);
@@ -606,65 +651,7 @@ __global__ __launch_bounds__(256) void tick_kernel(TickArgs a) {
     }
 }
 
-// ---- streaming: one resumable chain ------------------------------------------------------
-
-struct ResumeArgs {
-    double ap[3], r0[3];
-    uint8_t mu[3], om[3], k[3];
-    uint32_t decrypt;
-    double dt;
-    uint32_t n_it, block_len, tile;
-    ChainSlot *slot;
-    uint64_t block;     // block index of the chain
-    const uint8_t *in;
-    uint8_t *out;
-    uint32_t cnt;       // bytes to process now
-    uint32_t fresh;     // 1: start from the block's initial condition, else from *slot
-    uint32_t complete;  // 1: the block ends after these bytes: XOR its digest into tag_acc
-    unsigned long long *tag_acc;
-};
-
-// One wave; lane 0 carries the chain, the other lanes idle (cnt 0, no memory).
-template <int I>
-__global__ __launch_bounds__(64) void resume_kernel(ResumeArgs a) {
-    extern __shared__ char lds[];
-    const int lane = threadIdx.x % WAVE;
-    const WaveLds w = wave_lds<1>(lds, a.tile);
-    Chains<1> c;
-    const double ap[3] = {a.ap[0], a.ap[1], a.ap[2]};
-    const uint8_t mu0[3] = {a.mu[0], a.mu[1], a.mu[2]}, om0[3] = {a.om[0], a.om[1], a.om[2]},
-                  k[3] = {a.k[0], a.k[1], a.k[2]};
-    const bool mine = lane == 0;
-    if (a.fresh || !mine) {
-        const double r0[3] = {a.r0[0], a.r0[1], a.r0[2]};
-        init_chain<1>(c, 0, r0, ap, mu0, om0, k, a.block, a.decrypt);
-    } else {
-        const ChainSlot &s = *a.slot;
-        c.x[0] = s.r[0]; c.y[0] = s.r[1]; c.z[0] = s.r[2];
-        c.a0[0] = s.al[0]; c.a1[0] = s.al[1]; c.a2[0] = s.al[2];
-        c.mu0[0] = s.mu[0]; c.mu1[0] = s.mu[1]; c.mu2[0] = s.mu[2];
-        c.om0[0] = s.om[0]; c.om1[0] = s.om[1]; c.om2[0] = s.om[2];
-        c.ap0[0] = ap[0]; c.ap1[0] = ap[1]; c.ap2[0] = ap[2];
-        c.k0[0] = k[0]; c.k1[0] = k[1]; c.k2[0] = k[2];
-        c.dec[0] = a.decrypt;
-    }
-    const uint8_t *const in[1] = {mine ? a.in : nullptr};
-    uint8_t *const out[1] = {mine ? a.out : nullptr};
-    const uint32_t cnt[1] = {mine ? a.cnt : 0u};
-    wave_run<1, I>(c, w, a.tile, in, out, cnt, a.dt, a.n_it, lane, [&](int) __attribute__((always_inline)) {
-        if (!mine) return;
-        ChainSlot &s = *a.slot;
-        s.r[0] = c.x[0]; s.r[1] = c.y[0]; s.r[2] = c.z[0];
-        s.al[0] = c.a0[0]; s.al[1] = c.a1[0]; s.al[2] = c.a2[0];
-        s.mu[0] = (uint8_t)c.mu0[0]; s.mu[1] = (uint8_t)c.mu1[0]; s.mu[2] = (uint8_t)c.mu2[0];
-        s.om[0] = (uint8_t)c.om0[0]; s.om[1] = (uint8_t)c.om1[0]; s.om[2] = (uint8_t)c.om2[0];
-        if (a.complete) {
-            atomicXor(&a.tag_acc[0], digest_word(c.x[0]));
-            atomicXor(&a.tag_acc[1], digest_word(c.y[0]));
-            atomicXor(&a.tag_acc[2], digest_word(c.z[0]));
-        }
-    });
-}
+// ---- streaming ----------------------------------------------------------------------------
 
 // End of a stream: fold in the pending partial block (or, for an empty message, block 0's
 // initial state), then write the tag (encrypt) or compare it (decrypt).
@@ -756,10 +743,11 @@ hipError_t launch_fill_u64(unsigned long long *p, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_plain(const KernelShape &sh, const lz_key &key, const lz_params &prm, int decrypt,
-                        const uint8_t *in, uint8_t *out, uint64_t n, unsigned long long *tag_acc, hipStream_t s,
-                        uint64_t block_base) {
-    PlainArgs a;
+namespace {
+
+PlainArgs plain_args(const KernelShape &sh, const lz_key &key, const lz_params &prm, int decrypt, const uint8_t *in,
+                     uint8_t *out, uint64_t n, uint64_t nb, unsigned long long *tag_acc, uint64_t block_base) {
+    PlainArgs a{};
     for (int j = 0; j < 3; ++j) {
         a.ap[j] = key.a_prime[j];
         a.r0[j] = key.r0[j];
@@ -775,16 +763,43 @@ hipError_t launch_plain(const KernelShape &sh, const lz_key &key, const lz_param
     a.in = in;
     a.out = out;
     a.n = n;
-    a.nb = n == 0 ? 1 : (n + prm.block_len - 1) / prm.block_len;
+    a.nb = nb;
     a.block_base = block_base;
     a.tag_acc = tag_acc;
+    return a;
+}
+
+}  // namespace
+
+hipError_t launch_plain(const KernelShape &sh, const lz_key &key, const lz_params &prm, int decrypt,
+                        const uint8_t *in, uint8_t *out, uint64_t n, unsigned long long *tag_acc, hipStream_t s,
+                        uint64_t block_base) {
+    const uint64_t nb = n == 0 ? 1 : (n + prm.block_len - 1) / prm.block_len;
+    const PlainArgs a = plain_args(sh, key, prm, decrypt, in, out, n, nb, tag_acc, block_base);
     const uint64_t per_wg = (uint64_t)sh.wg * sh.m;
     const uint64_t grid = (a.nb + per_wg - 1) / per_wg;
     const size_t lds = lds_bytes(sh);
     return dispatch(sh.m, prm.integrator, [&](auto mc, auto ic) {
         constexpr int M = decltype(mc)::value;
         constexpr int I = decltype(ic)::value;
-        hipLaunchKernelGGL((plain_kernel<M, I>), dim3((unsigned)grid), dim3(sh.wg), lds, s, a);
+        hipLaunchKernelGGL((plain_kernel<M, I, false>), dim3((unsigned)grid), dim3(sh.wg), lds, s, a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_stream_step(const KernelShape &shape, const lz_key &key, const lz_params &prm, int decrypt,
+                              const uint8_t *in, uint8_t *out, uint64_t full, uint64_t block_base,
+                              const StreamExtra &x, unsigned long long *tag_acc, hipStream_t s) {
+    const KernelShape sh{1, shape.wg, shape.tile, shape.wps};
+    PlainArgs a = plain_args(sh, key, prm, decrypt, in, out, full * prm.block_len, full, tag_acc, block_base);
+    a.x = x;
+    const uint64_t lanes = full + (x.head_slot ? 1 : 0) + (x.tail_slot ? 1 : 0);
+    if (lanes == 0) return hipSuccess;
+    const uint64_t grid = (lanes + sh.wg - 1) / sh.wg;
+    const size_t lds = lds_bytes(sh);
+    return dispatch_i<1>(prm.integrator, [&](auto, auto ic) {
+        constexpr int I = decltype(ic)::value;
+        hipLaunchKernelGGL((plain_kernel<1, I, true>), dim3((unsigned)grid), dim3(sh.wg), lds, s, a);
         return hipGetLastError();
     });
 }
@@ -844,38 +859,6 @@ hipError_t launch_tick(const KernelShape &sh, const lz_params &prm, const TickDe
         constexpr int M = decltype(mc)::value;
         constexpr int I = decltype(ic)::value;
         hipLaunchKernelGGL((tick_kernel<M, I>), dim3((unsigned)grid), dim3(sh.wg), lds, s, a);
-        return hipGetLastError();
-    });
-}
-
-hipError_t launch_resume(const lz_key &key, const lz_params &prm, int decrypt, ChainSlot *slot, uint64_t block,
-                         const uint8_t *in, uint8_t *out, uint32_t cnt, int fresh, int complete,
-                         unsigned long long *tag_acc, hipStream_t s) {
-    ResumeArgs a;
-    for (int j = 0; j < 3; ++j) {
-        a.ap[j] = key.a_prime[j];
-        a.r0[j] = key.r0[j];
-        a.mu[j] = key.mu[j];
-        a.om[j] = key.omega[j];
-        a.k[j] = key.k[j];
-    }
-    a.decrypt = (uint32_t)decrypt;
-    a.dt = prm.dt;
-    a.n_it = prm.n_it;
-    a.block_len = prm.block_len;
-    a.tile = 64;
-    a.slot = slot;
-    a.block = block;
-    a.in = in;
-    a.out = out;
-    a.cnt = cnt;
-    a.fresh = (uint32_t)fresh;
-    a.complete = (uint32_t)complete;
-    a.tag_acc = tag_acc;
-    const size_t lds = wave_lds_bytes(1, 64);
-    return dispatch(1, prm.integrator, [&](auto, auto ic) {
-        constexpr int I = decltype(ic)::value;
-        hipLaunchKernelGGL((resume_kernel<I>), dim3(1), dim3(WAVE), lds, s, a);
         return hipGetLastError();
     });
 }

@@ -4,12 +4,11 @@
 // Each chunk is cut at block boundaries of the parallel version (Section 5):
 // the pending partial block continues from its device-resident checkpoint
 // (r, alpha, mu, Omega), the full blocks run as one plain launch at the right
-// block index, and the remainder starts the next partial block.  The two
-// partial blocks (one chain each, as slow as a whole block) run on internal
-// streams beside the full blocks: they are independent of the full blocks and
-// of each other, since the new partial block keeps its checkpoint in a second
-// slot.  The caller's stream waits for all three before the update's work
-// counts as done.
+// block index, and the remainder starts the next partial block.  All three run
+// in one launch on the caller's stream, the two partial blocks (one chain each,
+// as slow as a whole block) as the lanes after the full blocks: they are
+// independent of the full blocks and of each other, since the new partial block
+// keeps its checkpoint in a second slot.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -34,8 +33,6 @@ struct lz_stream {
     hipEvent_t ev;
     hipStream_t last;
     bool has_last;
-    hipStream_t aux[2];   // the head (continues slot[cur]) and the tail (starts slot[cur ^ 1]) of an update
-    hipEvent_t ev_in, ev_aux[2];
 };
 
 namespace {
@@ -44,16 +41,9 @@ void stream_free(lz_stream *st) {
     if (!st) return;
     hipSetDevice(st->ctx->device);
     if (st->has_last) hipEventSynchronize(st->ev);
-    for (hipStream_t a : st->aux)
-        if (a) hipStreamSynchronize(a);
     if (st->dmem) hipFree(st->dmem);
     if (st->h_status) hipHostFree(st->h_status);
     if (st->ev) hipEventDestroy(st->ev);
-    if (st->ev_in) hipEventDestroy(st->ev_in);
-    for (int i = 0; i < 2; ++i) {
-        if (st->ev_aux[i]) hipEventDestroy(st->ev_aux[i]);
-        if (st->aux[i]) hipStreamDestroy(st->aux[i]);
-    }
     delete st;
 }
 
@@ -89,11 +79,6 @@ extern "C" int lz_stream_open(lz_ctx *c, int decrypt, const uint8_t *pw, size_t 
     if (e == hipSuccess) e = hipMemset(st->dmem, 0, bytes);
     if (e == hipSuccess) e = hipHostMalloc(&st->h_status, sizeof(int32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_in, hipEventDisableTiming);
-    for (int i = 0; i < 2; ++i) {
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_aux[i], hipEventDisableTiming);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&st->aux[i], hipStreamNonBlocking);
-    }
     if (e != hipSuccess) {
         int rc = hip_fail(e, "stream allocation");
         stream_free(st);
@@ -125,29 +110,25 @@ extern "C" int lz_stream_update(lz_stream *st, const uint8_t *d_in, size_t n, ui
     const uint64_t full = (n - h) / B;                          // body: whole blocks
     const uint64_t rem = n - h - full * B;                      // tail: starts the next partial block
     const uint64_t pos0 = st->pos;
-    if (h > 0 || rem > 0) LZ_HIP(hipEventRecord(st->ev_in, s));
-    if (h > 0) {
-        LZ_HIP(hipStreamWaitEvent(st->aux[0], st->ev_in, 0));
-        LZ_HIP(launch_resume(st->key, c->prm, st->decrypt, st->slot[st->cur], pos0 / B, d_in, d_out, (uint32_t)h,
-                             0, r + h == B, st->tag, st->aux[0]));
-        LZ_HIP(hipEventRecord(st->ev_aux[0], st->aux[0]));
+    StreamExtra x{};
+    if (h > 0) {  // continues slot[cur]
+        x.head_slot = st->slot[st->cur];
+        x.head_in = d_in;
+        x.head_out = d_out;
+        x.head_cnt = (uint32_t)h;
+        x.head_complete = r + h == B;
     }
-    if (full > 0)
-        LZ_HIP(launch_plain(c->shape, st->key, c->prm, st->decrypt, d_in + h, d_out + h, full * B, st->tag, s,
-                            (pos0 + h) / B));
-    if (rem > 0) {
-        // a new chain in the other slot, independent of the head's
+    if (rem > 0) {  // a new chain in the other slot, independent of the head's
         const uint64_t o = h + full * B;
-        LZ_HIP(hipStreamWaitEvent(st->aux[1], st->ev_in, 0));
-        LZ_HIP(launch_resume(st->key, c->prm, st->decrypt, st->slot[st->cur ^ 1], (pos0 + o) / B, d_in + o,
-                             d_out + o, (uint32_t)rem, 1, 0, st->tag, st->aux[1]));
-        LZ_HIP(hipEventRecord(st->ev_aux[1], st->aux[1]));
+        x.tail_slot = st->slot[st->cur ^ 1];
+        x.tail_in = d_in + o;
+        x.tail_out = d_out + o;
+        x.tail_cnt = (uint32_t)rem;
+        x.tail_block = (pos0 + o) / B;
     }
-    if (h > 0) LZ_HIP(hipStreamWaitEvent(s, st->ev_aux[0], 0));
-    if (rem > 0) {
-        LZ_HIP(hipStreamWaitEvent(s, st->ev_aux[1], 0));
-        st->cur ^= 1;
-    }
+    LZ_HIP(launch_stream_step(c->shape, st->key, c->prm, st->decrypt, d_in + h, d_out + h, full, (pos0 + h) / B, x,
+                              st->tag, s));
+    if (rem > 0) st->cur ^= 1;
     st->pos = pos0 + n;
     return stream_record(st, s);
 }

@@ -68,6 +68,38 @@ def test_stream_equals_one_shot(lz, n):
     assert np.array_equal(host(back), P)
 
 
+@pytest.mark.parametrize("full", [63, 64, 255, 256, 257])
+def test_stream_partial_chains_at_workgroup_edges(lz, full):
+    """An update's head and tail chains run as the lanes after its whole blocks: with 63..257 whole
+    blocks they fall at the end of a wave or workgroup or spill into the next one.  Each case has a
+    head that completes its block, whole blocks, and a tail; then a head that does not complete its
+    block (a chunk shorter than the block's rest); decrypting back is checked too."""
+    import torch
+
+    rng = np.random.default_rng(70 + full)
+    ctx = lz.Context(0, lz.params(n_it=25))
+    B = 256
+    n = 100 + (B - 100) + full * B + 50 + 30 + 10
+    P = rng.integers(0, 256, n, dtype=np.uint8)
+    Pd = to_dev(P)
+    one = host(ctx.encrypt(Pd, b"edge pw"))
+    assert np.array_equal(one, oracle.encrypt(b"edge pw", P, n_it=25))
+    a = 100
+    b = a + (B - 100) + full * B + 50
+    cuts = [(0, a), (a, b), (b, b + 30), (b + 30, n)]  # tail; head + whole + tail; short head; rest
+    say("full", full, "cuts", cuts)
+    got = host(_stream_encrypt(lz, ctx, Pd, b"edge pw", cuts))
+    assert np.array_equal(got, one), full
+    C = to_dev(one)
+    st = lz.Stream(ctx, True, b"edge pw")
+    back = torch.empty(n, dtype=torch.uint8, device="cuda")
+    for x, y in cuts:
+        st.update(C[x:y], out=back[x:y])
+    st.finish(tag=C[n:n + 24].clone())
+    st.close()
+    assert np.array_equal(host(back), P)
+
+
 def test_stream_tamper_and_wrong_tag(lz):
     import torch
 
