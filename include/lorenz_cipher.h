@@ -350,6 +350,26 @@ int lz_autocorrelation(lz_ctx *ctx, const uint8_t *d_data, size_t n, uint32_t ma
 int lz_power_spectrum_2d(lz_ctx *ctx, const uint8_t *d_img, uint32_t h, uint32_t w, double *d_power, void *stream);
 int lz_autocorrelation_2d(lz_ctx *ctx, const uint8_t *d_img, uint32_t h, uint32_t w, double *d_acf, void *stream);
 
+/* ---- the method's scalar pieces, one by one --------------------------------
+ * Each evaluates one piece of the per-byte work element by element over
+ * device arrays, with the same device code as the cipher kernels, so that it
+ * can be checked on its own.  Asynchronous on stream; LZ_E_INVAL for a NULL
+ * context or (when n > 0) a NULL array.
+ *
+ * lz_unit_r: d_out[i] = R(d_alpha[i], d_omega[i]) (Section 3.2, Eq. R_nu):
+ * byte Omega (0 = least significant) of floor(alpha 10^13) as a two's
+ * complement integer.  Omega values are taken mod 4 (the method uses 0..3). */
+int lz_unit_r(lz_ctx *ctx, const double *d_alpha, const uint8_t *d_omega, size_t n, uint8_t *d_out, void *stream);
+
+/* lz_unit_theta: d_out[i] = d_p[i] / 10^(3 + d_omega3[i]), the correctly
+ * rounded quotient (Section 3.2, Step 2); omega3 taken mod 4. */
+int lz_unit_theta(lz_ctx *ctx, const uint8_t *d_p, const uint8_t *d_omega3, size_t n, double *d_out, void *stream);
+
+/* lz_unit_lorenz: each state (d_r[3i], d_r[3i+1], d_r[3i+2]) = (x, y, z) is
+ * advanced in place by `steps` steps of the context's integrator with its dt
+ * (Section 3.1; the loop of Step 2).  n <= 2^31. */
+int lz_unit_lorenz(lz_ctx *ctx, double *d_r, size_t n, uint32_t steps, void *stream);
+
 /* CLOCK_MONOTONIC now, in ns (the clock of arrival_ns and done_ns). */
 uint64_t lz_now_ns(void);
 

@@ -64,6 +64,14 @@ def lib():
         L.orc_R.restype = ctypes.c_int
         L.orc_theta.argtypes = [ctypes.c_int, ctypes.c_int]
         L.orc_theta.restype = ctypes.c_double
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_R_many.argtypes = [dp, u8p, ctypes.c_size_t, u8p]
+        L.orc_R_many.restype = None
+        L.orc_theta_many.argtypes = [u8p, u8p, ctypes.c_size_t, dp]
+        L.orc_theta_many.restype = None
+        L.orc_lorenz_many.argtypes = [dp, ctypes.c_size_t, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                      ctypes.c_int]
+        L.orc_lorenz_many.restype = None
         L.orc_encrypt.argtypes = [u8p, ctypes.c_size_t, ctypes.POINTER(Params), u8p, ctypes.c_size_t, u8p,
                                   ctypes.c_int]
         L.orc_encrypt.restype = ctypes.c_int
@@ -123,6 +131,36 @@ def R(alpha: float, omega: int) -> int:
 
 def theta(p: int, omega3: int) -> float:
     return lib().orc_theta(p, omega3)
+
+
+def R_many(alpha, omega) -> np.ndarray:
+    """R(alpha_i, omega_i) over arrays (loops over orc_R)."""
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    om = np.ascontiguousarray(omega, dtype=np.uint8)
+    out = np.empty(len(al), dtype=np.uint8)
+    lib().orc_R_many(al.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                     om.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), len(al),
+                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return out
+
+
+def theta_many(p, omega3) -> np.ndarray:
+    """Theta(p_i, omega3_i) over arrays (loops over orc_theta)."""
+    pa = np.ascontiguousarray(p, dtype=np.uint8)
+    om = np.ascontiguousarray(omega3, dtype=np.uint8)
+    out = np.empty(len(pa), dtype=np.float64)
+    lib().orc_theta_many(pa.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                         om.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), len(pa),
+                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def lorenz_many(r, dt, steps, integrator="euler", nthreads: int = 8) -> np.ndarray:
+    """Each row (x, y, z) of r advanced by `steps` integrator steps (loops over orc_lorenz_integrator)."""
+    arr = np.array(r, dtype=np.float64, order="C").reshape(-1, 3)
+    code = INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
+    lib().orc_lorenz_many(arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(arr), dt, steps, code, nthreads)
+    return arr
 
 
 def encrypt(pw: bytes, P, nthreads: int = 1, **kw) -> np.ndarray:

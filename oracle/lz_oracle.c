@@ -303,6 +303,48 @@ double orc_theta(int p, int omega3) {
     return (double)p / pow10[3 + omega3];
 }
 
+/* ---- the same functions over arrays, for checking other implementations ----
+ * Plain loops over orc_R, orc_theta and orc_lorenz_integrator (the Lorenz
+ * states split over nthreads threads); no arithmetic of their own.          */
+
+void orc_R_many(const double *alpha, const uint8_t *omega, size_t n, uint8_t *out) {
+    for (size_t i = 0; i < n; i++) out[i] = (uint8_t)orc_R(alpha[i], omega[i]);
+}
+
+void orc_theta_many(const uint8_t *p, const uint8_t *omega3, size_t n, double *out) {
+    for (size_t i = 0; i < n; i++) out[i] = orc_theta(p[i], omega3[i]);
+}
+
+typedef struct {
+    double *r;      /* 3 doubles per state */
+    size_t n;
+    double dt;
+    uint64_t steps;
+    uint32_t integrator;
+    int part, parts;
+} lorenz_job_t;
+
+static void *lorenz_worker(void *arg) {
+    const lorenz_job_t *J = (const lorenz_job_t *)arg;
+    for (size_t i = (size_t)J->part; i < J->n; i += (size_t)J->parts)
+        orc_lorenz_integrator(J->r + 3 * i, J->dt, J->steps, J->integrator);
+    return NULL;
+}
+
+void orc_lorenz_many(double *r, size_t n, double dt, uint64_t steps, uint32_t integrator, int nthreads) {
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 64) nthreads = 64;
+    pthread_t th[64];
+    lorenz_job_t J[64];
+    for (int t = 0; t < nthreads; t++) {
+        lorenz_job_t j = {r, n, dt, steps, integrator, t, nthreads};
+        J[t] = j;
+    }
+    for (int t = 1; t < nthreads; t++) pthread_create(&th[t], NULL, lorenz_worker, &J[t]);
+    lorenz_worker(&J[0]);
+    for (int t = 1; t < nthreads; t++) pthread_join(th[t], NULL);
+}
+
 /* N(v) of the integrity digest */
 static uint64_t digest_word(double v) { return (uint64_t)(int64_t)floor(v * SCALE_NU); }
 

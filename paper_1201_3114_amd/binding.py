@@ -85,6 +85,9 @@ SIGNATURES = {
     "lz_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
     "lz_server_destroy": (ctypes.c_int, [vp]),
     "lz_now_ns": (ctypes.c_uint64, []),
+    "lz_unit_r": (ctypes.c_int, [vp, vp, vp, ctypes.c_size_t, vp, vp]),
+    "lz_unit_theta": (ctypes.c_int, [vp, vp, vp, ctypes.c_size_t, vp, vp]),
+    "lz_unit_lorenz": (ctypes.c_int, [vp, vp, ctypes.c_size_t, ctypes.c_uint32, vp]),
     "lz_histogram": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp, vp]),
     "lz_lag_sums": (ctypes.c_int, [vp, vp, ctypes.c_size_t, ctypes.c_uint32, vp, vp]),
     "lz_entropy": (ctypes.c_int, [vp, vp, vp, vp]),

@@ -367,5 +367,41 @@ def autocorrelation_2d(ctx: Context, img: torch.Tensor, stream=None) -> torch.Te
     return out
 
 
+def _dev_typed(t: torch.Tensor, dtype):
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def unit_r(ctx: Context, alpha: torch.Tensor, omega: torch.Tensor, stream=None) -> torch.Tensor:
+    """R(alpha_i, omega_i) (Section 3.2) for float64 alpha and uint8 omega (0..3), as the kernels compute it."""
+    if alpha.numel() != omega.numel():
+        raise ValueError("alpha and omega differ in length")
+    out = torch.empty(alpha.numel(), dtype=torch.uint8, device=alpha.device)
+    check(B.lib.lz_unit_r(ctx.handle, _dev_typed(alpha, torch.float64), _dev_typed(omega, torch.uint8),
+                          alpha.numel(), _dev_typed(out, torch.uint8), _stream(stream, ctx.device)))
+    return out
+
+
+def unit_theta(ctx: Context, p: torch.Tensor, omega3: torch.Tensor, stream=None) -> torch.Tensor:
+    """Theta = p_i / 10^(3 + omega3_i) (Step 2) for uint8 p and omega3, as the kernels compute it."""
+    if p.numel() != omega3.numel():
+        raise ValueError("p and omega3 differ in length")
+    out = torch.empty(p.numel(), dtype=torch.float64, device=p.device)
+    check(B.lib.lz_unit_theta(ctx.handle, _dev_typed(p, torch.uint8), _dev_typed(omega3, torch.uint8), p.numel(),
+                              _dev_typed(out, torch.float64), _stream(stream, ctx.device)))
+    return out
+
+
+def unit_lorenz(ctx: Context, r: torch.Tensor, steps: int, stream=None) -> torch.Tensor:
+    """Advances each row (x, y, z) of the float64 (n, 3) tensor r in place by `steps` steps of the
+    context's integrator (Section 3.1); returns r."""
+    if r.dim() != 2 or r.shape[1] != 3:
+        raise ValueError("expected an (n, 3) tensor")
+    check(B.lib.lz_unit_lorenz(ctx.handle, _dev_typed(r, torch.float64), r.shape[0], int(steps),
+                               _stream(stream, ctx.device)))
+    return r
+
+
 def now_ns() -> int:
     return int(B.lib.lz_now_ns())

@@ -148,6 +148,11 @@ struct CopyPiece {
 constexpr uint64_t COPY_PIECE_BYTES = 1ull << 20;  // requests are cut into pieces of at most this size
 hipError_t launch_copy_many(const CopyPiece *pieces, uint32_t n, hipStream_t s);
 
+// The method's scalar pieces over device arrays (R, Theta, F^steps), for checking.
+hipError_t launch_unit_r(const double *alpha, const uint8_t *om, size_t n, uint8_t *out, hipStream_t s);
+hipError_t launch_unit_theta(const uint8_t *p, const uint8_t *o3, size_t n, double *out, hipStream_t s);
+hipError_t launch_unit_lorenz(const lz_params &prm, double *r, size_t n, uint32_t steps, hipStream_t s);
+
 // Streaming: fold the pending partial block into the tag, then write or check the tag.
 hipError_t launch_stream_finish(const ChainSlot *slot, int pending, int empty, const lz_key &key,
                                 unsigned long long *tag_acc, int decrypt, uint8_t *tag, int32_t *status,

@@ -40,6 +40,12 @@ __device__ __forceinline__ uint32_t r_nu(double alpha, uint32_t om) {
     return ((uint32_t)lo >> (8u * om)) & 0xFFu;
 }
 
+// Step 2: Theta = P / 10^(3 + Omega_3), one correctly rounded division.
+__device__ __forceinline__ double theta_of(uint32_t p, uint32_t o3) {
+    const double p10 = o3 == 0 ? 1e3 : (o3 == 1 ? 1e4 : (o3 == 2 ? 1e5 : 1e6));
+    return (double)p / p10;
+}
+
 // Integrity word N(v) = floor(v 10^13) as a two's complement 64-bit pattern.
 __device__ __forceinline__ unsigned long long digest_word(double v) {
     const double N = floor(v * SCALE_NU);
@@ -168,9 +174,7 @@ __device__ __forceinline__ void crypt_byte(Chains<M> &c, const uint32_t (&bin)[M
             bout[m] = (bin[m] + ks) & 0xFFu;
         }
         // Step 2: Theta = P_i / 10^(3 + Omega_3) added to the coordinate mu_3
-        const uint32_t o3 = c.om2[m];
-        const double p10 = o3 == 0 ? 1e3 : (o3 == 1 ? 1e4 : (o3 == 2 ? 1e5 : 1e6));
-        const double th = (double)p[m] / p10;
+        const double th = theta_of(p[m], c.om2[m]);
         // r[mu_3] += Theta, written as value selects: a select of the coordinate's address
         // would force the chain state out of registers
         const uint32_t s = c.mu2[m];
@@ -677,6 +681,30 @@ __global__ void stream_finish_kernel(const ChainSlot *slot, int pending, int emp
     *status = ok ? LZ_OK : LZ_E_INTEGRITY;
 }
 
+// ---- the method's scalar pieces over arrays, for checking them one by one -----------
+
+__global__ void unit_r_kernel(const double *alpha, const uint8_t *om, size_t n, uint8_t *out) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = (uint8_t)r_nu(alpha[i], om[i] & 3u);
+}
+
+__global__ void unit_theta_kernel(const uint8_t *p, const uint8_t *o3, size_t n, double *out) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = theta_of(p[i], o3[i] & 3u);
+}
+
+// F^steps of Step 2 (the cipher kernels' loop) on each state (x, y, z).
+template <int I>
+__global__ void unit_lorenz_kernel(double *r, size_t n, double dt, uint32_t steps) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x[1] = {r[3 * i]}, y[1] = {r[3 * i + 1]}, z[1] = {r[3 * i + 2]};
+    lorenz_steps<1, I>(x, y, z, dt, steps);
+    r[3 * i] = x[0];
+    r[3 * i + 1] = y[0];
+    r[3 * i + 2] = z[0];
+}
+
 // Zeroes the body of each listed request (failed decryptions), one workgroup each.
 __global__ void req_zero_kernel(const ReqDesc *reqs, const uint32_t *ids, uint32_t n) {
     if (blockIdx.x >= n) return;
@@ -859,6 +887,27 @@ hipError_t launch_tick(const KernelShape &sh, const lz_params &prm, const TickDe
         constexpr int M = decltype(mc)::value;
         constexpr int I = decltype(ic)::value;
         hipLaunchKernelGGL((tick_kernel<M, I>), dim3((unsigned)grid), dim3(sh.wg), lds, s, a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_unit_r(const double *alpha, const uint8_t *om, size_t n, uint8_t *out, hipStream_t s) {
+    const size_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+    hipLaunchKernelGGL(unit_r_kernel, dim3((unsigned)(blocks ? blocks : 1)), dim3(256), 0, s, alpha, om, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_unit_theta(const uint8_t *p, const uint8_t *o3, size_t n, double *out, hipStream_t s) {
+    const size_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+    hipLaunchKernelGGL(unit_theta_kernel, dim3((unsigned)(blocks ? blocks : 1)), dim3(256), 0, s, p, o3, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_unit_lorenz(const lz_params &prm, double *r, size_t n, uint32_t steps, hipStream_t s) {
+    const size_t blocks = (n + 255) / 256;
+    return dispatch_i<1>(prm.integrator, [&](auto, auto ic) {
+        constexpr int I = decltype(ic)::value;
+        hipLaunchKernelGGL((unit_lorenz_kernel<I>), dim3((unsigned)blocks), dim3(256), 0, s, r, n, prm.dt, steps);
         return hipGetLastError();
     });
 }
