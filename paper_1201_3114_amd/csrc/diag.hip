@@ -19,15 +19,15 @@ namespace {
 constexpr int DIAG_WG = 256;
 
 // Byte histogram.  The workgroup's LDS counters hold HIST_COPIES copies of each
-// bin, interleaved (bin * HIST_COPIES + copy, copy = lane mod HIST_COPIES): lanes
-// that see the same byte value hit different addresses in different banks, so
-// skewed input (text, constant runs) does not serialise the LDS atomics, and
-// random input spreads over the banks more evenly.  Each lane reads 16 bytes
+// bin, interleaved (bin * HIST_COPIES + copy, copy = lane mod HIST_COPIES): the
+// 32 lanes of a half-wave always add into 32 different banks, whatever their
+// bytes, so skewed input (text, constant runs) does not serialise the LDS
+// atomics and random input does not collide in banks.  Each lane reads 16 bytes
 // per load with HIST_U loads in flight; the copies are summed at the end and
 // merged into the 256 global counters with one atomic per occupied bin.
 // Block 0 also counts the unaligned head and the tail that does not fill 16 bytes.
 constexpr int HIST_U = 4;
-constexpr int HIST_COPIES = 16;
+constexpr int HIST_COPIES = 32;
 
 __device__ __forceinline__ void count_word(uint32_t *h, uint32_t w) {
     atomicAdd(&h[(w & 0xFF) * HIST_COPIES], 1u);

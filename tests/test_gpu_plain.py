@@ -160,6 +160,32 @@ def test_invalid_arguments(lz):
         ctx.set_launch(lz.LaunchShape(3, 256, 64, 4))
     with pytest.raises(lz.LorenzError):
         lz.Context(0, lz.params(dt=0.03))
+    for bad in (dict(dt=0.0), dict(dt=-0.01), dict(n_it=0), dict(block_len=0), dict(k=(5, 4, 4)), dict(k=(4, 2, 4))):
+        with pytest.raises(lz.LorenzError):
+            lz.Context(0, lz.params(**bad))
+
+
+def test_truncated_and_extended_ciphertexts(lz):
+    """The tag is the last 24 bytes: a ciphertext cut short or with bytes appended is rejected (its tag
+    and body no longer match) and the output zeroed; fewer than 24 bytes is an argument error."""
+    import torch
+
+    rng = np.random.default_rng(15)
+    P = rng.integers(0, 256, 700, dtype=np.uint8)
+    ctx = _ctx(lz, n_it=40)
+    C = ctx.encrypt(to_dev(P), b"cut")
+    variants = {"cut 1": C[:-1], "cut 24": C[:-24], "cut 300": C[:-300],
+                "extended 1": torch.cat([C, C[:1]]), "extended 256": torch.cat([C, C[:256]])}
+    for name, bad in variants.items():
+        say(name)
+        st = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+        out = ctx.decrypt(bad.contiguous(), b"cut", status=st)
+        torch.cuda.synchronize()
+        assert int(st.item()) == -2, name
+        assert not host(out).any(), name
+        assert not oracle.decrypt(b"cut", host(bad), n_it=40)[1], name
+    with pytest.raises(ValueError):
+        ctx.decrypt(C[:23].contiguous(), b"cut")
 
 
 def test_plain_64m_sampled(lz):
