@@ -98,6 +98,24 @@ def test_password_lengths_and_bytes(lz):
         assert np.array_equal(host(C), oracle.encrypt(pw, P, n_it=20)), npw
 
 
+def test_degenerate_and_example_passwords(lz):
+    """Passwords whose packed integers are 0 (all-zero bytes: a' = 0, so r0 = lambda on every coordinate) or
+    maximal (all 0xFF), one repeated byte, and the paper's example passwords 123456 and 123457 of Section 4."""
+    rng = np.random.default_rng(16)
+    ctx = _ctx(lz, n_it=40)
+    P = rng.integers(0, 256, 1500, dtype=np.uint8)
+    pws = [b"\0" * n for n in (1, 2, 3, 6, 64)] + [b"\xff" * n for n in (1, 3, 64)]
+    pws += [b"a" * 33, b"123456", b"123457"]
+    outs = {}
+    for pw in pws:
+        C = host(ctx.encrypt(to_dev(P), pw))
+        assert np.array_equal(C, oracle.encrypt(pw, P, n_it=40)), pw
+        outs[pw] = C
+    # the two example passwords differ in one character and give unrelated ciphertexts
+    a, b = outs[b"123456"][:1500], outs[b"123457"][:1500]
+    assert np.mean(a == b) < 0.02
+
+
 def test_tamper_detected_and_zeroed(lz):
     """A changed ciphertext byte (body or tag) fails the tag; the plaintext comes back zeroed."""
     import torch
