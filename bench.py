@@ -338,7 +338,8 @@ def bench_diag(lz, torch, reps=5):
     """Section 4 analyses on ciphertext-like (uniform random) bytes: histogram of 1 GiB (HBM-bound),
     the autocorrelation up to lag 256 of 16 MiB, the 2-D power spectrum and autocorrelation matrix
     of a 1024 x 1024 byte image (two / four FFT passes), and the power spectrum of a 1000 x 1000
-    image (two direct DFT passes on the binary64 matrix cores)."""
+    image (mixed-radix FFT passes) and of a 1009 x 1009 image (two direct DFT passes on the binary64
+    matrix cores)."""
     from paper_1201_3114_amd import workloads
 
     ctx = lz.Context(0)
@@ -388,12 +389,17 @@ def bench_diag(lz, torch, reps=5):
     res["autocorrelation_2d_1024x1024"] = dict(ms=ms, route="fft")
     a = lz.autocorrelation_2d(ctx, img)
     res["max_abs_offzero_acf2"] = float(a.flatten()[1:].abs().max())
-    # other sides: the direct DFT, a dense complex matrix product on the binary64 matrix cores
+    # sides with no prime factor above 5: mixed-radix FFT passes (1000 = 2^3 5^3)
     N = 1000
+    img_m = x[:N * N].view(N, N)
+    ms = timed(lambda: lz.power_spectrum_2d(ctx, img_m))
+    res["power_spectrum_1000x1000"] = dict(ms=ms, route="mixed-radix fft", hbm_GBps=41 * N * N / ms / 1e6)
+    # other sides (1009 is prime): the direct DFT, a dense complex matrix product on the binary64 matrix cores
+    N = 1009
     img_d = x[:N * N].view(N, N)
     flops_pass = N * N * N * 8  # complex multiply-add = 4 FMA = 8 flops, N x N outputs of N terms
     ms = timed(lambda: lz.power_spectrum_2d(ctx, img_d))
-    res["power_spectrum_1000x1000"] = dict(ms=ms, route="direct", TFLOPs=2 * flops_pass / ms / 1e9,
+    res["power_spectrum_1009x1009"] = dict(ms=ms, route="direct", TFLOPs=2 * flops_pass / ms / 1e9,
                                            frac_of_fp64_matrix_peak=2 * flops_pass / ms * 1e3 / FP64_FMA_COUNTED_PEAK)
     ctx.close()
     return res

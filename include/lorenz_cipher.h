@@ -342,9 +342,9 @@ int lz_autocorrelation(lz_ctx *ctx, const uint8_t *d_data, size_t n, uint32_t ma
  * Xc = X - mean; all NaN for a constant matrix.  It is computed as the inverse
  * 2-D DFT of the mean-removed power spectrum (Wiener-Khinchin).
  *
- * Each 1-D transform along a side runs as an FFT when the side is a power of
- * two up to 4096 and as a direct DFT otherwise; the routes agree within
- * rounding.  Both use the context's diagnostics workspace (about 32 h w bytes,
+ * Each 1-D transform along a side runs as an FFT when the side is at most
+ * 4096 with no prime factor above 5 and as a direct DFT otherwise; the
+ * routes agree within rounding.  Both use the context's diagnostics workspace (about 32 h w bytes,
  * grown on demand: LZ_E_NOMEM if it does not fit) and run asynchronously on
  * stream. */
 int lz_power_spectrum_2d(lz_ctx *ctx, const uint8_t *d_img, uint32_t h, uint32_t w, double *d_power, void *stream);

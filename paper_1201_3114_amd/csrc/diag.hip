@@ -711,6 +711,124 @@ __global__ __launch_bounds__(DIAG_WG) void fft_pass_kernel(const In *src, uint32
     }
 }
 
+// ---- the same pass by mixed-radix FFT, for lengths 2^a 3^b 5^c --------------------------
+//
+// Lengths N <= FFT_MAX whose only prime factors are 2, 3 and 5 (and that are not
+// powers of two) run as Stockham stages of radix 5, 3, 4 and 2 in turn (the radix
+// of each stage in FftPlan).  A radix-R stage with stride s, n = N / s, reads
+// x[q + s (j + l n/R)] for l < R, takes their R-point DFT (radix 2 and 4 in
+// their exact +-1, +-i form, radix 3 and 5 with W_R^p = W_N^{p N/R} from the
+// table), multiplies output k by W_n^{jk} = W_N^{j s k} and writes it to
+// x[q + s (R j + k)].  The N-entry table (the twiddle kernel's, sign applied) is
+// copied into LDS beside the data; the rest is as in fft_pass_kernel.
+struct FftPlan {
+    uint32_t nst;
+    uint8_t rad[16];
+};
+
+template <int R>
+__device__ __forceinline__ void mixed_stage(double2 *fbuf, const double2 *ftw, uint32_t N, uint32_t cols,
+                                            uint32_t s, double sign) {
+    constexpr int BPT = (int)((FFT_MAX / R + DIAG_WG - 1) / DIAG_WG);
+    const uint32_t nr = N / R, m = nr / s, nb = cols * nr, step = N / R;
+    double2 a[BPT][R];
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const uint32_t u = threadIdx.x + i * DIAG_WG;
+        if (u < nb) {
+            const uint32_t cl = u / nr, t = u - cl * nr, j = t / s, q = t - j * s;
+            const double2 *x = fbuf + (size_t)cl * N;
+#pragma unroll
+            for (int l = 0; l < R; ++l) a[i][l] = x[q + s * (j + l * m)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const uint32_t u = threadIdx.x + i * DIAG_WG;
+        if (u < nb) {
+            const uint32_t cl = u / nr, t = u - cl * nr, j = t / s, q = t - j * s;
+            double2 y[R];
+            if constexpr (R == 2) {
+                y[0] = cadd(a[i][0], a[i][1]);
+                y[1] = csub(a[i][0], a[i][1]);
+            } else if constexpr (R == 4) {
+                const double2 t0 = cadd(a[i][0], a[i][2]), t1 = csub(a[i][0], a[i][2]);
+                const double2 t2 = cadd(a[i][1], a[i][3]), t3 = csub(a[i][1], a[i][3]);
+                const double2 rt3 = make_double2(-sign * t3.y, sign * t3.x);  // W_4 t3, W_4 = sign i
+                y[0] = cadd(t0, t2);
+                y[1] = cadd(t1, rt3);
+                y[2] = csub(t0, t2);
+                y[3] = csub(t1, rt3);
+            } else {
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    double2 acc = a[i][0];
+#pragma unroll
+                    for (int l = 1; l < R; ++l)
+                        acc = k == 0 ? cadd(acc, a[i][l]) : cadd(acc, cmul(a[i][l], ftw[((l * k) % R) * step]));
+                    y[k] = acc;
+                }
+            }
+            double2 *x = fbuf + (size_t)cl * N;
+            x[q + s * (R * j)] = y[0];
+#pragma unroll
+            for (int k = 1; k < R; ++k) x[q + s * (R * j + k)] = cmul(y[k], ftw[j * s * k]);
+        }
+    }
+    __syncthreads();
+}
+
+template <typename In, int E>
+__global__ __launch_bounds__(DIAG_WG) void fft_mixed_pass_kernel(const In *src, uint32_t N, uint32_t M, uint32_t C,
+                                                                  FftPlan plan, const double2 *tw, double sign,
+                                                                  PassOut dst) {
+    extern __shared__ double2 fbuf[];  // C columns of N values, then the N twiddles
+    double2 *ftw = fbuf + (size_t)C * N;
+    uint32_t g = blockIdx.x;
+    if (gridDim.x % 8 == 0) g = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    const uint32_t c0 = g * C;
+    const uint32_t cols = M - c0 < C ? M - c0 : C;
+    const uint32_t total = cols * N;
+    {
+        In v[FFT_EPT];
+#pragma unroll
+        for (int i = 0; i < FFT_EPT; ++i) {
+            const uint32_t e = threadIdx.x + i * DIAG_WG;
+            if (e < total) {
+                const uint32_t k = e / cols, cl = e - k * cols;
+                v[i] = src[(size_t)k * M + c0 + cl];
+            }
+        }
+        for (uint32_t j = threadIdx.x; j < N; j += DIAG_WG) {
+            const double2 w = tw[j];
+            ftw[j] = make_double2(w.x, sign * w.y);
+        }
+#pragma unroll
+        for (int i = 0; i < FFT_EPT; ++i) {
+            const uint32_t e = threadIdx.x + i * DIAG_WG;
+            if (e < total) {
+                const uint32_t k = e / cols, cl = e - k * cols;
+                fbuf[cl * N + k] = dft_value(v[i]);
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t s = 1;
+    for (uint32_t st = 0; st < plan.nst; ++st) {
+        const uint32_t R = plan.rad[st];
+        if (R == 5) mixed_stage<5>(fbuf, ftw, N, cols, s, sign);
+        else if (R == 3) mixed_stage<3>(fbuf, ftw, N, cols, s, sign);
+        else if (R == 4) mixed_stage<4>(fbuf, ftw, N, cols, s, sign);
+        else mixed_stage<2>(fbuf, ftw, N, cols, s, sign);
+        s *= R;
+    }
+    for (uint32_t e = threadIdx.x; e < total; e += DIAG_WG) {
+        const double2 v = fbuf[e];
+        pass_store<E>(dst, (size_t)c0 * N + e, v.x, v.y);
+    }
+}
+
 // n S2 - S1^2 from the histogram (exact: n <= 2^24 keeps both products below 2^64),
 // the zero-lag sum of the mean-removed image scaled by n.
 __global__ __launch_bounds__(DIAG_WG) void acf2_den_kernel(const unsigned long long *hist, uint64_t n,
@@ -842,12 +960,44 @@ size_t dft2_bytes(uint32_t h, uint32_t w, size_t extra) {
 
 bool fft_ok(const lz_ctx *c, uint32_t N);
 
-// The twiddle tables of the lengths the direct pass transforms (the FFT makes its own).
+// The twiddle tables of the lengths that are not powers of two (the power-of-two FFT makes its own).
 int launch_twiddles(const lz_ctx *c, const Dft2 &d, uint32_t h, uint32_t w, hipStream_t s) {
     if (!fft_ok(c, h)) hipLaunchKernelGGL(twiddle_kernel, dim3((h + 255) / 256), dim3(256), 0, s, d.tw_h, h);
     if (!fft_ok(c, w)) hipLaunchKernelGGL(twiddle_kernel, dim3((w + 255) / 256), dim3(256), 0, s, d.tw_w, w);
     LZ_HIP(hipGetLastError());
     return LZ_OK;
+}
+
+// The radices of N for the mixed-radix pass (5s, 3s, 4s, then a 2), or nst = 0 if N has
+// another prime factor.
+FftPlan mixed_plan(uint32_t N) {
+    FftPlan p{};
+    uint32_t n = N;
+    for (uint32_t r : {5u, 3u}) {
+        while (n % r == 0 && p.nst < 16) {
+            p.rad[p.nst++] = (uint8_t)r;
+            n /= r;
+        }
+    }
+    while (n % 4 == 0 && p.nst < 16) {
+        p.rad[p.nst++] = 4;
+        n /= 4;
+    }
+    if (n == 2 && p.nst < 16) {
+        p.rad[p.nst++] = 2;
+        n = 1;
+    }
+    if (n != 1) p.nst = 0;
+    return p;
+}
+
+size_t mixed_lds(uint32_t N) {
+    const uint32_t per_wg = N > FFT_WG_ELEMS ? N : FFT_WG_ELEMS;
+    return ((size_t)(per_wg / N) * N + N) * sizeof(double2);
+}
+
+bool mixed_ok(const lz_ctx *c, uint32_t N) {
+    return N <= FFT_MAX && N > 1 && mixed_plan(N).nst > 0 && mixed_lds(N) <= (size_t)c->dev.lds_per_wg_max;
 }
 
 bool fft_ok(const lz_ctx *c, uint32_t N) {
@@ -857,8 +1007,9 @@ bool fft_ok(const lz_ctx *c, uint32_t N) {
 }
 
 // Output (M x N) = transpose of (DFT_N along the rows of src (N x M)), stored by epilogue E:
-// by FFT when N is a power of two up to FFT_MAX, otherwise directly on the matrix cores with
-// 64 x 64 outputs per workgroup (tw: the N-entry table, needed only then).
+// by FFT when N is a power of two up to FFT_MAX, by mixed-radix FFT when N <= FFT_MAX has no
+// prime factor above 5, otherwise directly on the matrix cores with 64 x 64 outputs per
+// workgroup (tw: the N-entry table, needed by the last two).
 template <typename In, int E>
 int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, const double2 *tw, double sign,
                     PassOut out, hipStream_t s) {
@@ -874,6 +1025,16 @@ int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, cons
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL((fft_pass_kernel<In, E>), dim3(groups), dim3(DIAG_WG), lds, s, src, N, M, logN, C, sign,
                            out);
+    } else if (mixed_ok(c, N)) {
+        const uint32_t per_wg = N > FFT_WG_ELEMS ? N : FFT_WG_ELEMS;
+        const uint32_t C = per_wg / N;
+        const uint32_t groups = (M + C - 1) / C;
+        const size_t lds = mixed_lds(N);
+        if (lds > 65536)
+            LZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_mixed_pass_kernel<In, E>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL((fft_mixed_pass_kernel<In, E>), dim3(groups), dim3(DIAG_WG), lds, s, src, N, M, C,
+                           mixed_plan(N), tw, sign, out);
     } else {
         const dim3 grid((N + DFT_T - 1) / DFT_T, (M + DFT_T - 1) / DFT_T);
         hipLaunchKernelGGL((dft_pass_kernel<In, E>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, out);
