@@ -100,6 +100,25 @@ def test_stream_partial_chains_at_workgroup_edges(lz, full):
     assert np.array_equal(host(back), P)
 
 
+@pytest.mark.parametrize("shape", [(1, 64, 16, 4), (1, 128, 32, 2), (2, 256, 64, 4), (4, 64, 128, 8)])
+def test_stream_under_launch_shapes(lz, shape):
+    """An update runs one chain per lane with the context's workgroup size and tile whatever its chains-per-lane
+    setting; the result equals the one-shot ciphertext made under the same shape."""
+    rng = np.random.default_rng(80 + shape[1] + shape[0])
+    ctx = lz.Context(0, lz.params(n_it=20))
+    ctx.set_launch(lz.LaunchShape(*shape))
+    n = 256 * 300 + 77
+    P = rng.integers(0, 256, n, dtype=np.uint8)
+    Pd = to_dev(P)
+    one = host(ctx.encrypt(Pd, b"shape pw"))
+    assert np.array_equal(one, oracle.encrypt(b"shape pw", P, n_it=20, nthreads=8))
+    cuts = [(0, 5), (5, 5 + 256 * 129 + 3), (5 + 256 * 129 + 3, n)]
+    got = host(_stream_encrypt(lz, ctx, Pd, b"shape pw", cuts))
+    assert np.array_equal(got, one), shape
+    cuts = _chunks(rng, n)
+    assert np.array_equal(host(_stream_encrypt(lz, ctx, Pd, b"shape pw", cuts)), one), shape
+
+
 def test_stream_tamper_and_wrong_tag(lz):
     import torch
 
