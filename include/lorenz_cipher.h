@@ -49,7 +49,8 @@ enum {
     LZ_E_INTEGRITY = -2, /* decryption: the recomputed tag differs from the stored one    */
     LZ_E_NOMEM = -3,     /* device or host allocation failed, or request exceeds a budget */
     LZ_E_HIP = -4,       /* a HIP runtime call failed (message in lz_last_error)          */
-    LZ_E_AGAIN = -5      /* server: nothing to return yet                                 */
+    LZ_E_AGAIN = -5,     /* server: nothing to return yet                                 */
+    LZ_E_CANCELLED = -6  /* server: the request was cancelled before it completed         */
 };
 
 /* Integrator of the dynamical system F (Section 3.1 uses forward Euler and
@@ -250,7 +251,8 @@ typedef struct {
 
 typedef struct {
     uint64_t id;         /* caller's request id                                   */
-    int32_t status;      /* LZ_OK, LZ_E_INTEGRITY (decrypt) or LZ_E_NOMEM (too big) */
+    int32_t status;      /* LZ_OK, LZ_E_INTEGRITY (decrypt), LZ_E_NOMEM (too big) or
+                            LZ_E_CANCELLED                                            */
     int32_t reserved;
     uint64_t arrival_ns; /* monotonic clock, as submitted                         */
     uint64_t admit_ns;   /* when the request got slots and memory                 */
@@ -283,6 +285,16 @@ int lz_server_submit_many(lz_server *srv, size_t count, const uint64_t *ids, con
                           const uint8_t *pw, const uint64_t *pw_off, const uint32_t *pw_len,
                           const void *const *src, const uint64_t *n, void *const *dst,
                           const uint64_t *arrival_ns);
+
+/* Asks the server to drop request id (the first queued or running request
+ * with that id).  Asynchronous, like submission: the request's completion
+ * reports LZ_E_CANCELLED, and its dst is not written; a request still waiting
+ * or not yet arrived completes at once, a running one once the tick running
+ * its chains has finished (its chain slots and memory are then free for
+ * others; the other requests' outputs do not change).  A request that
+ * completes before the cancellation takes effect reports its own status; an
+ * id that matches no request is ignored.  Thread-safe. */
+int lz_server_cancel(lz_server *srv, uint64_t id);
 
 /* Copies up to max completed requests into out, returns how many (>= 0), or
  * a negative error.  timeout_ms < 0 waits until at least one is available. */

@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblorenz_cipher.so")
 
-LZ_OK, LZ_E_INVAL, LZ_E_INTEGRITY, LZ_E_NOMEM, LZ_E_HIP, LZ_E_AGAIN = 0, -1, -2, -3, -4, -5
+LZ_OK, LZ_E_INVAL, LZ_E_INTEGRITY, LZ_E_NOMEM, LZ_E_HIP, LZ_E_AGAIN, LZ_E_CANCELLED = 0, -1, -2, -3, -4, -5, -6
 TAG_BYTES = 24
 INTEGRATORS = {"euler": 0, "euler_fma": 1, "rk4": 2}
 
@@ -81,6 +81,7 @@ SIGNATURES = {
                                              ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32),
                                              ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(vp),
                                              ctypes.POINTER(ctypes.c_uint64)]),
+    "lz_server_cancel": (ctypes.c_int, [vp, ctypes.c_uint64]),
     "lz_server_poll": (ctypes.c_int, [vp, ctypes.POINTER(Completion), ctypes.c_int, ctypes.c_int]),
     "lz_server_stats_get": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
     "lz_server_destroy": (ctypes.c_int, [vp]),

@@ -282,6 +282,10 @@ class Server:
                                           src_a.ctypes.data_as(PV), n_a.ctypes.data_as(P64), dst_a.ctypes.data_as(PV),
                                           arr_a.ctypes.data_as(P64)))
 
+    def cancel(self, rid: int):
+        """Drops request rid; its completion reports LZ_E_CANCELLED (-6) unless it finished first."""
+        check(B.lib.lz_server_cancel(self._h, rid))
+
     def poll(self, max_n: int = 4096, timeout_ms: int = 0):
         arr = (B.Completion * max_n)()
         k = check(B.lib.lz_server_poll(self._h, arr, max_n, timeout_ms))

@@ -17,7 +17,6 @@
 #include <map>
 #include <mutex>
 #include <new>
-#include <queue>
 #include <thread>
 #include <vector>
 
@@ -95,6 +94,8 @@ struct Request {
     uint64_t arena_off = 0, arena_bytes = 0;
     uint32_t ticks_full = 0, ticks_tail = 0;  // ticks until full / tail chains finish
     uint32_t ticks_run = 0;
+    bool cancelled = false;   // lz_server_cancel: no further ticks; released once no tick in flight lists it
+    uint64_t last_tick = 0;   // sequence number of the last tick that listed its chains
 };
 
 struct ArrivalLater {
@@ -154,6 +155,7 @@ struct TickSlot {
     hipEvent_t ev_start = nullptr, ev_end = nullptr;
     bool in_flight = false;
     uint64_t bytes = 0;
+    uint64_t seq = 0;  // tick sequence number (1, 2, ...)
 };
 
 struct lz_server {
@@ -182,10 +184,12 @@ struct lz_server {
     std::vector<Request *> active;
     std::deque<Request *> waiting;  // arrived, not admitted (FIFO)
     uint64_t hbm_fixed = 0;
+    uint64_t tick_seq = 0, done_seq = 0;  // last tick queued, last tick completed (ticks complete in order)
     // shared with submitters / pollers
     std::mutex mu;
     std::condition_variable cv_submit, cv_done;
-    std::priority_queue<Request *, std::vector<Request *>, ArrivalLater> pending;
+    std::vector<Request *> pending;  // not yet arrived: a heap on (arrival, submission order)
+    std::vector<uint64_t> cancels;   // ids from lz_server_cancel, applied by the server thread
     std::deque<lz_completion> done;
     uint64_t seq = 0;
     bool stop = false;
@@ -259,6 +263,8 @@ void admit(lz_server *s, std::vector<Request *> &admitted) {
 uint8_t *req_in(lz_server *s, const Request *r) { return s->arena_mem + r->arena_off; }
 uint8_t *req_out(lz_server *s, const Request *r) { return req_in(s, r) + (in_len(*r) + 255) / 256 * 256; }
 
+void release(lz_server *s, Request *r);
+
 // Reads a finished tick's completions, zeroes failed decryptions, copies the
 // outputs out, frees the requests' slots and memory and reports them.
 int complete_tick(lz_server *s, TickSlot &t) {
@@ -269,6 +275,7 @@ int complete_tick(lz_server *s, TickSlot &t) {
     s->stats.ticks++;
     s->stats.chain_bytes += t.bytes;
     t.in_flight = false;
+    s->done_seq = t.seq;
     LZ_HIP(hipMemcpyAsync(t.h_done, t.d_done, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, cs));
     LZ_HIP(hipStreamSynchronize(cs));
     const uint32_t nd = t.h_done[0];
@@ -311,18 +318,67 @@ int complete_tick(lz_server *s, TickSlot &t) {
     LZ_HIP(hipStreamSynchronize(cs));
     const uint64_t now = lz_now_ns();
     for (auto &f : fin) {
-        Request *r = f.first;
-        s->arena.release(r->arena_off, r->arena_bytes);
-        s->free_slots.insert(s->free_slots.end(), r->slots.begin(), r->slots.end());
-        s->free_reqs.push_back(r->req_slot);
-        s->by_slot[r->req_slot] = nullptr;
-        Request *last = s->active.back();  // swap-remove
-        s->active[r->active_idx] = last;
-        last->active_idx = r->active_idx;
-        s->active.pop_back();
-        finish(s, r, f.second, now);
+        release(s, f.first);
+        finish(s, f.first, f.second, now);
     }
     return LZ_OK;
+}
+
+// Frees an admitted request's chain slots, request slot and memory and takes it off
+// the active list (its chains are in no tick still in flight).
+void release(lz_server *s, Request *r) {
+    s->arena.release(r->arena_off, r->arena_bytes);
+    s->free_slots.insert(s->free_slots.end(), r->slots.begin(), r->slots.end());
+    s->free_reqs.push_back(r->req_slot);
+    s->by_slot[r->req_slot] = nullptr;
+    Request *last = s->active.back();  // swap-remove
+    s->active[r->active_idx] = last;
+    last->active_idx = r->active_idx;
+    s->active.pop_back();
+}
+
+// Applies the cancellations queued by lz_server_cancel: a request not yet admitted
+// completes as cancelled now (if it has not arrived yet, when it does); an active
+// one gets no further ticks and is released by release_cancelled.  Ids that match
+// nothing (already completed, or unknown) are dropped.
+void apply_cancels(lz_server *s) {
+    std::vector<uint64_t> ids;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        ids.swap(s->cancels);
+    }
+    for (uint64_t id : ids) {
+        auto w = std::find_if(s->waiting.begin(), s->waiting.end(), [&](Request *r) { return r->id == id; });
+        if (w != s->waiting.end()) {
+            Request *r = *w;
+            s->waiting.erase(w);
+            finish(s, r, LZ_E_CANCELLED, lz_now_ns());
+            continue;
+        }
+        auto a = std::find_if(s->active.begin(), s->active.end(),
+                              [&](Request *r) { return r->id == id && !r->cancelled; });
+        if (a != s->active.end()) {
+            (*a)->cancelled = true;
+            continue;
+        }
+        std::lock_guard<std::mutex> g(s->mu);
+        for (Request *r : s->pending)
+            if (r->id == id && !r->cancelled) {
+                r->cancelled = true;
+                break;
+            }
+    }
+}
+
+// Completes the cancelled active requests whose last tick has completed.
+void release_cancelled(lz_server *s) {
+    const uint64_t now = lz_now_ns();
+    for (size_t i = s->active.size(); i-- > 0;) {
+        Request *r = s->active[i];
+        if (!r->cancelled || r->last_tick > s->done_seq) continue;
+        release(s, r);
+        finish(s, r, LZ_E_CANCELLED, now);
+    }
 }
 
 // One scheduling step: admit into the free tick slot, queue its tick, then
@@ -335,6 +391,7 @@ int server_step(lz_server *s) {
     TickSlot &t = s->ts[s->cur];
     if (t.in_flight)
         if (int rc = complete_tick(s, t)) return rc;
+    apply_cancels(s);
     std::vector<Request *> admitted;
     admit(s, admitted);
     if (!admitted.empty()) {
@@ -383,7 +440,9 @@ int server_step(lz_server *s) {
     const uint32_t T = s->cfg.tick_bytes, B = s->ctx->prm.block_len;
     uint32_t n_list = 0;
     uint64_t tick_bytes = 0;
+    const uint64_t seq = s->tick_seq + 1;
     for (Request *r : s->active) {
+        if (r->cancelled) continue;
         const uint32_t tr = r->ticks_run;
         if (tr < r->ticks_full) {
             std::memcpy(t.h_list + n_list, r->slots.data(), (r->nb - 1) * sizeof(uint32_t));
@@ -396,7 +455,10 @@ int server_step(lz_server *s) {
             const uint64_t done = (uint64_t)tr * T;
             tick_bytes += tail > done ? std::min<uint64_t>(T, tail - done) : 0;
         }
-        if (tr < r->ticks_full || tr < r->ticks_tail) r->ticks_run++;
+        if (tr < r->ticks_full || tr < r->ticks_tail) {
+            r->ticks_run++;
+            r->last_tick = seq;
+        }
     }
     if (n_list) {
         LZ_HIP(hipMemcpyAsync(t.d_list, t.h_list, n_list * sizeof(uint32_t), hipMemcpyHostToDevice, pre));
@@ -415,12 +477,15 @@ int server_step(lz_server *s) {
         LZ_HIP(launch_tick(s->shape, s->ctx->prm, td, st));
         LZ_HIP(hipEventRecord(t.ev_end, st));
         t.bytes = tick_bytes;
+        t.seq = seq;
+        s->tick_seq = seq;
         t.in_flight = true;
     }
     s->cur ^= 1;
     TickSlot &prev = s->ts[s->cur];
     if (prev.in_flight)
         if (int rc = complete_tick(s, prev)) return rc;
+    release_cancelled(s);
     if (!n_list && !prev.in_flight && !s->ts[s->cur ^ 1].in_flight && !s->active.empty())
         return fail(LZ_E_HIP, "server: active requests without pending work");
     return LZ_OK;
@@ -430,24 +495,34 @@ bool busy(lz_server *s) { return !s->waiting.empty() || !s->active.empty() || s-
 
 void server_loop(lz_server *s) {
     hipSetDevice(s->ctx->device);
+    std::vector<Request *> arrived_cancelled;
     for (;;) {
         {
             std::unique_lock<std::mutex> g(s->mu);
             for (;;) {
                 const uint64_t now = lz_now_ns();
-                while (!s->pending.empty() && s->pending.top()->arrival_ns <= now) {
-                    s->waiting.push_back(s->pending.top());
-                    s->pending.pop();
+                while (!s->pending.empty() && s->pending.front()->arrival_ns <= now) {
+                    std::pop_heap(s->pending.begin(), s->pending.end(), ArrivalLater());
+                    Request *r = s->pending.back();
+                    s->pending.pop_back();
+                    if (r->cancelled) arrived_cancelled.push_back(r);
+                    else s->waiting.push_back(r);
                 }
-                if (busy(s)) break;
+                if (busy(s) || !arrived_cancelled.empty() || !s->cancels.empty()) break;
                 if (s->stop && s->pending.empty()) return;
                 if (s->pending.empty()) {
                     s->cv_submit.wait(g);
                 } else {
-                    const uint64_t dt = s->pending.top()->arrival_ns - now;
+                    const uint64_t dt = s->pending.front()->arrival_ns - now;
                     s->cv_submit.wait_for(g, std::chrono::nanoseconds(dt));
                 }
             }
+        }
+        for (Request *r : arrived_cancelled) finish(s, r, LZ_E_CANCELLED, lz_now_ns());
+        arrived_cancelled.clear();
+        if (!busy(s)) {  // only cancellations to apply
+            apply_cancels(s);
+            continue;
         }
         if (int rc = server_step(s)) {
             std::lock_guard<std::mutex> g(s->mu);
@@ -492,10 +567,7 @@ void server_free(lz_server *s) {
     if (s->in_stream) hipStreamDestroy(s->in_stream);
     if (s->copy_stream) hipStreamDestroy(s->copy_stream);
     if (s->ev_in) hipEventDestroy(s->ev_in);
-    while (!s->pending.empty()) {
-        delete s->pending.top();
-        s->pending.pop();
-    }
+    for (Request *r : s->pending) delete r;
     for (Request *r : s->waiting) delete r;
     for (Request *r : s->active) delete r;
     delete s;
@@ -607,7 +679,8 @@ extern "C" int lz_server_submit(lz_server *s, uint64_t id, int decrypt, const ui
             return fail(s->error ? s->error : LZ_E_INVAL, "server stopped");
         }
         r->seq = s->seq++;
-        s->pending.push(r);
+        s->pending.push_back(r);
+        std::push_heap(s->pending.begin(), s->pending.end(), ArrivalLater());
     }
     s->cv_submit.notify_all();
     return LZ_OK;
@@ -662,8 +735,20 @@ extern "C" int lz_server_submit_many(lz_server *s, size_t count, const uint64_t 
         }
         for (Request *r : batch) {
             r->seq = s->seq++;
-            s->pending.push(r);
+            s->pending.push_back(r);
+            std::push_heap(s->pending.begin(), s->pending.end(), ArrivalLater());
         }
+    }
+    s->cv_submit.notify_all();
+    return LZ_OK;
+}
+
+extern "C" int lz_server_cancel(lz_server *s, uint64_t id) {
+    if (!s) return fail(LZ_E_INVAL, "NULL argument");
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->stop) return fail(s->error ? s->error : LZ_E_INVAL, "server stopped");
+        s->cancels.push_back(id);
     }
     s->cv_submit.notify_all();
     return LZ_OK;

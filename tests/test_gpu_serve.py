@@ -74,6 +74,59 @@ def test_serve_mix_equals_plain(lz):
         assert np.array_equal(host(r["dst"])[:n_out], _expected(ctx, r)), r["id"]
 
 
+def test_serve_cancel(lz):
+    """Cancelled requests (not yet arrived, waiting, running, already finished, and an unknown id): a
+    cancelled request reports LZ_E_CANCELLED and leaves its output untouched unless it finished first;
+    every other request's output equals the plain path; the freed chain slots and memory serve a second
+    wave through a server too small to hold both waves at once."""
+    rng = np.random.default_rng(45)
+    ctx = lz.Context(0, lz.params(n_it=200))
+    reqs = _requests(lz, ctx, rng, 150, 30000, 200)
+    for r in reqs:
+        r["dst"].fill_(0xA5)
+    srv = lz.Server(ctx, hbm_budget=1 << 28, max_chains=4096, tick_bytes=8)
+    t0 = lz.now_ns()
+    for r in reqs:  # the last 30 arrive 40..70 ms later
+        late = r["id"] >= 120
+        srv.submit(r["id"], r["dec"], r["pw"], r["src"].data_ptr(), r["n"], r["dst"].data_ptr(),
+                   t0 + (40_000_000 + 1_000_000 * (r["id"] - 120) if late else 50_000 * r["id"]))
+    cancel_late = {r["id"] for r in reqs if r["id"] >= 120 and r["id"] % 3 == 0}
+    for i in cancel_late:
+        srv.cancel(i)
+    time.sleep(0.01)
+    cancel_mid = {r["id"] for r in reqs if r["id"] < 120 and r["id"] % 5 == 2}
+    for i in sorted(cancel_mid, reverse=True):
+        srv.cancel(i)
+    srv.cancel(99_999)
+    got = _drain(srv, len(reqs))
+    cancelled = cancel_late | cancel_mid
+    n_cancelled = 0
+    for r in reqs:
+        status = got[r["id"]][1]
+        n_out = r["n"] if r["dec"] else r["n"] + 24
+        if r["id"] in cancelled and status == -6:
+            n_cancelled += 1
+            assert (host(r["dst"]) == 0xA5).all(), r["id"]
+            continue
+        assert status == 0, (r["id"], status)
+        assert np.array_equal(host(r["dst"])[:n_out], _expected(ctx, r)), r["id"]
+    say("cancelled", n_cancelled, "of", len(cancelled))
+    for i in cancel_late:  # cancelled before they arrived
+        assert got[i][1] == -6, i
+    # a second wave needs the slots and memory the first one freed
+    wave = _requests(lz, ctx, rng, 60, 30000, 200)
+    for r in wave:
+        srv.submit(1000 + r["id"], r["dec"], r["pw"], r["src"].data_ptr(), r["n"], r["dst"].data_ptr())
+    got2 = _drain(srv, len(wave))
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs) + len(wave)
+    for r in wave:
+        assert got2[1000 + r["id"]][1] == 0
+        n_out = r["n"] if r["dec"] else r["n"] + 24
+        assert np.array_equal(host(r["dst"])[:n_out], _expected(ctx, r)), r["id"]
+
+
 def test_serve_alone_equals_in_mix(lz):
     """The same request gives the same bytes alone on an idle server and inside a mix."""
     import torch
