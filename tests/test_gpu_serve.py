@@ -77,11 +77,13 @@ def test_serve_mix_equals_plain(lz):
 def test_serve_cancel(lz):
     """Cancelled requests (not yet arrived, waiting, running, already finished, and an unknown id): a
     cancelled request reports LZ_E_CANCELLED and leaves its output untouched unless it finished first;
-    every other request's output equals the plain path; the freed chain slots and memory serve a second
-    wave through a server too small to hold both waves at once."""
+    every other request's output equals the plain path; afterwards a request needing all 4096 chain slots
+    is admitted (so no cancelled request kept a slot), then a second wave completes."""
+    import torch
+
     rng = np.random.default_rng(45)
-    ctx = lz.Context(0, lz.params(n_it=200))
-    reqs = _requests(lz, ctx, rng, 150, 30000, 200)
+    ctx = lz.Context(0, lz.params())  # a 256-byte chain is about 20 ms of serial work
+    reqs = _requests(lz, ctx, rng, 150, 30000, 3000)
     for r in reqs:
         r["dst"].fill_(0xA5)
     srv = lz.Server(ctx, hbm_budget=1 << 28, max_chains=4096, tick_bytes=8)
@@ -93,7 +95,7 @@ def test_serve_cancel(lz):
     cancel_late = {r["id"] for r in reqs if r["id"] >= 120 and r["id"] % 3 == 0}
     for i in cancel_late:
         srv.cancel(i)
-    time.sleep(0.01)
+    time.sleep(0.008)  # the first 120 have arrived; most of those admitted are running
     cancel_mid = {r["id"] for r in reqs if r["id"] < 120 and r["id"] % 5 == 2}
     for i in sorted(cancel_mid, reverse=True):
         srv.cancel(i)
@@ -113,14 +115,23 @@ def test_serve_cancel(lz):
     say("cancelled", n_cancelled, "of", len(cancelled))
     for i in cancel_late:  # cancelled before they arrived
         assert got[i][1] == -6, i
-    # a second wave needs the slots and memory the first one freed
-    wave = _requests(lz, ctx, rng, 60, 30000, 200)
+    assert n_cancelled > len(cancel_late)  # some were cancelled while waiting or running
+    # a request that needs every chain slot is admitted only if no cancelled request kept any
+    big = dict(id=500, n=4096 * 256, pw=b"all-slots-password", dec=False)
+    big["P"] = big["src"] = to_dev(rng.integers(0, 256, big["n"], dtype=np.uint8))
+    big["dst"] = torch.zeros(big["n"] + 24, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    srv.submit(500, False, big["pw"], big["src"].data_ptr(), big["n"], big["dst"].data_ptr())
+    assert _drain(srv, 1, 60)[500][1] == 0
+    assert np.array_equal(host(big["dst"]), _expected(ctx, big))
+    # then a second wave
+    wave = _requests(lz, ctx, rng, 60, 30000, 3000)
     for r in wave:
         srv.submit(1000 + r["id"], r["dec"], r["pw"], r["src"].data_ptr(), r["n"], r["dst"].data_ptr())
     got2 = _drain(srv, len(wave))
     st = srv.stats()
     srv.close()
-    assert st["completed"] == len(reqs) + len(wave)
+    assert st["completed"] == len(reqs) + 1 + len(wave)
     for r in wave:
         assert got2[1000 + r["id"]][1] == 0
         n_out = r["n"] if r["dec"] else r["n"] + 24
