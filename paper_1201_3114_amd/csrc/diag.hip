@@ -23,8 +23,10 @@ constexpr int DIAG_WG = 256;
 // 32 lanes of a half-wave always add into 32 different banks, whatever their
 // bytes, so skewed input (text, constant runs) does not serialise the LDS
 // atomics and random input does not collide in banks.  Each lane reads 16 bytes
-// per load with HIST_U loads in flight; the copies are summed at the end and
-// merged into the 256 global counters with one atomic per occupied bin.
+// per load, HIST_U loads per batch, and issues the next batch's loads before
+// counting the current one, so the loads overlap the LDS atomics.  The copies
+// are summed at the end and merged into the 256 global counters with one atomic
+// per occupied bin.
 // Block 0 also counts the unaligned head and the tail that does not fill 16 bytes.
 constexpr int HIST_U = 4;
 constexpr int HIST_COPIES = 32;
@@ -50,10 +52,16 @@ __global__ __launch_bounds__(DIAG_WG) void histogram_kernel(const uint8_t *data,
         for (uint64_t j = head + nv * 16 + threadIdx.x; j < n; j += DIAG_WG) atomicAdd(&hc[data[j] * HIST_COPIES], 1u);
     }
     const uint64_t stride = (uint64_t)gridDim.x * DIAG_WG;
-    for (uint64_t i = (uint64_t)blockIdx.x * DIAG_WG + threadIdx.x; i < nv; i += stride * HIST_U) {
-        uint4 q[HIST_U];
+    uint64_t i = (uint64_t)blockIdx.x * DIAG_WG + threadIdx.x;
+    uint4 q[HIST_U];
 #pragma unroll
-        for (int u = 0; u < HIST_U; ++u) q[u] = i + u * stride < nv ? v[i + u * stride] : make_uint4(0, 0, 0, 0);
+    for (int u = 0; u < HIST_U; ++u) q[u] = i + u * stride < nv ? v[i + u * stride] : make_uint4(0, 0, 0, 0);
+    for (; i < nv; i += stride * HIST_U) {
+        // the next batch's loads are issued before this batch is counted
+        const uint64_t j = i + stride * HIST_U;
+        uint4 next[HIST_U];
+#pragma unroll
+        for (int u = 0; u < HIST_U; ++u) next[u] = j + u * stride < nv ? v[j + u * stride] : make_uint4(0, 0, 0, 0);
 #pragma unroll
         for (int u = 0; u < HIST_U; ++u) {
             if (i + u * stride >= nv) break;
@@ -62,6 +70,8 @@ __global__ __launch_bounds__(DIAG_WG) void histogram_kernel(const uint8_t *data,
             count_word(hc, q[u].z);
             count_word(hc, q[u].w);
         }
+#pragma unroll
+        for (int u = 0; u < HIST_U; ++u) q[u] = next[u];
     }
     __syncthreads();
     unsigned long long c = 0;
