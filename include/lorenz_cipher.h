@@ -317,7 +317,9 @@ int lz_server_destroy(lz_server *srv);
 /* ---- diagnostics of Section 4 (frequency analysis, autocorrelation) -------------
  * lz_histogram: d_hist (device, 256 uint64, overwritten) receives the count of
  * each byte value of d_data (device, n bytes); the Shannon entropy
- * S = -sum p_i log2 p_i follows from it.  Asynchronous on stream. */
+ * S = -sum p_i log2 p_i follows from it.  Uses a 16 KB merge buffer of the
+ * context (calls of one context are ordered across streams, as for the
+ * workspace below).  Asynchronous on stream. */
 int lz_histogram(lz_ctx *ctx, const uint8_t *d_data, size_t n, uint64_t *d_hist, void *stream);
 
 /* lz_lag_sums: d_sums (device, max_lag + 1 uint64, overwritten) receives the

@@ -25,8 +25,11 @@ constexpr int DIAG_WG = 256;
 // atomics and random input does not collide in banks.  Each lane reads 16 bytes
 // per load, HIST_U loads per batch, and issues the next batch's loads before
 // counting the current one, so the loads overlap the LDS atomics.  The copies
-// are summed at the end and merged into the 256 global counters with one atomic
-// per occupied bin.
+// are summed at the end; workgroup b adds its counts to copy b mod HIST_MERGE of
+// the bins in the context's merge buffer (one device atomic per occupied bin:
+// eight tables instead of one spread the atomics of hundreds of workgroups over
+// more memory channels), and a one-workgroup kernel then writes the sum of the
+// copies to the output and clears them for the next call.
 // Block 0 also counts the unaligned head and the tail that does not fill 16 bytes.
 constexpr int HIST_U = 4;
 constexpr int HIST_COPIES = 32;
@@ -39,7 +42,7 @@ __device__ __forceinline__ void count_word(uint32_t *h, uint32_t w) {
 }
 
 __global__ __launch_bounds__(DIAG_WG) void histogram_kernel(const uint8_t *data, uint64_t n,
-                                                             unsigned long long *hist) {
+                                                             unsigned long long *merge) {
     __shared__ uint32_t h[256 * HIST_COPIES];
     for (int i = threadIdx.x; i < 256 * HIST_COPIES; i += DIAG_WG) h[i] = 0;
     __syncthreads();
@@ -76,7 +79,17 @@ __global__ __launch_bounds__(DIAG_WG) void histogram_kernel(const uint8_t *data,
     __syncthreads();
     unsigned long long c = 0;
     for (int k = 0; k < HIST_COPIES; ++k) c += h[threadIdx.x * HIST_COPIES + k];
-    if (c) atomicAdd(&hist[threadIdx.x], c);
+    if (c) atomicAdd(&merge[(blockIdx.x % HIST_MERGE) * 256 + threadIdx.x], c);
+}
+
+// Writes the sum of the merge copies to the output and clears them for the next call.
+__global__ __launch_bounds__(256) void hist_merge_kernel(unsigned long long *merge, unsigned long long *hist) {
+    unsigned long long t = 0;
+    for (int k = 0; k < HIST_MERGE; ++k) {
+        t += merge[k * 256 + threadIdx.x];
+        merge[k * 256 + threadIdx.x] = 0;
+    }
+    hist[threadIdx.x] = t;
 }
 
 // S_k = sum_{i < n-k} x_i x_{i+k} for k = 0..L.  A workgroup takes tiles of
@@ -858,22 +871,33 @@ __global__ __launch_bounds__(DIAG_WG) void acf2_den_kernel(const unsigned long l
 
 using namespace lz;
 
+namespace {
+int diag_begin(lz_ctx *c, hipStream_t s, size_t bytes, char **ws);
+int diag_end(lz_ctx *c, hipStream_t s);
+}  // namespace
+
 extern "C" int lz_histogram(lz_ctx *c, const uint8_t *d_data, size_t n, uint64_t *d_hist, void *stream) {
     if (!c || !d_hist || (!d_data && n)) return fail(LZ_E_INVAL, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
     LZ_HIP(hipSetDevice(c->device));
-    LZ_HIP(launch_fill_u64(reinterpret_cast<unsigned long long *>(d_hist), 256, s));
-    if (n == 0) return LZ_OK;
+    if (n == 0) {
+        LZ_HIP(launch_fill_u64(reinterpret_cast<unsigned long long *>(d_hist), 256, s));
+        return LZ_OK;
+    }
     // about 16 KiB per workgroup at least, at most 2 workgroups per CU; the 32-bit LDS counters
     // stay below 2^32 while each workgroup covers fewer than 2^32 bytes
     uint64_t blocks = (n + 16383) / 16384;
     if (blocks > (uint64_t)c->dev.cus * 2) blocks = (uint64_t)c->dev.cus * 2;
     if (n / blocks >= (1ull << 32) - 1024) blocks = (n >> 31) + 1;
     if (blocks > 0x7FFFFFFFull) return fail(LZ_E_INVAL, "input too long");
+    char *ws;  // the merge buffer is the context's: calls on different streams are ordered
+    if (int rc = diag_begin(c, s, 0, &ws)) return rc;
     hipLaunchKernelGGL(histogram_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n,
+                       c->hist_merge);
+    hipLaunchKernelGGL(hist_merge_kernel, dim3(1), dim3(256), 0, s, c->hist_merge,
                        reinterpret_cast<unsigned long long *>(d_hist));
     LZ_HIP(hipGetLastError());
-    return LZ_OK;
+    return diag_end(c, s);
 }
 
 extern "C" int lz_lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, uint64_t *d_sums,

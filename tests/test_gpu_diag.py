@@ -61,6 +61,26 @@ def test_histogram_skewed_exact(lz, ctx, kind):
     assert np.array_equal(host(lz.histogram(ctx, d[7:])).astype(np.int64), dg.histogram(x[7:]))
 
 
+def test_histogram_calls_in_a_row_on_two_streams(lz, ctx):
+    """Each call leaves the context's merge copies and workgroup counter cleared for the next: calls of one
+    workgroup and of hundreds, queued back to back on two streams, each equal their byte counts."""
+    import torch
+
+    rng = np.random.default_rng(83)
+    sizes = [1, 100, 16384, 16385, 3_000_001, 20_000_000, 0, 5]
+    xs = [rng.integers(0, 256, n, dtype=np.uint8) for n in sizes]
+    ds = [_dev(x) if len(x) else torch.zeros(0, dtype=torch.uint8, device="cuda") for x in xs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for rep in range(3):
+        for i, d in enumerate(ds):
+            outs.append((i, lz.histogram(ctx, d, stream=streams[(i + rep) % 2])))
+    torch.cuda.synchronize()
+    for i, h in outs:
+        assert np.array_equal(host(h).astype(np.int64), dg.histogram(xs[i])), sizes[i]
+
+
 @pytest.mark.parametrize("kind", ["empty", "one", "two", "uniform", "skewed", "all"])
 def test_entropy(lz, ctx, kind):
     rng = np.random.default_rng(81)
