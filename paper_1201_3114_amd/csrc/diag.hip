@@ -25,7 +25,7 @@ constexpr int DIAG_WG = 256;
 // atomics and random input does not collide in banks.  Each lane reads 16 bytes
 // per load, HIST_U loads per batch, and issues the next batch's loads before
 // counting the current one, so the loads overlap the LDS atomics.  The copies
-// are summed at the end; workgroup b adds its counts to copy b mod HIST_MERGE of
+// are summed at the end; workgroup b adds its counts to copy b mod DIAG_MERGE of
 // the bins in the context's merge buffer (one device atomic per occupied bin:
 // eight tables instead of one spread the atomics of hundreds of workgroups over
 // more memory channels), and a one-workgroup kernel then writes the sum of the
@@ -79,13 +79,13 @@ __global__ __launch_bounds__(DIAG_WG) void histogram_kernel(const uint8_t *data,
     __syncthreads();
     unsigned long long c = 0;
     for (int k = 0; k < HIST_COPIES; ++k) c += h[threadIdx.x * HIST_COPIES + k];
-    if (c) atomicAdd(&merge[(blockIdx.x % HIST_MERGE) * 256 + threadIdx.x], c);
+    if (c) atomicAdd(&merge[(blockIdx.x % DIAG_MERGE) * 256 + threadIdx.x], c);
 }
 
 // Writes the sum of the merge copies to the output and clears them for the next call.
 __global__ __launch_bounds__(256) void hist_merge_kernel(unsigned long long *merge, unsigned long long *hist) {
     unsigned long long t = 0;
-    for (int k = 0; k < HIST_MERGE; ++k) {
+    for (int k = 0; k < DIAG_MERGE; ++k) {
         t += merge[k * 256 + threadIdx.x];
         merge[k * 256 + threadIdx.x] = 0;
     }
@@ -196,8 +196,10 @@ __device__ T block_sum(T v, T *red) {
 // bytes, so the kernel works with x - 128 (byte XOR 0x80; 0 past n) and
 //   S_k = S'_k + 256 T - 128 (P_k + Q_k) - 16384 max(n - k, 0),
 // T the byte total, P_k and Q_k the sums of the first and the last min(k, n)
-// bytes: each workgroup adds 256 times its bytes' total into its one atomic per
-// lag, and lagsum_fix_kernel applies the rest.
+// bytes: each workgroup adds its sums plus 256 times its bytes' total, one atomic
+// per lag, into copy b mod DIAG_MERGE of the context's merge buffer (eight tables
+// spread the device atomics of hundreds of workgroups), and lagsum_fix_kernel
+// adds up the copies, clears them and applies the rest.
 //
 // A task is a chunk of MC_ROWS rows, staged in LDS column by column (lt[c][r],
 // row stride a multiple of 16) together with the rows the shifted operands reach
@@ -237,7 +239,7 @@ size_t lagsum_mc_lds_bytes(uint32_t L) {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(DIAG_WG) void lagsum_mc_kernel(const uint8_t *data, uint64_t n, uint32_t L,
-                                                             unsigned long long *sums) {
+                                                             unsigned long long *merge) {
     extern __shared__ uint32_t lds[];
     const McShape ms = mc_shape(L);
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(lds);
@@ -341,20 +343,45 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_mc_kernel(const uint8_t *data,
     __shared__ unsigned long long tred[DIAG_WG];
     const unsigned long long tot = block_sum<unsigned long long>(tsum, tred);
     __syncthreads();
+    unsigned long long *copy = merge + (size_t)(blockIdx.x % DIAG_MERGE) * (L + 1);
     for (uint32_t k = threadIdx.x; k <= L; k += DIAG_WG) {
         const unsigned long long v = acc[k] + 256ull * tot;
-        if (v) atomicAdd(&sums[k], v);
+        if (v) atomicAdd(&copy[k], v);
     }
 }
 
-// S_k = raw_k - 128 (P_k + Q_k) - 16384 max(n - k, 0) for k <= L < AC_LDS_LAGS, with
+// S_k = raw_k - 128 (P_k + Q_k) - 16384 max(n - k, 0) for k <= L < AC_LDS_LAGS, raw_k the
+// sum of the merge copies (cleared here for the next call), with
 // P_k and Q_k the sums of the first and the last min(k, n) bytes (one workgroup:
 // thread t holds values 16t .. 16t+15 of both ends, then a block-wide scan).
 __global__ __launch_bounds__(DIAG_WG) void lagsum_fix_kernel(const uint8_t *data, uint64_t n, uint32_t L,
-                                                             unsigned long long *sums) {
+                                                             unsigned long long *merge, unsigned long long *sums) {
     constexpr uint32_t SEG = AC_LDS_LAGS / DIAG_WG;  // 16
     __shared__ uint32_t scan[2][DIAG_WG];
+    __shared__ unsigned long long raw[AC_LDS_LAGS];
     const uint32_t t = threadIdx.x;
+    // the copies' sums, lag k on thread k mod 256 (all loads of a thread issued together)
+    for (uint32_t k0 = 0; k0 <= L; k0 += DIAG_WG * 4) {
+        unsigned long long part[4][DIAG_MERGE];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t k = k0 + q * DIAG_WG + t;
+#pragma unroll
+            for (int c = 0; c < DIAG_MERGE; ++c) part[q][c] = k <= L ? merge[(size_t)c * (L + 1) + k] : 0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t k = k0 + q * DIAG_WG + t;
+            if (k > L) continue;
+            unsigned long long r = 0;
+#pragma unroll
+            for (int c = 0; c < DIAG_MERGE; ++c) {
+                r += part[q][c];
+                merge[(size_t)c * (L + 1) + k] = 0;
+            }
+            raw[k] = r;
+        }
+    }
     uint32_t v[2][SEG], tot[2] = {0, 0};
 #pragma unroll
     for (uint32_t u = 0; u < SEG; ++u) {
@@ -380,7 +407,7 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_fix_kernel(const uint8_t *data
         const uint32_t k = t * SEG + u;
         if (k <= L) {
             const unsigned long long m = k < n ? n - k : 0;
-            sums[k] = sums[k] - 128ull * ((unsigned long long)p0 + p1) - 16384ull * m;
+            sums[k] = raw[k] - 128ull * ((unsigned long long)p0 + p1) - 16384ull * m;
         }
         p0 += v[0][u];
         p1 += v[1][u];
@@ -893,8 +920,8 @@ extern "C" int lz_histogram(lz_ctx *c, const uint8_t *d_data, size_t n, uint64_t
     char *ws;  // the merge buffer is the context's: calls on different streams are ordered
     if (int rc = diag_begin(c, s, 0, &ws)) return rc;
     hipLaunchKernelGGL(histogram_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n,
-                       c->hist_merge);
-    hipLaunchKernelGGL(hist_merge_kernel, dim3(1), dim3(256), 0, s, c->hist_merge,
+                       c->diag_merge);
+    hipLaunchKernelGGL(hist_merge_kernel, dim3(1), dim3(256), 0, s, c->diag_merge,
                        reinterpret_cast<unsigned long long *>(d_hist));
     LZ_HIP(hipGetLastError());
     return diag_end(c, s);
@@ -906,25 +933,32 @@ extern "C" int lz_lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t 
     if (max_lag > 16384) return fail(LZ_E_INVAL, "max_lag must be <= 16384");
     hipStream_t s = (hipStream_t)stream;
     LZ_HIP(hipSetDevice(c->device));
-    LZ_HIP(launch_fill_u64(reinterpret_cast<unsigned long long *>(d_sums), (size_t)max_lag + 1, s));
-    if (n == 0) return LZ_OK;
     unsigned long long *sums = reinterpret_cast<unsigned long long *>(d_sums);
     const size_t mc_lds = lagsum_mc_lds_bytes(max_lag);
-    if (max_lag < AC_LDS_LAGS && mc_lds <= (size_t)c->dev.lds_per_wg_max) {
+    if (n > 0 && max_lag < AC_LDS_LAGS && mc_lds <= (size_t)c->dev.lds_per_wg_max) {
+        // the workgroups' sums meet in the context's merge copies, which the fix kernel adds up,
+        // writes to d_sums and clears: calls on different streams are ordered
+        static_assert((size_t)DIAG_MERGE * AC_LDS_LAGS <= DIAG_MERGE_WORDS, "merge buffer too small");
+        char *ws;
+        if (int rc = diag_begin(c, s, 0, &ws)) return rc;
         const uint64_t tasks = ((n + 15) / 16 + MC_ROWS - 1) / MC_ROWS;
         const uint64_t blocks = tasks < (uint64_t)c->dev.cus * 2 ? tasks : (uint64_t)c->dev.cus * 2;
         if (mc_lds > 65536)
             LZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&lagsum_mc_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)mc_lds));
         hipLaunchKernelGGL(lagsum_mc_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), mc_lds, s, d_data, (uint64_t)n,
-                           max_lag, sums);
-        hipLaunchKernelGGL(lagsum_fix_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag, sums);
-    } else {
-        uint64_t blocks = (n + AC_TILE - 1) / AC_TILE;
-        if (blocks > (uint64_t)c->dev.cus * 2) blocks = (uint64_t)c->dev.cus * 2;
-        hipLaunchKernelGGL(lagsum_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), lagsum_lds_bytes(max_lag), s, d_data,
-                           (uint64_t)n, max_lag, sums);
+                           max_lag, c->diag_merge);
+        hipLaunchKernelGGL(lagsum_fix_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag,
+                           c->diag_merge, sums);
+        LZ_HIP(hipGetLastError());
+        return diag_end(c, s);
     }
+    LZ_HIP(launch_fill_u64(sums, (size_t)max_lag + 1, s));
+    if (n == 0) return LZ_OK;
+    uint64_t blocks = (n + AC_TILE - 1) / AC_TILE;
+    if (blocks > (uint64_t)c->dev.cus * 2) blocks = (uint64_t)c->dev.cus * 2;
+    hipLaunchKernelGGL(lagsum_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), lagsum_lds_bytes(max_lag), s, d_data,
+                       (uint64_t)n, max_lag, sums);
     LZ_HIP(hipGetLastError());
     return LZ_OK;
 }

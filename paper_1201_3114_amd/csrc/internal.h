@@ -146,9 +146,10 @@ struct CopyPiece {
     uint64_t len;
 };
 constexpr uint64_t COPY_PIECE_BYTES = 1ull << 20;  // requests are cut into pieces of at most this size
-// histogram: workgroup b merges its counts into copy b mod HIST_MERGE of the 256 bins
-constexpr int HIST_MERGE = 8;
-constexpr size_t HIST_MERGE_BYTES = (size_t)HIST_MERGE * 256 * 8;
+// diagnostics merge buffer: workgroup b of the histogram and of the lag sums adds its partial
+// results into copy b mod DIAG_MERGE; the one-workgroup kernel that follows sums and clears them
+constexpr int DIAG_MERGE = 8;
+constexpr size_t DIAG_MERGE_WORDS = (size_t)DIAG_MERGE * 4096;  // 64-bit: 256 bins or up to 4096 lags a copy
 hipError_t launch_copy_many(const CopyPiece *pieces, uint32_t n, hipStream_t s);
 
 // The method's scalar pieces over device arrays (R, Theta, F^steps), for checking.
@@ -178,9 +179,8 @@ struct lz_ctx {
     hipStream_t last_stream;
     hipEvent_t last_event;
     bool has_last;
-    // histogram merge buffer: 8 x 256 partial bin counts, zero between calls (each call's
-    // merge kernel clears them)
-    unsigned long long *hist_merge;
+    // diagnostics merge buffer (DIAG_MERGE_WORDS), zero between calls: each call's last kernel clears it
+    unsigned long long *diag_merge;
     // diagnostics workspace (grown on demand) and the event that orders its users
     void *diag_ws;
     size_t diag_ws_bytes;

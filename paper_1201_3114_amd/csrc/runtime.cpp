@@ -152,8 +152,8 @@ extern "C" int lz_context_create(int device, const lz_params *prm, lz_ctx **out)
     if (e == hipSuccess) e = hipHostMalloc(&c->host_status, sizeof(int32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->last_event, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->diag_event, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipMalloc(&c->hist_merge, HIST_MERGE_BYTES);
-    if (e == hipSuccess) e = hipMemset(c->hist_merge, 0, HIST_MERGE_BYTES);
+    if (e == hipSuccess) e = hipMalloc(&c->diag_merge, DIAG_MERGE_WORDS * 8);
+    if (e == hipSuccess) e = hipMemset(c->diag_merge, 0, DIAG_MERGE_WORDS * 8);
     if (e != hipSuccess) {
         int rc = hip_fail(e, "context allocation");
         lz_context_destroy(c);
@@ -171,7 +171,7 @@ extern "C" int lz_context_destroy(lz_ctx *c) {
     if (c->has_last) hipEventSynchronize(c->last_event);
     if (c->diag_has_last) hipEventSynchronize(c->diag_event);
     if (c->diag_ws) hipFree(c->diag_ws);
-    if (c->hist_merge) hipFree(c->hist_merge);
+    if (c->diag_merge) hipFree(c->diag_merge);
     if (c->diag_event) hipEventDestroy(c->diag_event);
     if (c->ws_tag) hipFree(c->ws_tag);
     if (c->ws_status) hipFree(c->ws_status);

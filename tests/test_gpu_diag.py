@@ -111,6 +111,30 @@ def test_lag_sums_exact(lz, ctx, n, L):
     assert np.array_equal(got, dg.lag_sums(x, L))
 
 
+def test_lag_sums_and_histograms_in_a_row_on_two_streams(lz, ctx):
+    """The lag sums below 4096 and the histogram share the context's merge copies, which each call clears:
+    calls with lags falling and rising (300, 100, 300, 4095, 0, ...), interleaved with histograms and queued
+    back to back on two streams, each equal their exact values."""
+    import torch
+
+    rng = np.random.default_rng(97)
+    cases = [(200_000, 300), (5_000, 100), (1_000_000, 300), (70_000, 4095), (33, 0), (9_999, 17), (64, 4095)]
+    xs = [rng.integers(0, 256, n, dtype=np.uint8) for n, _ in cases]
+    ds = [_dev(x) for x in xs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for rep in range(2):
+        for i, (d, (n, L)) in enumerate(zip(ds, cases)):
+            st = streams[(i + rep) % 2]
+            outs.append(("sums", i, lz.lag_sums(ctx, d, L, stream=st)))
+            outs.append(("hist", i, lz.histogram(ctx, d, stream=streams[(i + rep + 1) % 2])))
+    torch.cuda.synchronize()
+    for kind, i, t in outs:
+        want = dg.lag_sums(xs[i], cases[i][1]) if kind == "sums" else dg.histogram(xs[i])
+        assert np.array_equal(host(t).astype(np.int64), want), (kind, cases[i])
+
+
 @pytest.mark.parametrize("L", [0, 100, 4095])
 def test_lag_sums_unaligned_and_many_tasks(lz, ctx, L):
     """A data pointer off 4-byte alignment (byte loads when staging), and 40 MiB + 3 bytes: more
