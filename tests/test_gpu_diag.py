@@ -135,6 +135,45 @@ def test_lag_sums_and_histograms_in_a_row_on_two_streams(lz, ctx):
         assert np.array_equal(host(t).astype(np.int64), want), (kind, cases[i])
 
 
+def _ramp_histogram(n):
+    """Byte counts of x_i = i mod 256, i < n (closed form)."""
+    return np.array([n // 256 + (1 if v < n % 256 else 0) for v in range(256)], dtype=np.int64)
+
+
+def _ramp_lag_sum(n, k):
+    """S_k of x_i = i mod 256, i < n: (n - k) // 256 whole periods of the pairs (a, (a + k) mod 256), then
+    the first (n - k) mod 256 pairs of one more (closed form, Python integers)."""
+    if k >= n:
+        return 0
+    q, r = divmod(n - k, 256)
+    per = [a * ((a + k) % 256) for a in range(256)]
+    return q * sum(per) + sum(per[:r])
+
+
+def test_histogram_and_lag_sums_past_4GiB(lz, ctx):
+    """Maximum sizes: 2^32 + 4099 bytes of the ramp x_i = i mod 256, so bin counts and lag sums pass 2^32 and
+    the byte index passes 32 bits, checked exactly against closed forms (themselves checked against the
+    oracle on a short ramp first)."""
+    import torch
+
+    short = np.arange(70_001, dtype=np.int64).astype(np.uint8)
+    assert np.array_equal(_ramp_histogram(len(short)), dg.histogram(short))
+    ls = dg.lag_sums(short, 300)
+    assert all(int(ls[k]) == _ramp_lag_sum(len(short), k) for k in range(301))
+    n = (1 << 32) + 4099
+    big = torch.arange(256, dtype=torch.uint8, device="cuda").repeat(n // 256 + 1)[:n]
+    assert big.is_contiguous() and big.numel() == n
+    say("histogram and lag sums of", n, "bytes")
+    h = host(lz.histogram(ctx, big)).astype(np.int64)
+    assert np.array_equal(h, _ramp_histogram(n))
+    L = 300
+    got = host(lz.lag_sums(ctx, big, L))
+    for k in range(L + 1):
+        assert int(got[k]) == _ramp_lag_sum(n, k), k
+    del big
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("L", [0, 100, 4095])
 def test_lag_sums_unaligned_and_many_tasks(lz, ctx, L):
     """A data pointer off 4-byte alignment (byte loads when staging), and 40 MiB + 3 bytes: more
