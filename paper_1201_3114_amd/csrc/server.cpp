@@ -338,9 +338,9 @@ void release(lz_server *s, Request *r) {
 }
 
 // Applies the cancellations queued by lz_server_cancel: a request not yet admitted
-// completes as cancelled now (if it has not arrived yet, when it does); an active
-// one gets no further ticks and is released by release_cancelled.  Ids that match
-// nothing (already completed, or unknown) are dropped.
+// (waiting, or not arrived yet) completes as cancelled now; an active one gets no
+// further ticks and is released by release_cancelled.  Ids that match nothing
+// (already completed, or unknown) are dropped.
 void apply_cancels(lz_server *s) {
     std::vector<uint64_t> ids;
     {
@@ -361,12 +361,17 @@ void apply_cancels(lz_server *s) {
             (*a)->cancelled = true;
             continue;
         }
-        std::lock_guard<std::mutex> g(s->mu);
-        for (Request *r : s->pending)
-            if (r->id == id && !r->cancelled) {
-                r->cancelled = true;
-                break;
+        Request *early = nullptr;  // not arrived yet: leaves the arrival heap and completes now
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            auto p = std::find_if(s->pending.begin(), s->pending.end(), [&](Request *r) { return r->id == id; });
+            if (p != s->pending.end()) {
+                early = *p;
+                s->pending.erase(p);
+                std::make_heap(s->pending.begin(), s->pending.end(), ArrivalLater());
             }
+        }
+        if (early) finish(s, early, LZ_E_CANCELLED, lz_now_ns());
     }
 }
 
@@ -495,7 +500,6 @@ bool busy(lz_server *s) { return !s->waiting.empty() || !s->active.empty() || s-
 
 void server_loop(lz_server *s) {
     hipSetDevice(s->ctx->device);
-    std::vector<Request *> arrived_cancelled;
     for (;;) {
         {
             std::unique_lock<std::mutex> g(s->mu);
@@ -503,12 +507,10 @@ void server_loop(lz_server *s) {
                 const uint64_t now = lz_now_ns();
                 while (!s->pending.empty() && s->pending.front()->arrival_ns <= now) {
                     std::pop_heap(s->pending.begin(), s->pending.end(), ArrivalLater());
-                    Request *r = s->pending.back();
+                    s->waiting.push_back(s->pending.back());
                     s->pending.pop_back();
-                    if (r->cancelled) arrived_cancelled.push_back(r);
-                    else s->waiting.push_back(r);
                 }
-                if (busy(s) || !arrived_cancelled.empty() || !s->cancels.empty()) break;
+                if (busy(s) || !s->cancels.empty()) break;
                 if (s->stop && s->pending.empty()) return;
                 if (s->pending.empty()) {
                     s->cv_submit.wait(g);
@@ -518,8 +520,6 @@ void server_loop(lz_server *s) {
                 }
             }
         }
-        for (Request *r : arrived_cancelled) finish(s, r, LZ_E_CANCELLED, lz_now_ns());
-        arrived_cancelled.clear();
         if (!busy(s)) {  // only cancellations to apply
             apply_cancels(s);
             continue;
