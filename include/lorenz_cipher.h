@@ -317,7 +317,7 @@ int lz_server_destroy(lz_server *srv);
 /* ---- diagnostics of Section 4 (frequency analysis, autocorrelation) -------------
  * lz_histogram: d_hist (device, 256 uint64, overwritten) receives the count of
  * each byte value of d_data (device, n bytes); the Shannon entropy
- * S = -sum p_i log2 p_i follows from it.  Uses the context's 256 KB merge
+ * S = -sum p_i log2 p_i follows from it.  Uses the context's 1 MB merge
  * buffer (calls of one context are ordered across streams, as for the
  * workspace below).  Asynchronous on stream. */
 int lz_histogram(lz_ctx *ctx, const uint8_t *d_data, size_t n, uint64_t *d_hist, void *stream);
@@ -326,9 +326,9 @@ int lz_histogram(lz_ctx *ctx, const uint8_t *d_data, size_t n, uint64_t *d_hist,
  * exact integer sums S_k = sum_{i < n-k} x_i x_{i+k}, k = 0..max_lag
  * (max_lag <= 16384), from which the autocorrelation of the byte sequence
  * follows: r_k = (S_k - m (A_k + B_k) + (n-k) m^2) / (S_0 - n m^2), m the mean,
- * A_k = sum_{i < n-k} x_i, B_k = sum_{i >= k} x_i.  For max_lag < 4096 it uses
- * the context's merge buffer (calls of one context are ordered across
- * streams).  Asynchronous on stream. */
+ * A_k = sum_{i < n-k} x_i, B_k = sum_{i >= k} x_i.  Uses the context's merge
+ * buffer (calls of one context are ordered across streams).  Asynchronous on
+ * stream. */
 int lz_lag_sums(lz_ctx *ctx, const uint8_t *d_data, size_t n, uint32_t max_lag, uint64_t *d_sums, void *stream);
 
 /* lz_entropy: d_S (device, 1 double) receives S = -sum p_i log2 p_i, p_i =

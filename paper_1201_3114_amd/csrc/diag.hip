@@ -3,10 +3,10 @@
 // sequence, and, for a byte matrix (a text or an image laid out row by row),
 // the circular autocorrelation matrix and the 2-D Fourier power spectrum.
 // Integer sums are exact (the results do not depend on the reduction order);
-// the floating-point results are binary64.  The lag sums (below 4096 lags) are
-// int8 matrix products and the 2-D transforms of sides that are not powers of
-// two are binary64 matrix products, both on the matrix cores; power-of-two sides
-// are transformed by FFT.
+// the floating-point results are binary64.  The lag sums are int8 matrix
+// products (in windows of 4096 lags) on the matrix cores; the 2-D transforms run
+// as FFTs for sides with no prime factor above 5 and as binary64 matrix products
+// on the matrix cores otherwise.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -92,87 +92,6 @@ __global__ __launch_bounds__(256) void hist_merge_kernel(unsigned long long *mer
     hist[threadIdx.x] = t;
 }
 
-// S_k = sum_{i < n-k} x_i x_{i+k} for k = 0..L.  A workgroup takes tiles of
-// AC_TILE positions i in turn and stages each, plus the L + 4 bytes after it, in
-// LDS (zero past n, so out-of-range products vanish).  A work item is a group of
-// four consecutive lags 4g..4g+3 over a run of rows: per four rows it reads one
-// aligned word of x_i and one new aligned word of the shifted window, forms the
-// three byte-shifted windows with alignbyte, and accumulates four-byte dot
-// products (v_dot4_u32_u8) in 32-bit sums (at most AC_TILE * 255^2 < 2^32);
-// runs are multiples of 16 rows, read four words at a time.
-// For L < AC_LDS_LAGS the sums of all items and tiles meet in 64-bit LDS
-// counters, so a workgroup issues one global atomic per lag; beyond that each
-// item adds its sums to the global counters directly.
-constexpr int AC_TILE = 16384;         // a multiple of 4
-constexpr uint32_t AC_LDS_LAGS = 4096;
-
-size_t lagsum_lds_bytes(uint32_t L) {
-    const size_t acc = L < AC_LDS_LAGS ? ((size_t)(L + 1) * 8 + 15) / 16 * 16 : 0;
-    return acc + AC_TILE + ((L + 3) & ~3u) + 8;
-}
-
-__global__ __launch_bounds__(DIAG_WG) void lagsum_kernel(const uint8_t *data, uint64_t n, uint32_t L,
-                                                          unsigned long long *sums) {
-    extern __shared__ uint32_t lds[];
-    const bool use_acc = L < AC_LDS_LAGS;
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(lds);
-    const size_t acc_words = use_acc ? ((size_t)(L + 1) * 8 + 15) / 16 * 4 : 0;
-    uint32_t *t32 = lds + acc_words;
-    uint8_t *t = reinterpret_cast<uint8_t *>(t32);
-    if (use_acc)
-        for (uint32_t k = threadIdx.x; k <= L; k += DIAG_WG) acc[k] = 0;
-    const uint32_t span = AC_TILE + ((L + 3) & ~3u) + 8;
-    const uint32_t G = (L + 4) / 4;                         // lag groups: 4g .. 4g + 3 covers 0..L
-    const uint32_t P = G >= DIAG_WG ? 1 : DIAG_WG / G;      // row runs per group
-    const uint64_t tiles = (n + AC_TILE - 1) / AC_TILE;
-    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        const uint64_t i0 = tile * AC_TILE;
-        __syncthreads();  // the previous tile's reads are done
-        for (uint32_t j = threadIdx.x; j < span; j += DIAG_WG) t[j] = i0 + j < n ? data[i0 + j] : 0;
-        __syncthreads();
-        const uint64_t left = n - i0;
-        const uint32_t rows = left < (uint64_t)AC_TILE ? (uint32_t)((left + 15) & ~15ull) : (uint32_t)AC_TILE;
-        const uint32_t plen = ((rows / 16 + P - 1) / P) * 16;  // rows per run, a multiple of 16
-        for (uint32_t item = threadIdx.x; item < G * P; item += DIAG_WG) {
-            const uint32_t g = item % G, p = item / G;
-            const uint32_t r_lo = p * plen;
-            const uint32_t r_hi = r_lo + plen < rows ? r_lo + plen : rows;
-            if (r_lo >= r_hi) continue;
-            const uint32_t k0 = 4 * g;
-            uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-            uint32_t w0 = t32[(r_lo + k0) / 4];
-            for (uint32_t r = r_lo; r < r_hi; r += 16) {  // 16 rows: eight LDS words in flight
-                uint32_t a[4], w[5];
-                w[0] = w0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    a[q] = t32[r / 4 + q];
-                    w[q + 1] = t32[(r + k0) / 4 + q + 1];
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    s0 = __builtin_amdgcn_udot4(a[q], w[q], s0, false);
-                    s1 = __builtin_amdgcn_udot4(a[q], __builtin_amdgcn_alignbyte(w[q + 1], w[q], 1), s1, false);
-                    s2 = __builtin_amdgcn_udot4(a[q], __builtin_amdgcn_alignbyte(w[q + 1], w[q], 2), s2, false);
-                    s3 = __builtin_amdgcn_udot4(a[q], __builtin_amdgcn_alignbyte(w[q + 1], w[q], 3), s3, false);
-                }
-                w0 = w[4];
-            }
-            const uint32_t sk[4] = {s0, s1, s2, s3};
-            for (int q = 0; q < 4; ++q) {
-                if (k0 + q > L || sk[q] == 0) continue;
-                if (use_acc) atomicAdd(&acc[k0 + q], (unsigned long long)sk[q]);
-                else atomicAdd(&sums[k0 + q], (unsigned long long)sk[q]);
-            }
-        }
-    }
-    if (use_acc) {
-        __syncthreads();
-        for (uint32_t k = threadIdx.x; k <= L; k += DIAG_WG)
-            if (acc[k]) atomicAdd(&sums[k], acc[k]);
-    }
-}
-
 // Block-wide sum over 256 threads (LDS tree, fixed order, so the result is deterministic).
 template <typename T>
 __device__ T block_sum(T v, T *red) {
@@ -187,7 +106,7 @@ __device__ T block_sum(T v, T *red) {
     return r;
 }
 
-// ---- the lag sums on the matrix cores, for L < AC_LDS_LAGS ---------------------------------
+// ---- the lag sums on the matrix cores ----------------------------------------------------
 //
 // With the bytes laid out as rows of 16, S_k is a sum along the diagonals of
 // G[c][j] = sum_r x[16 r + c] x[16 r + j] (c < 16, j < L + 16; lag k = j - c):
@@ -222,26 +141,31 @@ struct McShape {
     uint32_t nt, ntg, rs, stride;  // column tiles, tile groups of 8, row splits, LDS column stride (bytes)
 };
 
-__host__ __device__ inline McShape mc_shape(uint32_t L) {
+// L: the window's last lag relative to its first, k_lo (a multiple of MC_WINDOW); the column
+// tiles start k_lo / 16 rows further on, so the staged rows reach that much further
+constexpr uint32_t MC_WINDOW = 4096;
+
+__host__ __device__ inline McShape mc_shape(uint32_t L, uint32_t k_lo) {
     McShape m;
     m.nt = (L + 15) / 16 + 1;
     m.ntg = (m.nt + 7) / 8;
     m.rs = m.ntg >= 3 ? 1 : 4 / m.ntg;
-    m.stride = MC_ROWS + 16 * ((m.ntg + 1) / 2);
+    m.stride = MC_ROWS + k_lo / 16 + 16 * ((m.ntg + 1) / 2);
     return m;
 }
 
-size_t lagsum_mc_lds_bytes(uint32_t L) {
-    const McShape m = mc_shape(L);
+size_t lagsum_mc_lds_bytes(uint32_t L, uint32_t k_lo) {
+    const McShape m = mc_shape(L, k_lo);
     return ((size_t)(L + 1) * 8 + 15) / 16 * 16 + (size_t)16 * m.stride;
 }
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(DIAG_WG) void lagsum_mc_kernel(const uint8_t *data, uint64_t n, uint32_t L,
+                                                             uint32_t k_lo, uint32_t L_all,
                                                              unsigned long long *merge) {
     extern __shared__ uint32_t lds[];
-    const McShape ms = mc_shape(L);
+    const McShape ms = mc_shape(L, k_lo);
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(lds);
     uint8_t *lt = reinterpret_cast<uint8_t *>(lds) + ((size_t)(L + 1) * 8 + 15) / 16 * 16;
     for (uint32_t k = threadIdx.x; k <= L; k += DIAG_WG) acc[k] = 0;
@@ -305,7 +229,7 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_mc_kernel(const uint8_t *data,
                 const uint8_t *colp = lt + (size_t)col * ms.stride;
                 const uint4 av = *reinterpret_cast<const uint4 *>(colp + rb + 16 * g);
                 const v4i a = (v4i){(int)av.x, (int)av.y, (int)av.z, (int)av.w};
-                const uint8_t *bp = colp + rb + 8 * tg + 16 * g;
+                const uint8_t *bp = colp + rb + k_lo / 16 + 8 * tg + 16 * g;
                 const uint2 w01 = *reinterpret_cast<const uint2 *>(bp);
                 const uint2 w23 = *reinterpret_cast<const uint2 *>(bp + 8);
                 const uint2 w45 = *reinterpret_cast<const uint2 *>(bp + 16);
@@ -343,74 +267,83 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_mc_kernel(const uint8_t *data,
     __shared__ unsigned long long tred[DIAG_WG];
     const unsigned long long tot = block_sum<unsigned long long>(tsum, tred);
     __syncthreads();
-    unsigned long long *copy = merge + (size_t)(blockIdx.x % DIAG_MERGE) * (L + 1);
+    unsigned long long *copy = merge + (size_t)(blockIdx.x % DIAG_MERGE) * (L_all + 1) + k_lo;
     for (uint32_t k = threadIdx.x; k <= L; k += DIAG_WG) {
         const unsigned long long v = acc[k] + 256ull * tot;
         if (v) atomicAdd(&copy[k], v);
     }
 }
 
-// S_k = raw_k - 128 (P_k + Q_k) - 16384 max(n - k, 0) for k <= L < AC_LDS_LAGS, raw_k the
-// sum of the merge copies (cleared here for the next call), with
-// P_k and Q_k the sums of the first and the last min(k, n) bytes (one workgroup:
-// thread t holds values 16t .. 16t+15 of both ends, then a block-wide scan).
+// S_k = raw_k - 128 (P_k + Q_k) - 16384 max(n - k, 0) for k <= L, raw_k the sum of the
+// merge copies (cleared here for the next call), with P_k and Q_k the sums of the first
+// and the last min(k, n) bytes (one workgroup, one window of 4096 lags at a time: thread
+// t holds values kb + 16t .. kb + 16t + 15 of both ends, then a block-wide scan, and the
+// totals carry over to the next window).
 __global__ __launch_bounds__(DIAG_WG) void lagsum_fix_kernel(const uint8_t *data, uint64_t n, uint32_t L,
                                                              unsigned long long *merge, unsigned long long *sums) {
-    constexpr uint32_t SEG = AC_LDS_LAGS / DIAG_WG;  // 16
+    constexpr uint32_t SEG = MC_WINDOW / DIAG_WG;  // 16
     __shared__ uint32_t scan[2][DIAG_WG];
-    __shared__ unsigned long long raw[AC_LDS_LAGS];
+    __shared__ unsigned long long raw[MC_WINDOW];
     const uint32_t t = threadIdx.x;
-    // the copies' sums, lag k on thread k mod 256 (all loads of a thread issued together)
-    for (uint32_t k0 = 0; k0 <= L; k0 += DIAG_WG * 4) {
-        unsigned long long part[4][DIAG_MERGE];
+    unsigned long long c0 = 0, c1 = 0;  // sums of the first and of the last kb bytes
+    for (uint32_t kb = 0; kb <= L; kb += MC_WINDOW) {  // lags kb .. ke, one window at a time
+        const uint32_t ke = L - kb < MC_WINDOW - 1 ? L : kb + MC_WINDOW - 1;
+        __syncthreads();  // the previous window's reads of raw and scan are done
+        // the copies' sums, lag k on thread k mod 256 (all loads of a thread issued together)
+        for (uint32_t k0 = kb; k0 <= ke; k0 += DIAG_WG * 4) {
+            unsigned long long part[4][DIAG_MERGE];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t k = k0 + q * DIAG_WG + t;
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t k = k0 + q * DIAG_WG + t;
 #pragma unroll
-            for (int c = 0; c < DIAG_MERGE; ++c) part[q][c] = k <= L ? merge[(size_t)c * (L + 1) + k] : 0ull;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t k = k0 + q * DIAG_WG + t;
-            if (k > L) continue;
-            unsigned long long r = 0;
-#pragma unroll
-            for (int c = 0; c < DIAG_MERGE; ++c) {
-                r += part[q][c];
-                merge[(size_t)c * (L + 1) + k] = 0;
+                for (int c = 0; c < DIAG_MERGE; ++c) part[q][c] = k <= ke ? merge[(size_t)c * (L + 1) + k] : 0ull;
             }
-            raw[k] = r;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t k = k0 + q * DIAG_WG + t;
+                if (k > ke) continue;
+                unsigned long long r = 0;
+#pragma unroll
+                for (int c = 0; c < DIAG_MERGE; ++c) {
+                    r += part[q][c];
+                    merge[(size_t)c * (L + 1) + k] = 0;
+                }
+                raw[k - kb] = r;
+            }
         }
-    }
-    uint32_t v[2][SEG], tot[2] = {0, 0};
+        uint32_t v[2][SEG], tot[2] = {0, 0};
 #pragma unroll
-    for (uint32_t u = 0; u < SEG; ++u) {
-        const uint64_t j = (uint64_t)t * SEG + u;
-        v[0][u] = j < n ? data[j] : 0u;          // x_0, x_1, ...
-        v[1][u] = j < n ? data[n - 1 - j] : 0u;  // x_{n-1}, x_{n-2}, ...
-    }
-#pragma unroll
-    for (uint32_t u = 0; u < SEG; ++u) tot[0] += v[0][u], tot[1] += v[1][u];
-    scan[0][t] = tot[0];
-    scan[1][t] = tot[1];
-    __syncthreads();
-    for (uint32_t d = 1; d < DIAG_WG; d <<= 1) {  // inclusive scan (Hillis-Steele)
-        const uint32_t a0 = t >= d ? scan[0][t - d] : 0u, a1 = t >= d ? scan[1][t - d] : 0u;
-        __syncthreads();
-        scan[0][t] += a0;
-        scan[1][t] += a1;
-        __syncthreads();
-    }
-    uint32_t p0 = scan[0][t] - tot[0], p1 = scan[1][t] - tot[1];  // sums of the first 16t values
-#pragma unroll
-    for (uint32_t u = 0; u < SEG; ++u) {
-        const uint32_t k = t * SEG + u;
-        if (k <= L) {
-            const unsigned long long m = k < n ? n - k : 0;
-            sums[k] = raw[k] - 128ull * ((unsigned long long)p0 + p1) - 16384ull * m;
+        for (uint32_t u = 0; u < SEG; ++u) {
+            const uint64_t j = (uint64_t)kb + t * SEG + u;
+            v[0][u] = j < n ? data[j] : 0u;          // x_j
+            v[1][u] = j < n ? data[n - 1 - j] : 0u;  // x_{n-1-j}
         }
-        p0 += v[0][u];
-        p1 += v[1][u];
+#pragma unroll
+        for (uint32_t u = 0; u < SEG; ++u) tot[0] += v[0][u], tot[1] += v[1][u];
+        scan[0][t] = tot[0];
+        scan[1][t] = tot[1];
+        __syncthreads();
+        for (uint32_t d = 1; d < DIAG_WG; d <<= 1) {  // inclusive scan (Hillis-Steele)
+            const uint32_t a0 = t >= d ? scan[0][t - d] : 0u, a1 = t >= d ? scan[1][t - d] : 0u;
+            __syncthreads();
+            scan[0][t] += a0;
+            scan[1][t] += a1;
+            __syncthreads();
+        }
+        // sums of the first and the last kb + 16 t values
+        unsigned long long p0 = c0 + (scan[0][t] - tot[0]), p1 = c1 + (scan[1][t] - tot[1]);
+#pragma unroll
+        for (uint32_t u = 0; u < SEG; ++u) {
+            const uint32_t k = kb + t * SEG + u;
+            if (k <= ke) {
+                const unsigned long long m = k < n ? n - k : 0;
+                sums[k] = raw[k - kb] - 128ull * (p0 + p1) - 16384ull * m;
+            }
+            p0 += v[0][u];
+            p1 += v[1][u];
+        }
+        c0 += scan[0][DIAG_WG - 1];
+        c1 += scan[1][DIAG_WG - 1];
     }
 }
 
@@ -934,11 +867,18 @@ extern "C" int lz_lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t 
     hipStream_t s = (hipStream_t)stream;
     LZ_HIP(hipSetDevice(c->device));
     unsigned long long *sums = reinterpret_cast<unsigned long long *>(d_sums);
-    const size_t mc_lds = lagsum_mc_lds_bytes(max_lag);
-    if (n > 0 && max_lag < AC_LDS_LAGS && mc_lds <= (size_t)c->dev.lds_per_wg_max) {
+    // the matrix-core route, one launch per window of MC_WINDOW lags, when each fits in LDS
+    size_t mc_lds = 0;
+    for (uint32_t k_lo = 0; k_lo <= max_lag; k_lo += MC_WINDOW) {
+        const uint32_t Lw = max_lag - k_lo < MC_WINDOW - 1 ? max_lag - k_lo : MC_WINDOW - 1;
+        const size_t b = lagsum_mc_lds_bytes(Lw, k_lo);
+        mc_lds = b > mc_lds ? b : mc_lds;
+    }
+    if (mc_lds > (size_t)c->dev.lds_per_wg_max) return fail(LZ_E_INVAL, "lag sums need more LDS than the device has");
+    if (n > 0) {
         // the workgroups' sums meet in the context's merge copies, which the fix kernel adds up,
         // writes to d_sums and clears: calls on different streams are ordered
-        static_assert((size_t)DIAG_MERGE * AC_LDS_LAGS <= DIAG_MERGE_WORDS, "merge buffer too small");
+        static_assert((size_t)DIAG_MERGE * (16384 + 1) <= DIAG_MERGE_WORDS, "merge buffer too small");
         char *ws;
         if (int rc = diag_begin(c, s, 0, &ws)) return rc;
         const uint64_t tasks = ((n + 15) / 16 + MC_ROWS - 1) / MC_ROWS;
@@ -946,19 +886,17 @@ extern "C" int lz_lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t 
         if (mc_lds > 65536)
             LZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&lagsum_mc_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)mc_lds));
-        hipLaunchKernelGGL(lagsum_mc_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), mc_lds, s, d_data, (uint64_t)n,
-                           max_lag, c->diag_merge);
+        for (uint32_t k_lo = 0; k_lo <= max_lag; k_lo += MC_WINDOW) {
+            const uint32_t Lw = max_lag - k_lo < MC_WINDOW - 1 ? max_lag - k_lo : MC_WINDOW - 1;
+            hipLaunchKernelGGL(lagsum_mc_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), lagsum_mc_lds_bytes(Lw, k_lo),
+                               s, d_data, (uint64_t)n, Lw, k_lo, max_lag, c->diag_merge);
+        }
         hipLaunchKernelGGL(lagsum_fix_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag,
                            c->diag_merge, sums);
         LZ_HIP(hipGetLastError());
         return diag_end(c, s);
     }
-    LZ_HIP(launch_fill_u64(sums, (size_t)max_lag + 1, s));
-    if (n == 0) return LZ_OK;
-    uint64_t blocks = (n + AC_TILE - 1) / AC_TILE;
-    if (blocks > (uint64_t)c->dev.cus * 2) blocks = (uint64_t)c->dev.cus * 2;
-    hipLaunchKernelGGL(lagsum_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), lagsum_lds_bytes(max_lag), s, d_data,
-                       (uint64_t)n, max_lag, sums);
+    LZ_HIP(launch_fill_u64(sums, (size_t)max_lag + 1, s));  // n == 0: every sum is 0
     LZ_HIP(hipGetLastError());
     return LZ_OK;
 }

@@ -100,11 +100,12 @@ def test_entropy(lz, ctx, kind):
 
 @pytest.mark.parametrize("n,L", [(0, 5), (1, 0), (10, 20), (5000, 300), (200_003, 256), (1_000_000, 1000),
                                  (50_000, 4095), (50_000, 4096), (30_001, 16384), (3, 16384), (15, 1), (16, 16),
-                                 (65_537, 127), (98_309, 511)])
+                                 (65_537, 127), (98_309, 511), (100_003, 8191), (100_003, 8192), (77_777, 12289),
+                                 (20_000, 16383)])
 def test_lag_sums_exact(lz, ctx, n, L):
-    """Lags below 4096 run on the matrix cores (bytes offset by -128, then corrected exactly); from 4096 up
-    to the limit 16384 on the four-byte dot products, each work item adding to the global counters
-    directly: both paths, lags beyond n and partial 16-byte rows are compared exactly."""
+    """The lags run on the matrix cores (bytes offset by -128, then corrected exactly) in windows of 4096
+    lags, one launch each, whose sums the correction kernel takes window by window: window edges, lags
+    beyond n and partial 16-byte rows are compared exactly."""
     rng = np.random.default_rng(90 + n)
     x = rng.integers(0, 256, n, dtype=np.uint8)
     got = host(lz.lag_sums(ctx, _dev(x), L)).astype(np.int64)
@@ -169,6 +170,9 @@ def test_histogram_and_lag_sums_past_4GiB(lz, ctx):
     L = 300
     got = host(lz.lag_sums(ctx, big, L))
     for k in range(L + 1):
+        assert int(got[k]) == _ramp_lag_sum(n, k), k
+    got = host(lz.lag_sums(ctx, big, 4200))  # two lag windows
+    for k in (0, 1, 255, 4095, 4096, 4097, 4111, 4199, 4200):
         assert int(got[k]) == _ramp_lag_sum(n, k), k
     del big
     torch.cuda.empty_cache()
