@@ -380,6 +380,9 @@ def bench_diag(lz, torch, reps=5):
     n16, L = 16 * MiB, 256
     ms = timed(lambda: lz.autocorrelation(ctx, x[:n16], L))
     res["autocorrelation_16MiB_lag256"] = dict(ms=ms, int_MAC_per_s=n16 * (L + 1) / ms * 1e3)
+    L = 16384  # the largest lag count: four windows of 4096 lags on the int8 matrix cores
+    ms = timed(lambda: lz.lag_sums(ctx, x[:n16], L))
+    res["lag_sums_16MiB_lag16384"] = dict(ms=ms, int_MAC_per_s=n16 * (L + 1) / ms * 1e3)
     # power-of-two sides: two FFT passes, bound by HBM; algorithmic bytes: the image (1 B per value)
     # in, 16 B complex out and in again, 8 B |Z|^2 out
     N = 1024
