@@ -563,6 +563,7 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
 // W^{a N/4 + b} = (sign i)^a W^b.  About 2.1 p flops per value instead of the
 // direct pass's 8 N.
 constexpr uint32_t FFT_MAX = 4096;
+constexpr uint32_t FFT_PP_MAX = 1024;             // two LDS copies of the columns up to this length (36 KB)
 constexpr uint32_t FFT_WG_ELEMS = 1024;           // complex values per workgroup when N <= 1024 (16 KB of LDS)
 constexpr int FFT_EPT = FFT_MAX / DIAG_WG;        // values per thread, at most
 constexpr int FFT_B2 = FFT_MAX / 2 / DIAG_WG;     // radix-2 butterflies per thread, at most
@@ -590,8 +591,12 @@ __device__ __forceinline__ double2 fft_twiddle(const double2 *q, uint32_t j, uin
 template <typename In, int E>
 __global__ __launch_bounds__(DIAG_WG) void fft_pass_kernel(const In *src, uint32_t N, uint32_t M, uint32_t logN,
                                                             uint32_t C, double sign, PassOut dst) {
-    extern __shared__ double2 fbuf[];  // C columns of N values, then the twiddles
-    double2 *ftw = fbuf + (size_t)C * N;
+    // C columns of N values (twice when N <= FFT_PP_MAX: each stage reads one copy and writes the
+    // other, so it needs one barrier instead of two), then the twiddles
+    extern __shared__ double2 fbuf[];
+    const bool pp = N <= FFT_PP_MAX;
+    double2 *cur = fbuf, *nxt = fbuf + (pp ? (size_t)C * N : 0);
+    double2 *ftw = fbuf + (size_t)(pp ? 2 : 1) * C * N;
     // consecutive column groups on the same XCD (workgroups are dealt to the 8 XCDs in turn),
     // so the partly shared cache lines of neighbouring groups meet in one L2
     uint32_t g = blockIdx.x;
@@ -621,7 +626,7 @@ __global__ __launch_bounds__(DIAG_WG) void fft_pass_kernel(const In *src, uint32
             const uint32_t e = threadIdx.x + i * DIAG_WG;
             if (e < total) {
                 const uint32_t k = e / cols, cl = e - k * cols;
-                fbuf[cl * N + k] = dft_value(v[i]);
+                cur[cl * N + k] = dft_value(v[i]);
             }
         }
     }
@@ -635,24 +640,27 @@ __global__ __launch_bounds__(DIAG_WG) void fft_pass_kernel(const In *src, uint32
         for (int i = 0; i < FFT_B2; ++i) {
             const uint32_t u = threadIdx.x + i * DIAG_WG;
             if (u < nb) {
-                const double2 *x = fbuf + (u >> (logN - 1)) * N;
+                const double2 *x = cur + (u >> (logN - 1)) * N;
                 const uint32_t j = u & (half - 1);
                 a[i] = x[j];
                 b[i] = x[j + half];
             }
         }
-        __syncthreads();
+        if (!pp) __syncthreads();
 #pragma unroll
         for (int i = 0; i < FFT_B2; ++i) {
             const uint32_t u = threadIdx.x + i * DIAG_WG;
             if (u < nb) {
-                double2 *x = fbuf + (u >> (logN - 1)) * N;
+                double2 *x = nxt + (u >> (logN - 1)) * N;
                 const uint32_t j = u & (half - 1);
                 x[2 * j] = cadd(a[i], b[i]);
                 x[2 * j + 1] = cmul(csub(a[i], b[i]), fft_twiddle(ftw, j, logN, sign));
             }
         }
         __syncthreads();
+        double2 *t = cur;
+        cur = nxt;
+        nxt = t;
         st = 1;
     }
     const uint32_t quarter = N >> 2, nb4 = cols * quarter;
@@ -663,18 +671,18 @@ __global__ __launch_bounds__(DIAG_WG) void fft_pass_kernel(const In *src, uint32
         for (int i = 0; i < FFT_B4; ++i) {
             const uint32_t u = threadIdx.x + i * DIAG_WG;
             if (u < nb4) {
-                const double2 *x = fbuf + (u >> (logN - 2)) * N;
+                const double2 *x = cur + (u >> (logN - 2)) * N;
                 const uint32_t t = u & (quarter - 1), q = t & (s - 1), j = t >> st;
 #pragma unroll
                 for (int l = 0; l < 4; ++l) a[i][l] = x[q + s * (j + l * m)];
             }
         }
-        __syncthreads();
+        if (!pp) __syncthreads();
 #pragma unroll
         for (int i = 0; i < FFT_B4; ++i) {
             const uint32_t u = threadIdx.x + i * DIAG_WG;
             if (u < nb4) {
-                double2 *x = fbuf + (u >> (logN - 2)) * N;
+                double2 *x = nxt + (u >> (logN - 2)) * N;
                 const uint32_t t = u & (quarter - 1), q = t & (s - 1), j = t >> st;
                 const double2 t0 = cadd(a[i][0], a[i][2]), t1 = csub(a[i][0], a[i][2]);
                 const double2 t2 = cadd(a[i][1], a[i][3]), t3 = csub(a[i][1], a[i][3]);
@@ -687,9 +695,12 @@ __global__ __launch_bounds__(DIAG_WG) void fft_pass_kernel(const In *src, uint32
             }
         }
         __syncthreads();
+        double2 *t = cur;
+        cur = nxt;
+        nxt = t;
     }
     for (uint32_t e = threadIdx.x; e < total; e += DIAG_WG) {
-        const double2 v = fbuf[e];
+        const double2 v = cur[e];
         pass_store<E>(dst, (size_t)c0 * N + e, v.x, v.y);
     }
 }
@@ -1006,9 +1017,13 @@ bool mixed_ok(const lz_ctx *c, uint32_t N) {
     return N <= FFT_MAX && N > 1 && mixed_plan(N).nst > 0 && mixed_lds(N) <= (size_t)c->dev.lds_per_wg_max;
 }
 
-bool fft_ok(const lz_ctx *c, uint32_t N) {
+size_t fft_lds(uint32_t N) {
     const uint32_t per_wg = N > FFT_WG_ELEMS ? N : FFT_WG_ELEMS;
-    const size_t lds = ((size_t)per_wg + fft_twiddles(N)) * sizeof(double2);
+    return ((size_t)(N <= FFT_PP_MAX ? 2 : 1) * per_wg + fft_twiddles(N)) * sizeof(double2);
+}
+
+bool fft_ok(const lz_ctx *c, uint32_t N) {
+    const size_t lds = fft_lds(N);
     return (N & (N - 1)) == 0 && N <= FFT_MAX && lds <= (size_t)c->dev.lds_per_wg_max;
 }
 
@@ -1025,7 +1040,7 @@ int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, cons
         const uint32_t per_wg = N > FFT_WG_ELEMS ? N : FFT_WG_ELEMS;
         const uint32_t C = per_wg / N;
         const uint32_t groups = (M + C - 1) / C;
-        const size_t lds = ((size_t)per_wg + fft_twiddles(N)) * sizeof(double2);
+        const size_t lds = fft_lds(N);
         if (lds > 65536)
             LZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_pass_kernel<In, E>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
