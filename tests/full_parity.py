@@ -1,5 +1,5 @@
-"""Full-size parity check, run by hand on a GPU machine (not collected by pytest: about ten minutes, almost
-all of it the CPU oracle): every byte and the tag of the 64 MiB plain workload, and every one of the 4,096
+"""Full-size parity check, run by hand on a machine with an MI355X (not collected by pytest: about ten
+minutes, almost all of it the CPU oracle): every byte and the tag of the 64 MiB plain workload, and every one of the 4,096
 messages of the batch workload (638 MB), against the oracle.
 
     python tests/full_parity.py
