@@ -635,9 +635,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU; every block is independent, so more GPUs "
-                                   "would shard blocks with no collective beyond a 24-byte tag XOR "
-                                   "(see the design notes); --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; every block is independent, so more GPUs "
+                                   "would shard the blocks, with a 24-byte tag XOR as the only collective; "
+                                   "--gpus must be 1"}))
         sys.exit(2)
 
     import torch
