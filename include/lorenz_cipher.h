@@ -65,7 +65,7 @@ enum {
  *                           r += dt/6 ((k1 + k4) + 2 (k2 + k3)). */
 enum { LZ_INTEGRATOR_EULER = 0, LZ_INTEGRATOR_EULER_FMA = 1, LZ_INTEGRATOR_RK4 = 2 };
 
-/* Parameters of the method (Section 3.1; readings in the design notes).
+/* Parameters of the method (Section 3.1).
  * Defaults (lz_params_default): dt = 0.01, lambda = (1,1,1), n_it = 3000,
  * block_len = 256, k = (4,4,4), integrator = LZ_INTEGRATOR_EULER.  Valid
  * ranges (else LZ_E_INVAL): 0 < dt <= 0.024 (forward Euler diverges from the

@@ -16,7 +16,7 @@
  * round-to-nearest-even operation, no contraction, no reassociation.)
  *
  * Readings of the paper taken here (the paper is silent or garbled at these
- * points); each is listed with its justification in the design notes:
+ * points):
  *   - the Euler map of Section 3.1 is the standard forward Euler step of the
  *     Lorenz system, evaluated in the fixed order of lorenz_euler_step();
  *   - log in g(x) of Section 3.1 is log10, so D = digit count of 2^(8(L+1))
