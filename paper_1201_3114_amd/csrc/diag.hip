@@ -267,11 +267,13 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_mc_kernel(const uint8_t *data,
     __shared__ unsigned long long tred[DIAG_WG];
     const unsigned long long tot = block_sum<unsigned long long>(tsum, tred);
     __syncthreads();
-    unsigned long long *copy = merge + (size_t)(blockIdx.x % DIAG_MERGE) * (L_all + 1) + k_lo;
+    // copy layout: lags 0..L_all, then the byte total (added by the first window only)
+    unsigned long long *copy = merge + (size_t)(blockIdx.x % DIAG_MERGE) * (L_all + 2);
     for (uint32_t k = threadIdx.x; k <= L; k += DIAG_WG) {
         const unsigned long long v = acc[k] + 256ull * tot;
-        if (v) atomicAdd(&copy[k], v);
+        if (v) atomicAdd(&copy[k_lo + k], v);
     }
+    if (k_lo == 0 && threadIdx.x == 0 && tot) atomicAdd(&copy[L_all + 1], tot);
 }
 
 // S_k = raw_k - 128 (P_k + Q_k) - 16384 max(n - k, 0) for k <= L, raw_k the sum of the
@@ -280,11 +282,21 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_mc_kernel(const uint8_t *data,
 // t holds values kb + 16t .. kb + 16t + 15 of both ends, then a block-wide scan, and the
 // totals carry over to the next window).
 __global__ __launch_bounds__(DIAG_WG) void lagsum_fix_kernel(const uint8_t *data, uint64_t n, uint32_t L,
-                                                             unsigned long long *merge, unsigned long long *sums) {
+                                                             unsigned long long *merge, unsigned long long *sums,
+                                                             unsigned long long *total) {
     constexpr uint32_t SEG = MC_WINDOW / DIAG_WG;  // 16
     __shared__ uint32_t scan[2][DIAG_WG];
     __shared__ unsigned long long raw[MC_WINDOW];
     const uint32_t t = threadIdx.x;
+    if (t < 64) {  // wave 0: the byte total over the copies (cleared), written to *total when asked for
+        unsigned long long v = 0;
+        if (t < DIAG_MERGE) {
+            v = merge[(size_t)t * (L + 2) + L + 1];
+            merge[(size_t)t * (L + 2) + L + 1] = 0;
+        }
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (t == 0 && total) *total = v;
+    }
     unsigned long long c0 = 0, c1 = 0;  // sums of the first and of the last kb bytes
     for (uint32_t kb = 0; kb <= L; kb += MC_WINDOW) {  // lags kb .. ke, one window at a time
         const uint32_t ke = L - kb < MC_WINDOW - 1 ? L : kb + MC_WINDOW - 1;
@@ -296,7 +308,7 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_fix_kernel(const uint8_t *data
             for (int q = 0; q < 4; ++q) {
                 const uint32_t k = k0 + q * DIAG_WG + t;
 #pragma unroll
-                for (int c = 0; c < DIAG_MERGE; ++c) part[q][c] = k <= ke ? merge[(size_t)c * (L + 1) + k] : 0ull;
+                for (int c = 0; c < DIAG_MERGE; ++c) part[q][c] = k <= ke ? merge[(size_t)c * (L + 2) + k] : 0ull;
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -306,7 +318,7 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_fix_kernel(const uint8_t *data
 #pragma unroll
                 for (int c = 0; c < DIAG_MERGE; ++c) {
                     r += part[q][c];
-                    merge[(size_t)c * (L + 1) + k] = 0;
+                    merge[(size_t)c * (L + 2) + k] = 0;
                 }
                 raw[k - kb] = r;
             }
@@ -372,15 +384,14 @@ __global__ __launch_bounds__(DIAG_WG) void entropy_kernel(const unsigned long lo
 // One workgroup scans the first and last L bytes in chunks of 256.
 __global__ __launch_bounds__(DIAG_WG) void autocorr_norm_kernel(const uint8_t *data, uint64_t n, uint32_t L,
                                                                  const unsigned long long *sums,
-                                                                 const unsigned long long *hist, double *r) {
-    __shared__ unsigned long long ired[DIAG_WG];
+                                                                 const unsigned long long *total, double *r) {
     __shared__ unsigned long long sh[DIAG_WG], st[DIAG_WG];
-    const unsigned long long T =
-        block_sum<unsigned long long>(hist[threadIdx.x] * (unsigned long long)threadIdx.x, ired);
+    const unsigned long long T = *total;
     const double m = (double)T / (double)n;
     const double den = (double)sums[0] - (double)n * m * m;
-    // no coefficient when every byte is equal (or there are none): at most one occupied value
-    const bool constant = block_sum<unsigned long long>(hist[threadIdx.x] != 0, ired) <= 1;
+    // no coefficient when every byte is equal (or there are none): n S_0 = T^2 exactly then, and
+    // only then (the equality case of Cauchy-Schwarz), compared in 128-bit integers
+    const bool constant = n == 0 || (unsigned __int128)n * sums[0] == (unsigned __int128)T * T;
     unsigned long long carry_h = 0, carry_t = 0;
     if (threadIdx.x == 0) r[0] = constant ? __builtin_nan("") : 1.0;
     for (uint32_t c = 0; c < L; c += DIAG_WG) {
@@ -871,13 +882,11 @@ extern "C" int lz_histogram(lz_ctx *c, const uint8_t *d_data, size_t n, uint64_t
     return diag_end(c, s);
 }
 
-extern "C" int lz_lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, uint64_t *d_sums,
-                           void *stream) {
-    if (!c || !d_sums || (!d_data && n)) return fail(LZ_E_INVAL, "NULL argument");
-    if (max_lag > 16384) return fail(LZ_E_INVAL, "max_lag must be <= 16384");
-    hipStream_t s = (hipStream_t)stream;
-    LZ_HIP(hipSetDevice(c->device));
-    unsigned long long *sums = reinterpret_cast<unsigned long long *>(d_sums);
+namespace {
+
+// The lag sums into sums[0..max_lag]; with total non-null, also the byte total into *total.
+int lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, unsigned long long *sums,
+             unsigned long long *total, hipStream_t s) {
     // the matrix-core route, one launch per window of MC_WINDOW lags, when each fits in LDS
     size_t mc_lds = 0;
     for (uint32_t k_lo = 0; k_lo <= max_lag; k_lo += MC_WINDOW) {
@@ -889,7 +898,7 @@ extern "C" int lz_lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t 
     if (n > 0) {
         // the workgroups' sums meet in the context's merge copies, which the fix kernel adds up,
         // writes to d_sums and clears: calls on different streams are ordered
-        static_assert((size_t)DIAG_MERGE * (16384 + 1) <= DIAG_MERGE_WORDS, "merge buffer too small");
+        static_assert((size_t)DIAG_MERGE * (16384 + 2) <= DIAG_MERGE_WORDS, "merge buffer too small");
         char *ws;
         if (int rc = diag_begin(c, s, 0, &ws)) return rc;
         const uint64_t tasks = ((n + 15) / 16 + MC_ROWS - 1) / MC_ROWS;
@@ -903,13 +912,25 @@ extern "C" int lz_lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t 
                                s, d_data, (uint64_t)n, Lw, k_lo, max_lag, c->diag_merge);
         }
         hipLaunchKernelGGL(lagsum_fix_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag,
-                           c->diag_merge, sums);
+                           c->diag_merge, sums, total);
         LZ_HIP(hipGetLastError());
         return diag_end(c, s);
     }
     LZ_HIP(launch_fill_u64(sums, (size_t)max_lag + 1, s));  // n == 0: every sum is 0
+    if (total) LZ_HIP(launch_fill_u64(total, 1, s));
     LZ_HIP(hipGetLastError());
     return LZ_OK;
+}
+
+}  // namespace
+
+extern "C" int lz_lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, uint64_t *d_sums,
+                           void *stream) {
+    if (!c || !d_sums || (!d_data && n)) return fail(LZ_E_INVAL, "NULL argument");
+    if (max_lag > 16384) return fail(LZ_E_INVAL, "max_lag must be <= 16384");
+    LZ_HIP(hipSetDevice(c->device));
+    return lag_sums(c, d_data, n, max_lag, reinterpret_cast<unsigned long long *>(d_sums), nullptr,
+                    (hipStream_t)stream);
 }
 
 namespace {
@@ -1086,14 +1107,12 @@ extern "C" int lz_autocorrelation(lz_ctx *c, const uint8_t *d_data, size_t n, ui
     hipStream_t s = (hipStream_t)stream;
     LZ_HIP(hipSetDevice(c->device));
     char *ws;
-    if (int rc = diag_begin(c, s, 256 * 8 + ((size_t)max_lag + 1) * 8, &ws)) return rc;
-    uint64_t *hist = reinterpret_cast<uint64_t *>(ws);
-    uint64_t *sums = hist + 256;
-    if (int rc = lz_histogram(c, d_data, n, hist, stream)) return rc;
-    if (int rc = lz_lag_sums(c, d_data, n, max_lag, sums, stream)) return rc;
-    hipLaunchKernelGGL(autocorr_norm_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag,
-                       reinterpret_cast<const unsigned long long *>(sums),
-                       reinterpret_cast<const unsigned long long *>(hist), d_r);
+    if (int rc = diag_begin(c, s, 8 + ((size_t)max_lag + 1) * 8, &ws)) return rc;
+    unsigned long long *total = reinterpret_cast<unsigned long long *>(ws);
+    unsigned long long *sums = total + 1;
+    if (int rc = lag_sums(c, d_data, n, max_lag, sums, total, s)) return rc;
+    hipLaunchKernelGGL(autocorr_norm_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag, sums,
+                       total, d_r);
     LZ_HIP(hipGetLastError());
     return diag_end(c, s);
 }

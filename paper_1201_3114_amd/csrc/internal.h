@@ -149,7 +149,7 @@ constexpr uint64_t COPY_PIECE_BYTES = 1ull << 20;  // requests are cut into piec
 // diagnostics merge buffer: workgroup b of the histogram and of the lag sums adds its partial
 // results into copy b mod DIAG_MERGE; the one-workgroup kernel that follows sums and clears them
 constexpr int DIAG_MERGE = 8;
-constexpr size_t DIAG_MERGE_WORDS = (size_t)DIAG_MERGE * 16385;  // 64-bit: 256 bins or up to 16385 lags a copy
+constexpr size_t DIAG_MERGE_WORDS = (size_t)DIAG_MERGE * 16386;  // 64-bit: 256 bins, or up to 16385 lags + the byte total, a copy
 hipError_t launch_copy_many(const CopyPiece *pieces, uint32_t n, hipStream_t s);
 
 // The method's scalar pieces over device arrays (R, Theta, F^steps), for checking.
