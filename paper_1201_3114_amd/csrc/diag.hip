@@ -885,8 +885,10 @@ extern "C" int lz_histogram(lz_ctx *c, const uint8_t *d_data, size_t n, uint64_t
 namespace {
 
 // The lag sums into sums[0..max_lag]; with total non-null, also the byte total into *total.
+// ordered: the caller has already ordered this stream after the context's other diagnostics
+// (diag_begin) and records the event afterwards itself.
 int lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, unsigned long long *sums,
-             unsigned long long *total, hipStream_t s) {
+             unsigned long long *total, hipStream_t s, bool ordered = false) {
     // the matrix-core route, one launch per window of MC_WINDOW lags, when each fits in LDS
     size_t mc_lds = 0;
     for (uint32_t k_lo = 0; k_lo <= max_lag; k_lo += MC_WINDOW) {
@@ -900,7 +902,8 @@ int lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, unsig
         // writes to d_sums and clears: calls on different streams are ordered
         static_assert((size_t)DIAG_MERGE * (16384 + 2) <= DIAG_MERGE_WORDS, "merge buffer too small");
         char *ws;
-        if (int rc = diag_begin(c, s, 0, &ws)) return rc;
+        if (!ordered)
+            if (int rc = diag_begin(c, s, 0, &ws)) return rc;
         const uint64_t tasks = ((n + 15) / 16 + MC_ROWS - 1) / MC_ROWS;
         const uint64_t blocks = tasks < (uint64_t)c->dev.cus * 2 ? tasks : (uint64_t)c->dev.cus * 2;
         if (mc_lds > 65536)
@@ -914,7 +917,7 @@ int lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, unsig
         hipLaunchKernelGGL(lagsum_fix_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag,
                            c->diag_merge, sums, total);
         LZ_HIP(hipGetLastError());
-        return diag_end(c, s);
+        return ordered ? LZ_OK : diag_end(c, s);
     }
     LZ_HIP(launch_fill_u64(sums, (size_t)max_lag + 1, s));  // n == 0: every sum is 0
     if (total) LZ_HIP(launch_fill_u64(total, 1, s));
@@ -1110,7 +1113,7 @@ extern "C" int lz_autocorrelation(lz_ctx *c, const uint8_t *d_data, size_t n, ui
     if (int rc = diag_begin(c, s, 8 + ((size_t)max_lag + 1) * 8, &ws)) return rc;
     unsigned long long *total = reinterpret_cast<unsigned long long *>(ws);
     unsigned long long *sums = total + 1;
-    if (int rc = lag_sums(c, d_data, n, max_lag, sums, total, s)) return rc;
+    if (int rc = lag_sums(c, d_data, n, max_lag, sums, total, s, true)) return rc;
     hipLaunchKernelGGL(autocorr_norm_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag, sums,
                        total, d_r);
     LZ_HIP(hipGetLastError());
