@@ -42,6 +42,17 @@ extern "C" {
 #define LZ_TAG_BYTES 24
 #define LZ_MAX_PASSWORD 64
 #define LZ_MAX_MESSAGE (1ull << 32)
+/* Block b of a message starts at r0 + b 2^-24 (every coordinate), so a
+ * message may have at most 2^24 blocks: every start then lies within 1 of
+ * r0.  With the default block_len of 256 every message up to 2^32 bytes
+ * fits; a smaller block_len lowers the longest message accordingly. */
+#define LZ_MAX_BLOCKS (1ull << 24)
+/* Largest accepted Euler step.  The paper allows 0 < dt <= 0.027
+ * (Section 3.1), but forward Euler of the Lorenz system leaves the attractor
+ * and overflows from some starts inside the lambda ranges once dt reaches
+ * about 0.02, and from points of the attractor moved by the per-byte
+ * perturbations at 0.024; at 0.015 and below no such escape was found. */
+#define LZ_MAX_DT 0.015
 
 enum {
     LZ_OK = 0,
@@ -68,11 +79,15 @@ enum { LZ_INTEGRATOR_EULER = 0, LZ_INTEGRATOR_EULER_FMA = 1, LZ_INTEGRATOR_RK4 =
 /* Parameters of the method (Section 3.1).
  * Defaults (lz_params_default): dt = 0.01, lambda = (1,1,1), n_it = 3000,
  * block_len = 256, k = (4,4,4), integrator = LZ_INTEGRATOR_EULER.  Valid
- * ranges (else LZ_E_INVAL): 0 < dt <= 0.024 (forward Euler diverges from the
- * attractor above it), each lambda_j inside the paper's range for its
- * coordinate, n_it >= 1, block_len >= 1 (block_len >= n gives the sequential
+ * ranges (else LZ_E_INVAL): 0 < dt <= LZ_MAX_DT = 0.015 (see LZ_MAX_DT),
+ * each lambda_j inside the paper's open range for its coordinate
+ * (-15.67 < lambda_1 < 16.01, -11.28 < lambda_2 < 16.01, 0.090 < lambda_3 <
+ * 62), n_it >= 1, block_len >= 1 (block_len >= n gives the sequential
  * version of Section 5: the whole message is one chain), k_i in {3, 4}
- * (2 < k_i <= floor((xi-14)/8) = 4), integrator one of the values above. */
+ * (2 < k_i <= floor((xi-14)/8) = 4), integrator one of the values above.
+ * sigma = 10, rho = 28 and beta = 8/3 are fixed by Section 3.1 and are not
+ * parameters.  Every entry point that takes a message also rejects one of
+ * more than LZ_MAX_BLOCKS blocks (LZ_E_INVAL), see lz_block_count. */
 typedef struct {
     double dt;
     double lambda[3];
@@ -120,6 +135,12 @@ int lz_params_check(const lz_params *prm);
 
 /* n + LZ_TAG_BYTES. */
 size_t lz_ciphertext_len(size_t n_plain);
+
+/* Number of blocks (independent chains, Section 5) of an n-byte message
+ * under *prm: ceil(n / block_len), 1 for n = 0.  LZ_E_INVAL if prm is
+ * invalid, n > 2^32 or the count exceeds LZ_MAX_BLOCKS; the entry points
+ * that take a message apply the same rule.  Host only. */
+int lz_block_count(const lz_params *prm, uint64_t n, uint64_t *nb);
 
 /* Password stage of Section 3.1 on the host: packing of pi into a = (a1,a2,a3),
  * a' = g(a), r0 = a' + lambda, mu, Omega.  pw: host pointer, 1..64 bytes (any
@@ -186,13 +207,31 @@ int lz_decrypt_key(lz_ctx *ctx, const lz_key *key, const uint8_t *d_C, size_t n_
  * lz_batch_create does key setup for every message, builds and uploads the
  * work list (full blocks first, then partial blocks longest first), and
  * captures [reset, persistent kernel, finalize] into a HIP graph bound to
- * d_in/d_out/d_status; shape NULL = the context's launch shape.  It does not
- * run the batch.  lz_batch_launch replays the graph on stream (asynchronous;
- * may be called many times).  The batch owns its device descriptors. */
+ * d_in/d_out; shape NULL = the context's launch shape.  It does not run the
+ * batch.  d_status may be NULL (a decrypt batch then takes its statuses from
+ * each lz_decrypt_batch call).  The batch owns its device descriptors.
+ * LZ_E_INVAL for a NULL argument, n_msg outside [1, 2^30], a message over
+ * 2^32 bytes or LZ_MAX_BLOCKS blocks, a bad password length or shape. */
 int lz_batch_create(lz_ctx *ctx, int decrypt, size_t n_msg, const uint64_t *lens,
                     const uint64_t *in_off, const uint64_t *out_off, const uint8_t *pw,
                     const uint64_t *pw_off, const uint32_t *pw_len, const uint8_t *d_in,
                     uint8_t *d_out, int32_t *d_status, const lz_launch *shape, lz_batch **out);
+
+/* C_i = E_pi_i(P_i) for every message of the batch at once (Section 1's
+ * problem statement over many messages, each split into the parallel
+ * version's blocks of Section 5): one replay of the batch's graph on stream,
+ * asynchronous, repeatable.  batch must come from lz_batch_create on ctx
+ * with decrypt = 0 (else LZ_E_INVAL). */
+int lz_encrypt_batch(lz_ctx *ctx, const lz_batch *batch, void *stream);
+
+/* P_i = D_pi_i(C_i) for every message of the batch: one replay on stream,
+ * asynchronous.  d_status (device int32, n_msg entries, NOT NULL) receives
+ * LZ_OK or LZ_E_INTEGRITY per message; a failed message's output is zeroed.
+ * batch must come from lz_batch_create on ctx with decrypt = 1. */
+int lz_decrypt_batch(lz_ctx *ctx, const lz_batch *batch, int32_t *d_status, void *stream);
+
+/* Replays the graph with the d_status given at creation (LZ_E_INVAL for a
+ * decrypt batch created without one). */
 int lz_batch_launch(lz_batch *batch, void *stream);
 int lz_batch_destroy(lz_batch *batch);
 

@@ -66,7 +66,7 @@ def lib():
         L.orc_theta.restype = ctypes.c_double
         dp = ctypes.POINTER(ctypes.c_double)
         L.orc_R_many.argtypes = [dp, u8p, ctypes.c_size_t, u8p]
-        L.orc_R_many.restype = None
+        L.orc_R_many.restype = ctypes.c_int
         L.orc_theta_many.argtypes = [u8p, u8p, ctypes.c_size_t, dp]
         L.orc_theta_many.restype = None
         L.orc_lorenz_many.argtypes = [dp, ctypes.c_size_t, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
@@ -86,6 +86,19 @@ def lib():
 
 
 INTEGRATORS = {"euler": 0, "euler_fma": 1, "rk4": 2}
+
+ESCAPED = -4  # the oracle's code for a trajectory that left the domain of R and N
+
+
+class TrajectoryEscaped(ValueError):
+    """A coordinate of the trajectory became non-finite or reached 2^19 in magnitude, where
+    floor(v 10^13) no longer fits a 64-bit integer: R and the tag are undefined there."""
+
+
+def _raise(what: str, rc: int):
+    if rc == ESCAPED:
+        raise TrajectoryEscaped(f"{what}: the trajectory left the attractor")
+    raise ValueError(f"{what} rc={rc}")
 
 
 def params(dt=0.01, n_it=3000, block_len=256, lam=(1.0, 1.0, 1.0), k=(4, 4, 4), integrator="euler") -> Params:
@@ -138,9 +151,11 @@ def R_many(alpha, omega) -> np.ndarray:
     al = np.ascontiguousarray(alpha, dtype=np.float64)
     om = np.ascontiguousarray(omega, dtype=np.uint8)
     out = np.empty(len(al), dtype=np.uint8)
-    lib().orc_R_many(al.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                     om.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), len(al),
-                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    rc = lib().orc_R_many(al.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          om.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), len(al),
+                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    if rc:
+        raise ValueError("R_many: some alpha outside the domain |alpha| < 2^19")
     return out
 
 
@@ -171,7 +186,7 @@ def encrypt(pw: bytes, P, nthreads: int = 1, **kw) -> np.ndarray:
     rc = lib().orc_encrypt(pwp, len(pw), ctypes.byref(prm), pp, len(pa),
                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), nthreads)
     if rc:
-        raise ValueError(f"orc_encrypt rc={rc}")
+        _raise("orc_encrypt", rc)
     return out
 
 
@@ -186,7 +201,7 @@ def decrypt(pw: bytes, C, nthreads: int = 1, **kw):
     rc = lib().orc_decrypt(pwp, len(pw), ctypes.byref(prm), cp, len(ca),
                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), nthreads)
     if rc not in (0, -2):
-        raise ValueError(f"orc_decrypt rc={rc}")
+        _raise("orc_decrypt", rc)
     return out, rc == 0
 
 
@@ -200,5 +215,5 @@ def crypt_block(pw: bytes, b: int, data, decrypt: bool = False, **kw):
     rc = lib().orc_crypt_block(pwp, len(pw), ctypes.byref(prm), b, dp, len(da),
                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(decrypt), d)
     if rc:
-        raise ValueError(f"orc_crypt_block rc={rc}")
+        _raise("orc_crypt_block", rc)
     return out, tuple(d)

@@ -32,6 +32,14 @@
  *   - integrity (Abstract, end of Section 2): the ciphertext carries a
  *     24-byte tag, the XOR over blocks of (N(x),N(y),N(z)) of each block's
  *     final state, N(v) = floor(v 1e13) as a two's complement 64-bit integer.
+ *
+ * Domain.  R and N read floor(v 1e13) as a 64-bit integer, which needs
+ * |v| < 2^63 / 1e13.  Forward Euler leaves the attractor for some steps and
+ * starting points the paper allows (dt near its bound of 0.027, or a start
+ * far outside the lambda ranges); the trajectory then overflows.  The oracle
+ * checks every coordinate after each byte's iterations and at the end of a
+ * block: a coordinate that is not finite or has |v| >= 2^19 stops the
+ * computation with ORC_E_ESCAPED instead of reading an undefined integer.
  */
 #define _POSIX_C_SOURCE 200809L
 #include <math.h>
@@ -70,6 +78,11 @@ static const double SIGMA = 10.0;
 static const double RHO = 28.0;
 static const double BETA = 8.0 / 3.0;
 static const double SCALE_NU = 1e13; /* 10^nu, nu = floor(log10 2^(52-6)) = 13 */
+
+#define ORC_E_ESCAPED (-4) /* a coordinate left the domain of R and N (see the file header) */
+
+/* |v| < 2^19 keeps |v 1e13| < 2^63; false for infinities and NaN */
+static int in_domain(double v) { return fabs(v) < 0x1p19; }
 
 /* ---- little-endian byte bignums for the password integers ---------------- */
 
@@ -290,9 +303,12 @@ void orc_lorenz_integrator(double r[3], double dt, uint64_t steps, uint32_t inte
 
 void orc_lorenz(double r[3], double dt, uint64_t steps) { orc_lorenz_integrator(r, dt, steps, 0); }
 
-/* ---- Eq. R_nu: byte Omega of floor(alpha 10^nu) --------------------------- */
+/* ---- Eq. R_nu: byte Omega of floor(alpha 10^nu) ---------------------------
+ * Returns -1 for alpha outside the domain (never reached from orc_block,
+ * which stops first). */
 
 int orc_R(double alpha, int omega) {
+    if (!in_domain(alpha)) return -1;
     int64_t N = (int64_t)floor(alpha * SCALE_NU);
     return (int)(((uint64_t)N >> (8 * omega)) & 0xFFu);
 }
@@ -307,8 +323,15 @@ double orc_theta(int p, int omega3) {
  * Plain loops over orc_R, orc_theta and orc_lorenz_integrator (the Lorenz
  * states split over nthreads threads); no arithmetic of their own.          */
 
-void orc_R_many(const double *alpha, const uint8_t *omega, size_t n, uint8_t *out) {
-    for (size_t i = 0; i < n; i++) out[i] = (uint8_t)orc_R(alpha[i], omega[i]);
+/* Returns 0, or -1 (out[i] = 0) when some alpha is outside the domain. */
+int orc_R_many(const double *alpha, const uint8_t *omega, size_t n, uint8_t *out) {
+    int rc = 0;
+    for (size_t i = 0; i < n; i++) {
+        int v = orc_R(alpha[i], omega[i]);
+        if (v < 0) rc = -1;
+        out[i] = (uint8_t)(v < 0 ? 0 : v);
+    }
+    return rc;
 }
 
 void orc_theta_many(const uint8_t *p, const uint8_t *omega3, size_t n, double *out) {
@@ -345,17 +368,21 @@ void orc_lorenz_many(double *r, size_t n, double dt, uint64_t steps, uint32_t in
     for (int t = 1; t < nthreads; t++) pthread_join(th[t], NULL);
 }
 
-/* N(v) of the integrity digest */
+/* N(v) of the integrity digest (v in the domain) */
 static uint64_t digest_word(double v) { return (uint64_t)(int64_t)floor(v * SCALE_NU); }
+
+static int state_in_domain(const double r[3]) { return in_domain(r[0]) && in_domain(r[1]) && in_domain(r[2]); }
 
 /* ---- Steps 1-3 of Section 3.2 over one block -------------------------------
  * Block b of the parallel version (Section 5) starts at r0 + b 2^-24.
- * decrypt = 0: in = P bytes, out = C bytes; decrypt = 1: in = C, out = P.   */
-void orc_block(const orc_key *K, const orc_params *prm, uint64_t b, const uint8_t *in,
-               size_t len, uint8_t *out, int decrypt, uint64_t d[3]) {
+ * decrypt = 0: in = P bytes, out = C bytes; decrypt = 1: in = C, out = P.
+ * Returns 0, or ORC_E_ESCAPED when the trajectory leaves the domain.        */
+int orc_block(const orc_key *K, const orc_params *prm, uint64_t b, const uint8_t *in,
+              size_t len, uint8_t *out, int decrypt, uint64_t d[3]) {
     double r[3], alpha[3];
     int mu[3], Om[3];
     for (int j = 0; j < 3; j++) r[j] = K->r0[j] + (double)b * 0x1p-24;
+    if (!state_in_domain(r)) return ORC_E_ESCAPED;
     for (int i = 0; i < 3; i++) { mu[i] = K->mu[i]; Om[i] = K->omega[i]; }
     for (int i = 0; i < 3; i++) alpha[i] = r[mu[i]]; /* Eq. alpha with n = 0 */
 
@@ -376,6 +403,7 @@ void orc_block(const orc_key *K, const orc_params *prm, uint64_t b, const uint8_
         double theta = orc_theta(p, Om[2]);
         r[mu[2]] = r[mu[2]] + theta;
         orc_lorenz_integrator(r, prm->dt, prm->n_it, prm->integrator);
+        if (!state_in_domain(r)) return ORC_E_ESCAPED;
         /* Step 3 */
         int R3 = orc_R(alpha[2], Om[2]);
         int Rold[3] = {R1, R2, R3};
@@ -387,7 +415,9 @@ void orc_block(const orc_key *K, const orc_params *prm, uint64_t b, const uint8_
         }
         for (int j = 0; j < 3; j++) r[j] = r[j] + K->a_prime[j];
     }
+    if (!state_in_domain(r)) return ORC_E_ESCAPED;
     for (int j = 0; j < 3; j++) d[j] = digest_word(r[j]);
+    return 0;
 }
 
 /* ---- whole messages, blocks spread over threads ---------------------------- */
@@ -402,6 +432,7 @@ typedef struct {
     int decrypt;
     uint64_t *digests; /* 3 per block */
     uint64_t next;     /* shared block counter */
+    int rc;            /* first error of a block (under lock) */
     pthread_mutex_t lock;
 } job_t;
 
@@ -414,7 +445,12 @@ static void *worker(void *arg) {
         if (b >= J->nb) break;
         size_t off = (size_t)b * J->prm->block_len;
         size_t len = J->n - off < J->prm->block_len ? J->n - off : J->prm->block_len;
-        orc_block(J->K, J->prm, b, J->in + off, len, J->out + off, J->decrypt, J->digests + 3 * b);
+        int rc = orc_block(J->K, J->prm, b, J->in + off, len, J->out + off, J->decrypt, J->digests + 3 * b);
+        if (rc) {
+            pthread_mutex_lock(&J->lock);
+            if (!J->rc) J->rc = rc;
+            pthread_mutex_unlock(&J->lock);
+        }
     }
     return NULL;
 }
@@ -422,7 +458,7 @@ static void *worker(void *arg) {
 static int run_blocks(const orc_key *K, const orc_params *prm, const uint8_t *in, size_t n,
                       uint8_t *out, int decrypt, int nthreads, uint64_t tag[3]) {
     uint64_t nb = n == 0 ? 1 : (n + prm->block_len - 1) / prm->block_len;
-    job_t J = {K, prm, in, out, n, nb, decrypt, NULL, 0, PTHREAD_MUTEX_INITIALIZER};
+    job_t J = {K, prm, in, out, n, nb, decrypt, NULL, 0, 0, PTHREAD_MUTEX_INITIALIZER};
     J.digests = (uint64_t *)calloc(3 * nb, sizeof(uint64_t));
     if (!J.digests) return -3;
     if (nthreads < 1) nthreads = 1;
@@ -432,6 +468,10 @@ static int run_blocks(const orc_key *K, const orc_params *prm, const uint8_t *in
     worker(&J);
     for (int t = 1; t < nthreads; t++) pthread_join(th[t], NULL);
     free(th);
+    if (J.rc) {
+        free(J.digests);
+        return J.rc;
+    }
     tag[0] = tag[1] = tag[2] = 0;
     for (uint64_t b = 0; b < nb; b++)
         for (int j = 0; j < 3; j++) tag[j] ^= J.digests[3 * b + j];
@@ -446,7 +486,8 @@ static int check_params(const orc_params *prm) {
     return 0;
 }
 
-/* C = E(P) || LE64(T1) || LE64(T2) || LE64(T3); C has n + 24 bytes. */
+/* C = E(P) || LE64(T1) || LE64(T2) || LE64(T3); C has n + 24 bytes.
+ * Returns 0, -1 (bad argument) or ORC_E_ESCAPED (C then undefined).        */
 int orc_encrypt(const uint8_t *pw, size_t n_pw, const orc_params *prm, const uint8_t *P,
                 size_t n, uint8_t *C, int nthreads) {
     if (check_params(prm) || (!P && n) || !C) return -1;
@@ -460,7 +501,8 @@ int orc_encrypt(const uint8_t *pw, size_t n_pw, const orc_params *prm, const uin
     return 0;
 }
 
-/* Returns 0 and P (n_c - 24 bytes), or -2 with P zeroed when the tag fails. */
+/* Returns 0 and P (n_c - 24 bytes), -2 with P zeroed when the tag fails,
+ * -1 for a bad argument, or ORC_E_ESCAPED (P then zeroed).                   */
 int orc_decrypt(const uint8_t *pw, size_t n_pw, const orc_params *prm, const uint8_t *C,
                 size_t n_c, uint8_t *P, int nthreads) {
     if (check_params(prm) || !C || n_c < 24 || (!P && n_c > 24)) return -1;
@@ -469,7 +511,10 @@ int orc_decrypt(const uint8_t *pw, size_t n_pw, const orc_params *prm, const uin
     size_t n = n_c - 24;
     uint64_t tag[3];
     int rc = run_blocks(&K, prm, C, n, P, 1, nthreads, tag);
-    if (rc) return rc;
+    if (rc) {
+        if (n) memset(P, 0, n);
+        return rc;
+    }
     int ok = 1;
     for (int j = 0; j < 3; j++) {
         uint64_t stored = 0;
@@ -489,6 +534,5 @@ int orc_crypt_block(const uint8_t *pw, size_t n_pw, const orc_params *prm, uint6
     if (check_params(prm) || len > prm->block_len) return -1;
     orc_key K;
     if (orc_key_setup(pw, n_pw, prm, &K, NULL)) return -1;
-    orc_block(&K, prm, b, in, len, out, decrypt, d);
-    return 0;
+    return orc_block(&K, prm, b, in, len, out, decrypt, d);
 }

@@ -56,6 +56,7 @@ SIGNATURES = {
     "lz_params_default": (ctypes.c_int, [ctypes.POINTER(Params)]),
     "lz_params_check": (ctypes.c_int, [ctypes.POINTER(Params)]),
     "lz_ciphertext_len": (ctypes.c_size_t, [ctypes.c_size_t]),
+    "lz_block_count": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
     "lz_key_setup": (ctypes.c_int, [u8p, ctypes.c_size_t, ctypes.POINTER(Params), ctypes.POINTER(Key)]),
     "lz_last_error": (ctypes.c_char_p, []),
     "lz_context_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Params), ctypes.POINTER(vp)]),
@@ -72,6 +73,8 @@ SIGNATURES = {
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32), vp, vp, vp,
                                        ctypes.POINTER(Launch), ctypes.POINTER(vp)]),
     "lz_batch_launch": (ctypes.c_int, [vp, vp]),
+    "lz_encrypt_batch": (ctypes.c_int, [vp, vp, vp]),
+    "lz_decrypt_batch": (ctypes.c_int, [vp, vp, vp, vp]),
     "lz_batch_destroy": (ctypes.c_int, [vp]),
     "lz_autotune": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(Launch)]),
     "lz_server_create": (ctypes.c_int, [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),

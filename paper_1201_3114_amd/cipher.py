@@ -180,8 +180,23 @@ class Batch:
                                     ctypes.c_void_p(d_in.data_ptr()), ctypes.c_void_p(d_out.data_ptr()), st,
                                     ctypes.byref(l) if l is not None else None, ctypes.byref(self._h)))
 
+        self.decrypt_batch = bool(decrypt)
+
     def launch(self, stream=None):
+        """Replays the batch with the statuses given at creation (lz_batch_launch)."""
         check(B.lib.lz_batch_launch(self._h, _stream(stream, self.ctx.device)))
+
+    def encrypt(self, stream=None):
+        """lz_encrypt_batch: every message of an encrypt batch, one replay."""
+        check(B.lib.lz_encrypt_batch(self.ctx.handle, self._h, _stream(stream, self.ctx.device)))
+
+    def decrypt(self, d_status: torch.Tensor, stream=None):
+        """lz_decrypt_batch: every message of a decrypt batch, statuses into d_status (int32, n)."""
+        if d_status.dtype != torch.int32 or not d_status.is_cuda or d_status.numel() < self.n:
+            raise ValueError("d_status must be an int32 GPU tensor with one entry per message")
+        self._status = d_status
+        check(B.lib.lz_decrypt_batch(self.ctx.handle, self._h, ctypes.c_void_p(d_status.data_ptr()),
+                                     _stream(stream, self.ctx.device)))
 
     def close(self):
         if self._h:

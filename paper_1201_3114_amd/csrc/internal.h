@@ -25,6 +25,8 @@ int hip_fail(hipError_t e, const char *what);
 void sha256(const uint8_t *msg, size_t len, uint8_t out[32]);
 int key_setup(const uint8_t *pw, size_t n, const lz_params &prm, lz_key &key);
 int check_params(const lz_params &prm);
+// n <= 2^32 and at most LZ_MAX_BLOCKS blocks of prm.block_len; *nb (may be NULL) = block count
+int check_blocks(const lz_params &prm, uint64_t n, uint64_t *nb);
 
 // ---- device-side descriptors -----------------------------------------------------
 
@@ -118,11 +120,13 @@ struct BatchDev {
     uint64_t n_tasks;
     unsigned long long *tag_acc;  // 3 per message
     unsigned long long *counter;  // work-queue head
-    int32_t *status;              // decrypt: per message
+    int32_t *const *status_ref;   // decrypt: device slot holding the address of the per-message statuses
 };
 hipError_t launch_batch(const KernelShape &sh, const DevInfo &dev, const lz_params &prm, const BatchDev &b,
                         hipStream_t s);
 hipError_t launch_batch_finalize(const BatchDev &b, int decrypt, hipStream_t s);
+// One-thread kernel: *slot = status (ordered on s before a batch replay that reads the slot).
+hipError_t launch_set_status_ref(int32_t **slot, int32_t *status, hipStream_t s);
 
 // Served path: advance the listed chains by up to tick_bytes bytes each.
 struct TickDev {

@@ -441,6 +441,9 @@ __global__ void plain_finalize_kernel(int decrypt, const unsigned long long *tag
         for (uint64_t i = tid; i < n; i += (uint64_t)gridDim.x * blockDim.x) body[i] = 0;
 }
 
+// Stores the address of a batch's status array in its slot (read by batch_finalize_kernel).
+__global__ void set_status_ref_kernel(int32_t **slot, int32_t *status) { *slot = status; }
+
 __global__ void fill_u64_kernel(unsigned long long *p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = 0;
@@ -553,7 +556,7 @@ __global__ void batch_finalize_kernel(BatchDev b, int decrypt) {
     const uint8_t *stored = md.in + md.n;
     bool ok = true;
     for (int q = 0; q < LZ_TAG_BYTES; ++q) ok = ok && stored[q] == (uint8_t)(t[q / 8] >> (8 * (q % 8)));
-    if (threadIdx.x == 0) b.status[i] = ok ? LZ_OK : LZ_E_INTEGRITY;
+    if (threadIdx.x == 0) (*b.status_ref)[i] = ok ? LZ_OK : LZ_E_INTEGRITY;
     if (!ok)
         for (uint64_t j = threadIdx.x; j < md.n; j += blockDim.x) md.out[j] = 0;
 }
@@ -865,6 +868,11 @@ hipError_t launch_batch(const KernelShape &sh, const DevInfo &dev, const lz_para
         hipLaunchKernelGGL((batch_kernel<M, I>), dim3((unsigned)grid), dim3(sh.wg), lds, s, a);
         return hipGetLastError();
     });
+}
+
+hipError_t launch_set_status_ref(int32_t **slot, int32_t *status, hipStream_t s) {
+    hipLaunchKernelGGL(set_status_ref_kernel, dim3(1), dim3(1), 0, s, slot, status);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_finalize(const BatchDev &b, int decrypt, hipStream_t s) {

@@ -33,8 +33,9 @@ int hip_fail(hipError_t e, const char *what) {
 }
 
 int check_params(const lz_params &p) {
-    // 0 < dt <= 0.024: forward Euler from the attractor overflows for dt >= 0.025
-    if (!(p.dt > 0.0 && p.dt <= 0.024)) return fail(LZ_E_INVAL, "dt must be in (0, 0.024]");
+    // 0 < dt <= 0.015: above about 0.02 some starts inside the lambda ranges, and some points of the
+    // attractor moved by the per-byte perturbations, leave the attractor under forward Euler and overflow
+    if (!(p.dt > 0.0 && p.dt <= LZ_MAX_DT)) return fail(LZ_E_INVAL, "dt must be in (0, 0.015]");
     // lambda inside the ranges of Section 3.1 (stable chaotic phases)
     if (!(p.lambda[0] > -15.67 && p.lambda[0] < 16.01) || !(p.lambda[1] > -11.28 && p.lambda[1] < 16.01) ||
         !(p.lambda[2] > 0.090 && p.lambda[2] < 62.0))
@@ -46,6 +47,15 @@ int check_params(const lz_params &p) {
         if (p.k[i] != 3 && p.k[i] != 4) return fail(LZ_E_INVAL, "k_i must be 3 or 4");
     for (uint8_t r : p.reserved)
         if (r) return fail(LZ_E_INVAL, "reserved bytes of lz_params must be zero");
+    return LZ_OK;
+}
+
+int check_blocks(const lz_params &p, uint64_t n, uint64_t *nb_out) {
+    if (n > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+    const uint64_t nb = n == 0 ? 1 : (n + p.block_len - 1) / p.block_len;
+    // block b starts at r0 + b 2^-24: at most 2^24 blocks keep every start within 1 of r0
+    if (nb > LZ_MAX_BLOCKS) return fail(LZ_E_INVAL, "message of more than 2^24 blocks (raise block_len)");
+    if (nb_out) *nb_out = nb;
     return LZ_OK;
 }
 
@@ -102,6 +112,12 @@ extern "C" int lz_params_check(const lz_params *prm) {
 }
 
 extern "C" size_t lz_ciphertext_len(size_t n_plain) { return n_plain + LZ_TAG_BYTES; }
+
+extern "C" int lz_block_count(const lz_params *prm, uint64_t n, uint64_t *nb) {
+    if (!prm || !nb) return fail(LZ_E_INVAL, "NULL argument");
+    if (int rc = check_params(*prm)) return rc;
+    return check_blocks(*prm, n, nb);
+}
 
 extern "C" int lz_key_setup(const uint8_t *pw, size_t n_pw, const lz_params *prm, lz_key *out) {
     if (!pw || !out) return fail(LZ_E_INVAL, "NULL argument");
@@ -206,7 +222,7 @@ extern "C" int lz_context_get_launch(const lz_ctx *c, lz_launch *out) {
 extern "C" int lz_encrypt_key(lz_ctx *c, const lz_key *key, const uint8_t *d_P, size_t n, uint8_t *d_C,
                               void *stream) {
     if (!c || !key || !d_C || (!d_P && n)) return fail(LZ_E_INVAL, "NULL argument");
-    if (n > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+    if (int rc = check_blocks(c->prm, n, nullptr)) return rc;
     hipStream_t s = (hipStream_t)stream;
     LZ_HIP(hipSetDevice(c->device));
     if (int rc = order_after(s, c->last_stream, c->last_event, c->has_last)) return rc;
@@ -221,7 +237,7 @@ extern "C" int lz_decrypt_key(lz_ctx *c, const lz_key *key, const uint8_t *d_C, 
     if (!c || !key || !d_C) return fail(LZ_E_INVAL, "NULL argument");
     if (n_c < LZ_TAG_BYTES) return fail(LZ_E_INVAL, "ciphertext shorter than the 24-byte tag");
     const size_t n = n_c - LZ_TAG_BYTES;
-    if (n > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+    if (int rc = check_blocks(c->prm, n, nullptr)) return rc;
     if (!d_P && n) return fail(LZ_E_INVAL, "NULL plaintext buffer");
     hipStream_t s = (hipStream_t)stream;
     LZ_HIP(hipSetDevice(c->device));
@@ -261,12 +277,15 @@ struct lz_batch {
     int decrypt;
     KernelShape shape;
     BatchDev dev;
-    void *dmem;          // one device allocation holding every descriptor array
+    void *dmem;           // one device allocation holding every descriptor array
+    int32_t **status_slot;  // in dmem: the address of the statuses the next replay writes (decrypt)
+    int32_t *bound_status;  // statuses given at creation (lz_batch_launch), may be NULL
     hipGraph_t graph;
     hipGraphExec_t exec;
-    hipEvent_t last_event;
-    hipStream_t last_stream;
-    bool has_last;
+    // replay ordering across streams; a replay changes only these, so calls take a const batch
+    mutable hipEvent_t last_event;
+    mutable hipStream_t last_stream;
+    mutable bool has_last;
 };
 
 namespace {
@@ -295,7 +314,6 @@ extern "C" int lz_batch_create(lz_ctx *c, int decrypt, size_t n_msg, const uint6
     *out = nullptr;
     if (!c || !lens || !in_off || !out_off || !pw || !pw_off || !pw_len || !d_in || !d_out)
         return fail(LZ_E_INVAL, "NULL argument");
-    if (decrypt && !d_status) return fail(LZ_E_INVAL, "decrypt batch needs d_status");
     if (n_msg == 0 || n_msg > (1u << 30)) return fail(LZ_E_INVAL, "n_msg must be in [1, 2^30]");
     KernelShape sh = shape ? to_shape(*shape) : c->shape;
     if (!shape_valid(sh, c->dev)) return fail(LZ_E_INVAL, "launch shape out of range or over the LDS limit");
@@ -306,8 +324,7 @@ extern "C" int lz_batch_create(lz_ctx *c, int decrypt, size_t n_msg, const uint6
     std::vector<uint64_t> prefix(n_msg + 1, 0);
     std::vector<uint32_t> tails;
     for (size_t i = 0; i < n_msg; ++i) {
-        if (lens[i] > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
-        if ((lens[i] + B - 1) / B > 0xFFFFFFFFull) return fail(LZ_E_INVAL, "message has 2^32 blocks or more");
+        if (int rc = check_blocks(c->prm, lens[i], nullptr)) return rc;
         lz_key key;
         if (int rc = lz_key_setup(pw + pw_off[i], pw_len[i], &c->prm, &key)) return rc;
         MsgDesc &m = md[i];
@@ -339,7 +356,8 @@ extern "C" int lz_batch_create(lz_ctx *c, int decrypt, size_t n_msg, const uint6
     const size_t o_msgs = 0;
     const size_t o_prefix = align_up(o_msgs + n_msg * sizeof(MsgDesc), 256);
     const size_t o_tail = align_up(o_prefix + (n_msg + 1) * sizeof(uint64_t), 256);
-    const size_t o_tag = align_up(o_tail + std::max<size_t>(tails.size(), 1) * sizeof(uint32_t), 256);
+    const size_t o_slot = align_up(o_tail + std::max<size_t>(tails.size(), 1) * sizeof(uint32_t), 256);
+    const size_t o_tag = o_slot + 256;
     const size_t total = o_tag + (3 * n_msg + 1) * sizeof(unsigned long long);
     hipError_t e = hipMalloc(&b->dmem, total);
     if (e != hipSuccess) {
@@ -352,6 +370,9 @@ extern "C" int lz_batch_create(lz_ctx *c, int decrypt, size_t n_msg, const uint6
         e = hipMemcpy(base + o_prefix, prefix.data(), (n_msg + 1) * sizeof(uint64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess && !tails.empty())
         e = hipMemcpy(base + o_tail, tails.data(), tails.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    b->status_slot = reinterpret_cast<int32_t **>(base + o_slot);
+    b->bound_status = decrypt ? d_status : nullptr;
+    if (e == hipSuccess) e = hipMemcpy(b->status_slot, &b->bound_status, sizeof(int32_t *), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         batch_free(b);
         return hip_fail(e, "hipMemcpy(batch descriptors)");
@@ -367,7 +388,7 @@ extern "C" int lz_batch_create(lz_ctx *c, int decrypt, size_t n_msg, const uint6
     d.n_tasks = (d.n_full + d.n_tail + per_task - 1) / per_task;
     d.tag_acc = reinterpret_cast<unsigned long long *>(base + o_tag);
     d.counter = d.tag_acc + 3 * n_msg;
-    d.status = d_status;
+    d.status_ref = b->status_slot;
 
     // capture [reset, persistent kernel, finalize]
     hipStream_t cap;
@@ -395,13 +416,38 @@ extern "C" int lz_batch_create(lz_ctx *c, int decrypt, size_t n_msg, const uint6
     return LZ_OK;
 }
 
-extern "C" int lz_batch_launch(lz_batch *b, void *stream) {
-    if (!b) return fail(LZ_E_INVAL, "batch is NULL");
-    hipStream_t s = (hipStream_t)stream;
+namespace {
+
+// One replay of the batch graph on stream; for a decrypt batch the statuses go to d_status.
+int batch_replay(const lz_batch *b, int32_t *d_status, hipStream_t s) {
     LZ_HIP(hipSetDevice(b->ctx->device));
     if (int rc = order_after(s, b->last_stream, b->last_event, b->has_last)) return rc;
+    if (b->decrypt) LZ_HIP(launch_set_status_ref(b->status_slot, d_status, s));
     LZ_HIP(hipGraphLaunch(b->exec, s));
     return record(s, b->last_stream, b->last_event, b->has_last);
+}
+
+}  // namespace
+
+extern "C" int lz_encrypt_batch(lz_ctx *c, const lz_batch *b, void *stream) {
+    if (!c || !b) return fail(LZ_E_INVAL, "NULL argument");
+    if (b->ctx != c) return fail(LZ_E_INVAL, "batch belongs to another context");
+    if (b->decrypt) return fail(LZ_E_INVAL, "batch was created for decryption");
+    return batch_replay(b, nullptr, (hipStream_t)stream);
+}
+
+extern "C" int lz_decrypt_batch(lz_ctx *c, const lz_batch *b, int32_t *d_status, void *stream) {
+    if (!c || !b || !d_status) return fail(LZ_E_INVAL, "NULL argument");
+    if (b->ctx != c) return fail(LZ_E_INVAL, "batch belongs to another context");
+    if (!b->decrypt) return fail(LZ_E_INVAL, "batch was created for encryption");
+    return batch_replay(b, d_status, (hipStream_t)stream);
+}
+
+extern "C" int lz_batch_launch(lz_batch *b, void *stream) {
+    if (!b) return fail(LZ_E_INVAL, "batch is NULL");
+    if (b->decrypt && !b->bound_status)
+        return fail(LZ_E_INVAL, "decrypt batch created without d_status: use lz_decrypt_batch");
+    return batch_replay(b, b->bound_status, (hipStream_t)stream);
 }
 
 extern "C" int lz_batch_destroy(lz_batch *b) { return batch_free(b); }

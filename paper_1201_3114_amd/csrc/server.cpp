@@ -254,9 +254,10 @@ void admit(lz_server *s, std::vector<Request *> &admitted) {
         r->ticks_tail = tail == 0 ? 1 : (uint32_t)((tail + T - 1) / T);
         r->ticks_run = 0;
         admitted.push_back(r);
-        s->stats.admitted++;
     }
     const uint64_t inuse = s->arena.used() + s->hbm_fixed;
+    std::lock_guard<std::mutex> g(s->mu);  // stats are read by lz_server_stats_get on other threads
+    s->stats.admitted += admitted.size();
     if (inuse > s->stats.peak_hbm) s->stats.peak_hbm = inuse;
 }
 
@@ -271,9 +272,13 @@ int complete_tick(lz_server *s, TickSlot &t) {
     hipStream_t cs = s->copy_stream;
     LZ_HIP(hipEventSynchronize(t.ev_end));
     float ms = 0;
-    if (hipEventElapsedTime(&ms, t.ev_start, t.ev_end) == hipSuccess) s->stats.busy_ms += ms;
-    s->stats.ticks++;
-    s->stats.chain_bytes += t.bytes;
+    const bool timed = hipEventElapsedTime(&ms, t.ev_start, t.ev_end) == hipSuccess;
+    {
+        std::lock_guard<std::mutex> g(s->mu);  // stats are read by lz_server_stats_get on other threads
+        if (timed) s->stats.busy_ms += ms;
+        s->stats.ticks++;
+        s->stats.chain_bytes += t.bytes;
+    }
     t.in_flight = false;
     s->done_seq = t.seq;
     LZ_HIP(hipMemcpyAsync(t.h_done, t.d_done, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, cs));
@@ -656,7 +661,7 @@ extern "C" int lz_server_create(lz_ctx *c, const lz_server_config *cfg, lz_serve
 extern "C" int lz_server_submit(lz_server *s, uint64_t id, int decrypt, const uint8_t *pw, size_t n_pw,
                                 const void *src, uint64_t n, void *dst, uint64_t arrival_ns) {
     if (!s || !pw) return fail(LZ_E_INVAL, "NULL argument");
-    if (n > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+    if (int rc = check_blocks(s->ctx->prm, n, nullptr)) return rc;
     const uint64_t nin = decrypt ? n + LZ_TAG_BYTES : n, nout = decrypt ? n : n + LZ_TAG_BYTES;
     if ((nin && !src) || (nout && !dst)) return fail(LZ_E_INVAL, "NULL buffer");
     Request *r = new (std::nothrow) Request();
@@ -700,9 +705,9 @@ extern "C" int lz_server_submit_many(lz_server *s, size_t count, const uint64_t 
     const uint64_t now = lz_now_ns();
     for (size_t i = 0; i < count; ++i) {
         const int dec = decrypt[i] ? 1 : 0;
-        if (n[i] > LZ_MAX_MESSAGE) {
+        if (int rc = check_blocks(s->ctx->prm, n[i], nullptr)) {
             drop();
-            return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+            return rc;
         }
         const uint64_t nin = dec ? n[i] + LZ_TAG_BYTES : n[i], nout = dec ? n[i] : n[i] + LZ_TAG_BYTES;
         if ((nin && !src[i]) || (nout && !dst[i])) {

@@ -99,8 +99,9 @@ extern "C" int lz_stream_update(lz_stream *st, const uint8_t *d_in, size_t n, ui
     if (st->finished) return fail(LZ_E_INVAL, "stream already finished");
     if (n == 0) return LZ_OK;
     if (!d_in || !d_out) return fail(LZ_E_INVAL, "NULL buffer");
-    if (st->pos + n > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
     lz_ctx *c = st->ctx;
+    if (n > LZ_MAX_MESSAGE || st->pos + n > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+    if (int rc = check_blocks(c->prm, st->pos + n, nullptr)) return rc;
     hipStream_t s = (hipStream_t)stream;
     LZ_HIP(hipSetDevice(c->device));
     if (int rc = stream_order(st, s)) return rc;

@@ -48,7 +48,8 @@ def test_params_default_and_check(B):
     assert B.lib.lz_params_default(ctypes.byref(p)) == 0
     assert (p.dt, p.n_it, p.block_len, list(p.k), list(p.lam)) == (0.01, 3000, 256, [4, 4, 4], [1.0, 1.0, 1.0])
     assert B.lib.lz_params_check(ctypes.byref(p)) == 0
-    for field, bad in [("dt", 0.0), ("dt", 0.025), ("dt", -1.0), ("n_it", 0), ("block_len", 0), ("integrator", 3)]:
+    for field, bad in [("dt", 0.0), ("dt", 0.0150000001), ("dt", 0.024), ("dt", -1.0), ("dt", float("nan")),
+                       ("n_it", 0), ("block_len", 0), ("integrator", 3)]:
         q = B.Params()
         B.lib.lz_params_default(ctypes.byref(q))
         setattr(q, field, bad)
@@ -59,7 +60,7 @@ def test_params_default_and_check(B):
         B.lib.lz_params_default(ctypes.byref(q))
         q.k[1] = k
         assert B.lib.lz_params_check(ctypes.byref(q)) == B.LZ_E_INVAL
-    for ok_field, ok in [("block_len", (1 << 32) - 1), ("integrator", 1), ("integrator", 2)]:
+    for ok_field, ok in [("block_len", (1 << 32) - 1), ("integrator", 1), ("integrator", 2), ("dt", 0.015)]:
         q = B.Params()
         B.lib.lz_params_default(ctypes.byref(q))
         setattr(q, ok_field, ok)
@@ -70,6 +71,30 @@ def test_params_default_and_check(B):
     assert B.lib.lz_params_check(ctypes.byref(q)) == B.LZ_E_INVAL
     assert B.lib.lz_params_check(None) == B.LZ_E_INVAL
     assert B.lib.lz_ciphertext_len(1000) == 1024
+
+
+def test_block_count_limits(B):
+    """Block b starts at r0 + b 2^-24: at most 2^24 blocks per message, and at most 2^32 bytes."""
+    def count(n, block_len=256):
+        p = B.Params()
+        B.lib.lz_params_default(ctypes.byref(p))
+        p.block_len = block_len
+        nb = ctypes.c_uint64(0)
+        rc = B.lib.lz_block_count(ctypes.byref(p), n, ctypes.byref(nb))
+        return rc, nb.value
+
+    assert count(0) == (0, 1)
+    assert count(1) == (0, 1)
+    assert count(257) == (0, 2)
+    assert count(1 << 32) == (0, 1 << 24)
+    assert count((1 << 32) + 1)[0] == B.LZ_E_INVAL
+    assert count((1 << 32), 255)[0] == B.LZ_E_INVAL
+    assert count(1 << 24, 1) == (0, 1 << 24)
+    assert count((1 << 24) + 1, 1)[0] == B.LZ_E_INVAL
+    assert count(3 << 24, 3) == (0, 1 << 24)
+    assert count((3 << 24) + 1, 3)[0] == B.LZ_E_INVAL
+    assert b"2^24" in B.lib.lz_last_error()
+    assert B.lib.lz_block_count(None, 5, None) == B.LZ_E_INVAL
 
 
 def _lib_key(B, pw, k=(4, 4, 4)):
@@ -123,6 +148,8 @@ def test_null_handles_rejected_without_gpu(B):
     assert B.lib.lz_encrypt(None, None, 0, None, 0, None, None) == B.LZ_E_INVAL
     assert B.lib.lz_decrypt(None, None, 0, None, 0, None, None, None) == B.LZ_E_INVAL
     assert B.lib.lz_batch_launch(None, None) == B.LZ_E_INVAL
+    assert B.lib.lz_encrypt_batch(None, None, None) == B.LZ_E_INVAL
+    assert B.lib.lz_decrypt_batch(None, None, None, None) == B.LZ_E_INVAL
     assert B.lib.lz_server_submit(None, 0, 0, None, 0, None, 0, None, 0) == B.LZ_E_INVAL
     assert B.lib.lz_context_destroy(None) == 0
     assert B.lib.lz_batch_destroy(None) == 0
@@ -167,6 +194,13 @@ int main(void) {
     if (lz_key_setup((const uint8_t *)"123456", 6, &p, &k) != LZ_OK) return 3;
     if (k.mu[0] != 0 || k.mu[1] != 2 || k.mu[2] != 2) return 4;
     if (lz_key_setup((const uint8_t *)"", 0, &p, &k) != LZ_E_INVAL || strlen(lz_last_error()) == 0) return 5;
+    uint64_t nb = 0;
+    if (lz_block_count(&p, LZ_MAX_MESSAGE, &nb) != LZ_OK || nb != LZ_MAX_BLOCKS) return 6;
+    /* the batch calls of the problem statement, over a batch handle; no GPU here, so NULL handles */
+    if (lz_encrypt_batch(NULL, NULL, NULL) != LZ_E_INVAL) return 7;
+    if (lz_decrypt_batch(NULL, NULL, NULL, NULL) != LZ_E_INVAL) return 8;
+    p.dt = LZ_MAX_DT * 1.0000001;
+    if (lz_params_check(&p) != LZ_E_INVAL) return 9;
     printf("ok\n");
     return 0;
 }

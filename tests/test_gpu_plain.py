@@ -73,7 +73,7 @@ def test_launch_shapes_identical(lz, m, wg, tile):
 
 
 @pytest.mark.parametrize("kw", [dict(block_len=1), dict(block_len=3), dict(block_len=64), dict(block_len=1000),
-                                dict(k=(3, 3, 3)), dict(k=(4, 3, 4)), dict(dt=0.024), dict(dt=0.001),
+                                dict(k=(3, 3, 3)), dict(k=(4, 3, 4)), dict(dt=0.015), dict(dt=0.001),
                                 dict(lam=(-15.0, 15.9, 61.5)), dict(n_it=1), dict(n_it=7)])
 def test_parameters_vs_oracle(lz, kw):
     rng = np.random.default_rng(11)
@@ -285,3 +285,46 @@ def test_maximum_message_size(lz):
     assert rc == -1
     del dP, C, Q
     torch.cuda.empty_cache()
+
+
+def test_block_limit_rejected_on_every_path(lz):
+    """A message of more than 2^24 blocks (block b starts at r0 + b 2^-24, so its start would lie 1 or more
+    away from r0) is rejected on the host by the plain, batched, streamed and served paths; 2^24 blocks are
+    accepted.  Buffers of the full size are passed, so the calls touch only memory they own."""
+    import ctypes
+
+    import torch
+
+    from paper_1201_3114_amd import binding as B
+
+    n_ok, n_bad = 1 << 24, (1 << 24) + 1
+    ctx = _ctx(lz, block_len=1, n_it=1)
+    dP = torch.zeros(n_bad, dtype=torch.uint8, device="cuda")
+    dC = torch.zeros(n_bad + 24, dtype=torch.uint8, device="cuda")
+    pbuf, npw = B.pw_buf(b"limit")
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+    say("block limit: plain")
+    assert B.lib.lz_encrypt(ctx.handle, pbuf, npw, vp(dP), n_bad, vp(dC), None) == -1
+    assert b"2^24" in B.lib.lz_last_error()
+    assert B.lib.lz_decrypt(ctx.handle, pbuf, npw, vp(dC), n_bad + 24, vp(dP), None, None) == -1
+    say("block limit: batch")
+    with pytest.raises(lz.LorenzError):
+        lz.Batch(ctx, False, [n_bad], [b"limit"], dP, [0], dC, [0])
+    say("block limit: stream")
+    st = lz.Stream(ctx, False, b"limit")
+    st.update(dP[:n_ok], dC[:n_ok])
+    with pytest.raises(lz.LorenzError):
+        st.update(dP[:1], dC[:1])
+    st.finish()
+    st.close()
+    say("block limit: server")
+    srv = lz.Server(ctx, 1 << 30)
+    with pytest.raises(lz.LorenzError):
+        srv.submit(1, False, b"limit", dP.data_ptr(), n_bad, dC.data_ptr())
+    srv.close()
+    say("block limit: 2^24 blocks accepted")
+    ctx.encrypt(dP[:n_ok], b"limit", out=dC[:n_ok + 24])
+    torch.cuda.synchronize()
+    Q = ctx.decrypt(dC[:n_ok + 24], b"limit")
+    assert torch.equal(Q, dP[:n_ok])
+    ctx.close()

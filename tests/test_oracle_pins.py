@@ -163,6 +163,58 @@ def test_dt_bound_reading():
     assert all(abs(v) < 100 for v in r)
 
 
+def test_escape_inside_the_paper_ranges_is_reported():
+    """At dt = 0.024 a start inside the lambda ranges of Section 3.1 leaves the attractor and overflows; the
+    oracle reports it (floor(v 10^13) is then no 64-bit integer) instead of producing bytes.  The same holds
+    for a block index whose start r0 + b 2^-24 lies 64 away from r0."""
+    r = oracle.lorenz([0.0, 16.0, 0.091], 0.024, 3000)
+    assert not all(math.isfinite(v) for v in r)
+    P = np.zeros(64, np.uint8)
+    with pytest.raises(oracle.TrajectoryEscaped):
+        oracle.encrypt(b"123456", P, dt=0.024, lam=(0.0, 16.0, 0.091), n_it=3000)
+    with pytest.raises(oracle.TrajectoryEscaped):
+        oracle.crypt_block(b"123456", 64 << 24, P, n_it=3000)
+    C = oracle.encrypt(b"123456", P, n_it=3000)
+    Q, ok = oracle.decrypt(b"123456", C, n_it=3000)
+    assert ok and not Q.any()
+    with pytest.raises(oracle.TrajectoryEscaped):
+        oracle.decrypt(b"123456", C, dt=0.024, lam=(0.0, 16.0, 0.091), n_it=3000)
+
+
+@pytest.mark.parametrize("integrator", ["euler", "euler_fma", "rk4"])
+def test_largest_accepted_dt_stays_on_the_attractor(integrator):
+    """dt = 0.015 (the largest the library accepts): starts on a 5 x 5 x 5 grid over the closure of the lambda
+    ranges shifted by a' and the block offset (each in [0, 1]) stay bounded for 2 x 10^5 steps, and so do
+    points of the attractor moved by up to 1.5 in every coordinate (Theta <= 0.255 plus a' < 1 per byte)."""
+    lo = np.array([-15.67, -11.28, 0.090])
+    hi = np.array([16.01, 16.01, 62.0]) + 2.0
+    g = [np.linspace(lo[j], hi[j], 5) for j in range(3)]
+    starts = np.array(np.meshgrid(*g, indexing="ij")).reshape(3, -1).T
+    end = oracle.lorenz_many(starts, 0.015, 200_000, integrator, nthreads=8)
+    assert np.all(np.abs(end) < 100), starts[np.any(~(np.abs(end) < 100), axis=1)][:3]
+    path = [oracle.lorenz([1.0, 1.0, 1.0], 0.015, 5000, integrator)]
+    for _ in range(63):
+        path.append(oracle.lorenz(path[-1], 0.015, 97, integrator))
+    corners = np.array([[sx, sy, sz] for sx in (-1.5, 1.5) for sy in (-1.5, 1.5) for sz in (-1.5, 1.5)])
+    moved = (np.array(path)[:, None, :] + corners[None, :, :]).reshape(-1, 3)
+    end = oracle.lorenz_many(moved, 0.015, 20_000, integrator, nthreads=8)
+    assert np.all(np.abs(end) < 100)
+
+
+def test_cipher_at_the_corners_of_the_parameter_domain():
+    """The whole cipher at dt = 0.015 with lambda near each corner of its ranges, on the first block and on the
+    last block a message may have (2^24 - 1), runs without leaving the attractor and round-trips."""
+    rng = np.random.default_rng(40)
+    P = rng.integers(0, 256, 600, dtype=np.uint8)
+    for lam in [(-15.66, -11.27, 0.0901), (16.0, 16.0, 61.99), (-15.66, 16.0, 0.0901), (16.0, -11.27, 61.99)]:
+        kw = dict(dt=0.015, lam=lam, n_it=3000)
+        C = oracle.encrypt(b"corner", P, nthreads=4, block_len=600, **kw)
+        Q, ok = oracle.decrypt(b"corner", C, nthreads=4, block_len=600, **kw)
+        assert ok and np.array_equal(Q, P)
+        out, _ = oracle.crypt_block(b"corner", (1 << 24) - 1, P[:256], **kw)
+        assert len(out) == 256
+
+
 def test_literal_printed_map_is_degenerate():
     """Reading of the garbled Euler equations: taken literally they contract to the origin."""
     x, y, z, s, rho, b, dt = 1.5, 1.2, 1.3, 10.0, 28.0, 8.0 / 3.0, 0.01
