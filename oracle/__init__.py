@@ -81,6 +81,10 @@ def lib():
         L.orc_crypt_block.argtypes = [u8p, ctypes.c_size_t, ctypes.POINTER(Params), ctypes.c_uint64, u8p,
                                       ctypes.c_size_t, u8p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
         L.orc_crypt_block.restype = ctypes.c_int
+        L.orc_crypt_range.argtypes = [u8p, ctypes.c_size_t, ctypes.POINTER(Params), ctypes.c_uint64, u8p,
+                                      ctypes.c_size_t, u8p, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_uint64)]
+        L.orc_crypt_range.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -216,4 +220,19 @@ def crypt_block(pw: bytes, b: int, data, decrypt: bool = False, **kw):
                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(decrypt), d)
     if rc:
         _raise("orc_crypt_block", rc)
+    return out, tuple(d)
+
+
+def crypt_range(pw: bytes, b0: int, data, decrypt: bool = False, nthreads: int = 1, **kw):
+    """Blocks b0, b0 + 1, ... of a message (data starts at byte b0 * block_len of it): returns
+    (output bytes, XOR of the blocks' digests).  The parts of a message's ranges XOR to its tag."""
+    prm = params(**kw)
+    da, dp = _u8(data)
+    out = np.empty(len(da), dtype=np.uint8)
+    d = (ctypes.c_uint64 * 3)()
+    pwa, pwp = _u8(pw)
+    rc = lib().orc_crypt_range(pwp, len(pw), ctypes.byref(prm), b0, dp, len(da),
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(decrypt), nthreads, d)
+    if rc:
+        _raise("orc_crypt_range", rc)
     return out, tuple(d)

@@ -425,10 +425,11 @@ int orc_block(const orc_key *K, const orc_params *prm, uint64_t b, const uint8_t
 typedef struct {
     const orc_key *K;
     const orc_params *prm;
-    const uint8_t *in;
+    const uint8_t *in;  /* bytes of blocks b0, b0 + 1, ... */
     uint8_t *out;
     size_t n;
     uint64_t nb;
+    uint64_t b0;        /* index in the message of the first block */
     int decrypt;
     uint64_t *digests; /* 3 per block */
     uint64_t next;     /* shared block counter */
@@ -445,7 +446,8 @@ static void *worker(void *arg) {
         if (b >= J->nb) break;
         size_t off = (size_t)b * J->prm->block_len;
         size_t len = J->n - off < J->prm->block_len ? J->n - off : J->prm->block_len;
-        int rc = orc_block(J->K, J->prm, b, J->in + off, len, J->out + off, J->decrypt, J->digests + 3 * b);
+        int rc = orc_block(J->K, J->prm, J->b0 + b, J->in + off, len, J->out + off, J->decrypt,
+                           J->digests + 3 * b);
         if (rc) {
             pthread_mutex_lock(&J->lock);
             if (!J->rc) J->rc = rc;
@@ -455,10 +457,12 @@ static void *worker(void *arg) {
     return NULL;
 }
 
-static int run_blocks(const orc_key *K, const orc_params *prm, const uint8_t *in, size_t n,
+/* Blocks b0, b0 + 1, ... covering the n bytes at in (n = 0: the one empty block b0); tag = XOR of
+ * their digests. */
+static int run_blocks(const orc_key *K, const orc_params *prm, uint64_t b0, const uint8_t *in, size_t n,
                       uint8_t *out, int decrypt, int nthreads, uint64_t tag[3]) {
     uint64_t nb = n == 0 ? 1 : (n + prm->block_len - 1) / prm->block_len;
-    job_t J = {K, prm, in, out, n, nb, decrypt, NULL, 0, 0, PTHREAD_MUTEX_INITIALIZER};
+    job_t J = {K, prm, in, out, n, nb, b0, decrypt, NULL, 0, 0, PTHREAD_MUTEX_INITIALIZER};
     J.digests = (uint64_t *)calloc(3 * nb, sizeof(uint64_t));
     if (!J.digests) return -3;
     if (nthreads < 1) nthreads = 1;
@@ -494,7 +498,7 @@ int orc_encrypt(const uint8_t *pw, size_t n_pw, const orc_params *prm, const uin
     orc_key K;
     if (orc_key_setup(pw, n_pw, prm, &K, NULL)) return -1;
     uint64_t tag[3];
-    int rc = run_blocks(&K, prm, P, n, C, 0, nthreads, tag);
+    int rc = run_blocks(&K, prm, 0, P, n, C, 0, nthreads, tag);
     if (rc) return rc;
     for (int j = 0; j < 3; j++)
         for (int q = 0; q < 8; q++) C[n + 8 * j + q] = (uint8_t)(tag[j] >> (8 * q));
@@ -510,7 +514,7 @@ int orc_decrypt(const uint8_t *pw, size_t n_pw, const orc_params *prm, const uin
     if (orc_key_setup(pw, n_pw, prm, &K, NULL)) return -1;
     size_t n = n_c - 24;
     uint64_t tag[3];
-    int rc = run_blocks(&K, prm, C, n, P, 1, nthreads, tag);
+    int rc = run_blocks(&K, prm, 0, C, n, P, 1, nthreads, tag);
     if (rc) {
         if (n) memset(P, 0, n);
         return rc;
@@ -535,4 +539,16 @@ int orc_crypt_block(const uint8_t *pw, size_t n_pw, const orc_params *prm, uint6
     orc_key K;
     if (orc_key_setup(pw, n_pw, prm, &K, NULL)) return -1;
     return orc_block(&K, prm, b, in, len, out, decrypt, d);
+}
+
+/* Blocks b0, b0 + 1, ... of a message, covering the len bytes at in (which start at byte b0 block_len
+ * of the message), spread over threads: out receives their output bytes and part the XOR of their
+ * digests, so that the parts of a message's block ranges XOR to its tag.  For checks of large
+ * messages slice by slice. */
+int orc_crypt_range(const uint8_t *pw, size_t n_pw, const orc_params *prm, uint64_t b0, const uint8_t *in,
+                    size_t len, uint8_t *out, int decrypt, int nthreads, uint64_t part[3]) {
+    if (check_params(prm) || (!in && len) || (!out && len) || !part) return -1;
+    orc_key K;
+    if (orc_key_setup(pw, n_pw, prm, &K, NULL)) return -1;
+    return run_blocks(&K, prm, b0, in, len, out, decrypt, nthreads, part);
 }

@@ -12,8 +12,8 @@
 namespace lz {
 
 // ---- errors -------------------------------------------------------------------
-void set_error(const std::string &msg);
-int fail(int code, const std::string &msg);
+void set_error(const char *msg);
+int fail(int code, const char *msg);
 int hip_fail(hipError_t e, const char *what);
 #define LZ_HIP(call)                                        \
     do {                                                    \

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -17,19 +18,20 @@
 namespace lz {
 
 namespace {
-thread_local std::string g_last_error;
+// fixed storage: reporting an error never allocates
+thread_local char g_last_error[512];
 }
 
-void set_error(const std::string &msg) { g_last_error = msg; }
+void set_error(const char *msg) { std::snprintf(g_last_error, sizeof g_last_error, "%s", msg); }
 
-int fail(int code, const std::string &msg) {
+int fail(int code, const char *msg) {
     set_error(msg);
     return code;
 }
 
 int hip_fail(hipError_t e, const char *what) {
-    return fail(e == hipErrorOutOfMemory ? LZ_E_NOMEM : LZ_E_HIP,
-                std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+    std::snprintf(g_last_error, sizeof g_last_error, "%s: %s (%s)", what, hipGetErrorName(e), hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? LZ_E_NOMEM : LZ_E_HIP;
 }
 
 int check_params(const lz_params &p) {
@@ -131,7 +133,7 @@ extern "C" int lz_key_setup(const uint8_t *pw, size_t n_pw, const lz_params *prm
     return key_setup(pw, n_pw, *prm, *out);
 }
 
-extern "C" const char *lz_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *lz_last_error(void) { return g_last_error; }
 
 extern "C" uint64_t lz_now_ns(void) {
     return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(

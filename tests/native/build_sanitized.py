@@ -2,6 +2,7 @@
 
     python tests/native/build_sanitized.py
 
+tests/test_gpu_host_sanitized.py calls build() itself, into a fresh directory, before each run.
 
 The program is tests/native/host_sanitize.cpp linked with every library source compiled as in the package
 build, plus AddressSanitizer and UndefinedBehaviorSanitizer: each sanitizer option is passed through -Xarch_host, so
@@ -36,14 +37,15 @@ KINDS = {
 LSAN_SUPP = "leak:libamdhip64\nleak:libhsa-runtime64\nleak:libdrm\nleak:libamd_comgr\n"
 
 
-def build(kind: str) -> str:
+def build(kind: str, out_dir: str = OUT) -> str:
+    """Builds host_<kind> (and lsan.supp) in out_dir; returns the program's path."""
     flags = KINDS[kind]
-    os.makedirs(OUT, exist_ok=True)
+    os.makedirs(out_dir, exist_ok=True)
     with tempfile.TemporaryDirectory(prefix="lzsan") as objdir:
-        return _build_in(kind, flags, objdir)
+        return _build_in(kind, flags, objdir, out_dir)
 
 
-def _build_in(kind: str, flags: list[str], objdir: str) -> str:
+def _build_in(kind: str, flags: list[str], objdir: str, out_dir: str) -> str:
     cmds, objs = [], []
     srcs = [(os.path.join(LB.CSRC, s), s) for s in LB.SOURCES] + [(os.path.join(HERE, "host_sanitize.cpp"),
                                                                     "host_sanitize.cpp")]
@@ -57,9 +59,9 @@ def _build_in(kind: str, flags: list[str], objdir: str) -> str:
         objs.append(obj)
     with ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as pool:
         list(pool.map(LB._run, cmds))
-    exe = os.path.join(OUT, "host_" + kind)
+    exe = os.path.join(out_dir, "host_" + kind)
     LB._run([LB.HIPCC, f"--offload-arch={LB.ARCH}", *flags, *objs, "-o", exe, "-lpthread"])
-    with open(os.path.join(OUT, "lsan.supp"), "w") as f:
+    with open(os.path.join(out_dir, "lsan.supp"), "w") as f:
         f.write(LSAN_SUPP)
     return exe
 
