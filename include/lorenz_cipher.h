@@ -195,6 +195,35 @@ int lz_encrypt_key(lz_ctx *ctx, const lz_key *key, const uint8_t *d_P, size_t n,
 int lz_decrypt_key(lz_ctx *ctx, const lz_key *key, const uint8_t *d_C, size_t n_c, uint8_t *d_P,
                    int32_t *d_status, void *stream);
 
+/* ---- decrypt without allocation -------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * lz_decrypt_noalloc is lz_decrypt (same kernels, same output, same status)
+ * without a context: parameters *prm (NULL = defaults), the current HIP
+ * device, the plain path's default launch shape.  It calls no hipMalloc,
+ * hipFree or allocating routine.  Its one scratch buffer, the tag
+ * accumulator, is a static device array of LZ_NOALLOC_SCRATCH_BYTES held by
+ * each GPU until the process ends (its address is resolved once per device,
+ * on the first call there); each call clears what it uses first.  Messages
+ * up to the plain path's limits (2^32 bytes, LZ_MAX_BLOCKS blocks) fit it;
+ * larger ones are rejected with LZ_E_INVAL before anything runs.
+ *
+ * d_C device pointer of n_c >= 24 bytes; d_P device pointer of n_c - 24
+ * bytes; d_status device int32, required (LZ_OK or LZ_E_INTEGRITY; on
+ * LZ_E_INTEGRITY the plaintext is zeroed).  stream must belong to the
+ * current device.  Asynchronous on stream.
+ *
+ * Every call on one GPU shares that GPU's scratch: calls on one stream are
+ * ordered and safe; calls that overlap on one GPU (other streams, no
+ * ordering between them) race and give wrong statuses.  LZ_E_INVAL for a
+ * NULL argument, bad parameters or password length, n_c < 24, a message
+ * beyond the limits, or a device index >= LZ_NOALLOC_MAX_DEVICES. */
+#define LZ_NOALLOC_SCRATCH_BYTES 256
+#define LZ_NOALLOC_MAX_DEVICES 64
+int lz_decrypt_noalloc(const lz_params *prm, const uint8_t *pw, size_t n_pw, const uint8_t *d_C, size_t n_c,
+                       uint8_t *d_P, int32_t *d_status, void *stream);
+
 /* ---- batched path: many messages, one persistent launch in a HIP graph ---------
  * n_msg messages, message i with its own password and plaintext length
  * lens[i] (host arrays).  Encrypt: input i is lens[i] bytes at d_in +

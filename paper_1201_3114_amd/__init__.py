@@ -5,5 +5,5 @@ with hand-written HIP kernels, and this thin Python layer over it.
 Importing the package loads the library and fails if it is not built.
 """
 from .cipher import (TAG_BYTES, Batch, Context, IntegrityError, LaunchShape, LorenzError, Server, Stream,  # noqa: F401
-                     autocorrelation, autocorrelation_2d, entropy, histogram, key_setup, lag_sums, now_ns,
+                     autocorrelation, autocorrelation_2d, decrypt_noalloc, entropy, histogram, key_setup, lag_sums, now_ns,
                      packed_offsets, params, power_spectrum_2d, unit_lorenz, unit_r, unit_theta)

@@ -68,6 +68,8 @@ SIGNATURES = {
     "lz_decrypt": (ctypes.c_int, [vp, u8p, ctypes.c_size_t, vp, ctypes.c_size_t, vp, vp, vp]),
     "lz_encrypt_key": (ctypes.c_int, [vp, ctypes.POINTER(Key), vp, ctypes.c_size_t, vp, vp]),
     "lz_decrypt_key": (ctypes.c_int, [vp, ctypes.POINTER(Key), vp, ctypes.c_size_t, vp, vp, vp]),
+    "lz_decrypt_noalloc": (ctypes.c_int, [ctypes.POINTER(Params), u8p, ctypes.c_size_t, vp, ctypes.c_size_t, vp,
+                                          vp, vp]),
     "lz_batch_create": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint64),
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), u8p,
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32), vp, vp, vp,

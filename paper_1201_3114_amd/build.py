@@ -19,8 +19,8 @@ ARCH = os.environ.get("LZ_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-result"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["kernels.hip", "diag.hip", "copy.hip", "runtime.cpp", "server.cpp", "stream.cpp", "keysetup.cpp",
-           "units.cpp"]
+SOURCES = ["kernels.hip", "diag.hip", "copy.hip", "noalloc.hip", "runtime.cpp", "server.cpp", "stream.cpp",
+           "keysetup.cpp", "units.cpp"]
 
 
 def _run(cmd):

@@ -147,6 +147,23 @@ class Context:
         return out
 
 
+def decrypt_noalloc(C: torch.Tensor, pw: bytes, out: torch.Tensor, status: torch.Tensor,
+                    prm: B.Params | None = None, stream=None) -> torch.Tensor:
+    """lz_decrypt_noalloc: lz_decrypt without a context and without device allocation, on the
+    current device; out (n_c - 24 bytes) and status (one int32) are caller-provided GPU tensors.
+    Calls that overlap on one GPU share its scratch and race; calls on one stream are ordered."""
+    nc = C.numel()
+    if nc < TAG_BYTES or out.numel() != nc - TAG_BYTES:
+        raise ValueError("C must hold at least the 24-byte tag and out n_c - 24 bytes")
+    if status.dtype != torch.int32 or not status.is_cuda or status.numel() < 1:
+        raise ValueError("status must be a torch.int32 tensor on the GPU")
+    buf, npw = B.pw_buf(pw)
+    check(B.lib.lz_decrypt_noalloc(ctypes.byref(prm) if prm is not None else None, buf, npw, _dev_ptr(C), nc,
+                                   _dev_ptr(out) if out.numel() else None, ctypes.c_void_p(status.data_ptr()),
+                                   _stream(stream, C.device)))
+    return out
+
+
 class Batch:
     """Many messages, each with its own password, in one graph-captured persistent launch.
 

@@ -227,3 +227,32 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"] and "--gpus must be 1" in msg["error"]
+
+
+def test_decrypt_noalloc_rejects_bad_arguments_on_the_host(B):
+    """lz_decrypt_noalloc checks its arguments before any HIP call: the stand-in pointers below are
+    never dereferenced (no GPU is needed)."""
+    p = B.Params()
+    B.lib.lz_params_default(ctypes.byref(p))
+    buf, npw = B.pw_buf(b"password")
+    fake = ctypes.c_void_p(4096)
+    cases = [
+        (ctypes.byref(p), buf, npw, fake, 23, fake, fake, "shorter than the 24-byte tag"),
+        (ctypes.byref(p), buf, npw, fake, 100, fake, None, "d_status"),
+        (ctypes.byref(p), buf, 0, fake, 100, fake, fake, "password length"),
+        (ctypes.byref(p), buf, 65, fake, 100, fake, fake, "password length"),
+        (ctypes.byref(p), None, npw, fake, 100, fake, fake, "NULL"),
+        (ctypes.byref(p), buf, npw, None, 100, fake, fake, "NULL"),
+        (ctypes.byref(p), buf, npw, fake, 100, None, fake, "NULL plaintext"),
+        (ctypes.byref(p), buf, npw, fake, (1 << 32) + 25, fake, fake, "2^32"),
+    ]
+    for *args, msg in cases:
+        assert B.lib.lz_decrypt_noalloc(*args, None) == B.LZ_E_INVAL, msg
+        assert msg.encode() in B.lib.lz_last_error(), (msg, B.lib.lz_last_error())
+    q = B.Params()
+    B.lib.lz_params_default(ctypes.byref(q))
+    q.block_len = 16
+    assert B.lib.lz_decrypt_noalloc(ctypes.byref(q), buf, npw, fake, (1 << 28) + 25, fake, fake, None) == B.LZ_E_INVAL
+    assert b"blocks" in B.lib.lz_last_error()
+    q.dt = 0.02
+    assert B.lib.lz_decrypt_noalloc(ctypes.byref(q), buf, npw, fake, 100, fake, fake, None) == B.LZ_E_INVAL
