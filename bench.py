@@ -12,9 +12,11 @@ Beside it, on the same line:
   batched      4096 messages (log-uniform 1 KiB..1 MiB, own passwords) in one
                graph-captured persistent launch, vs the plain path per message,
                and the integrity check of 10% altered ciphertexts;
-  served       a Poisson trace of mixed encrypt/decrypt requests through the
-               continuous-batching server: p50/p99 latency and GB/s, vs the plain
-               path one request at a time on a prefix of the same trace.
+  served       a Poisson trace of mixed encrypt/decrypt requests at fixed offered
+               loads (0.3, 0.5, 0.7, 0.9 of capacity) through the continuous-
+               batching server: p50/p99 latency and GB/s under the adaptive tick
+               (waves per SIMD from the backlog) and with every admitted chain in
+               each tick, and vs the plain path one request at a time on a prefix.
 """
 from __future__ import annotations
 
@@ -49,12 +51,13 @@ def fp64_ops_per_byte(n_it: int, integrator: str = "euler") -> int:
 
 
 def kernel_stamp() -> str:
-    """First 16 hex digits of sha256 over the kernel and runtime sources."""
+    """First 16 hex digits of sha256 over the kernel and runtime sources and the build script
+    (its compiler flags shape the kernels' code)."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("kernels.hip", "runtime.cpp"):
-        with open(os.path.join(ROOT, "paper_1201_3114_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/kernels.hip", "csrc/runtime.cpp", "build.py"):
+        with open(os.path.join(ROOT, "paper_1201_3114_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -416,11 +419,12 @@ def bench_batch(lz, torch, steps, plain_sample=256):
     sizes = wl.sizes
     total = int(sizes.sum())
     ctx = lz.Context(0)
-    tuned = None
+    tuned, tune = None, dict(source="none")
     try:
         t = time.perf_counter()
-        tuned = ctx.autotune(budget_ms=4000)
-        log(f"autotune: {tuned} in {time.perf_counter() - t:.1f} s")
+        tuned, hit = ctx.autotune_cached(budget_ms=8000)
+        tune = dict(source="cache" if hit else "tuned", seconds=time.perf_counter() - t, shape=vars(tuned))
+        log(f"autotune: {tuned} ({tune['source']}) in {tune['seconds']:.1f} s")
     except lz.LorenzError as e:
         log("autotune failed:", e)
     in_off = wl.offsets.astype(np.uint64)
@@ -491,7 +495,7 @@ def bench_batch(lz, torch, steps, plain_sample=256):
     return dict(
         messages=len(sizes), bytes=total, launch=dict(chains_per_lane=shape.chains_per_lane, wg_size=shape.wg_size,
                                                       tile=shape.tile, waves_per_simd=shape.waves_per_simd),
-        autotuned=tuned is not None, encrypt_GBps=total / enc_ms / 1e6, decrypt_GBps=total / dec_ms / 1e6,
+        autotune=tune, encrypt_GBps=total / enc_ms / 1e6, decrypt_GBps=total / dec_ms / 1e6,
         enc_dec_GBps=2 * total / (enc_ms + dec_ms) / 1e6, enc_ms=enc_ms, dec_ms=dec_ms, setup_s=setup_s,
         roundtrip_exact=ok,
         plain_per_message=dict(messages=k, bytes=pb, encrypt_GBps=pb / plain_ms / 1e6, ms=plain_ms,
@@ -502,10 +506,14 @@ def bench_batch(lz, torch, steps, plain_sample=256):
 
 
 # ---------------------------------------------------------------------------------------------
-def bench_serve(lz, torch, qps, count, plain_prefix, budget, tick_bytes=16):
+def bench_serve(lz, torch, count, plain_prefix, budget, tick_bytes=16, run_waves=0, curve_requests=40_000):
+    """Continuous batching on the fixed-QPS trace: the headline run at 0.7 of capacity, the
+    latency curve at every fixed load, the same runs with every admitted chain in each tick
+    (the all-chains policy), saturation, and the plain path one request at a time."""
     from paper_1201_3114_amd import workloads
 
-    tr = workloads.serve_trace(count=count, qps=qps)
+    q_ref = workloads.SERVE_QPS[0.7]
+    tr = workloads.serve_trace(count=count, qps=q_ref)
     sizes = tr.sizes
     dec = tr.decrypt.astype(bool)
     tot = int(sizes.sum())
@@ -529,11 +537,14 @@ def bench_serve(lz, torch, qps, count, plain_prefix, budget, tick_bytes=16):
     src_all = np.where(dec, dC.data_ptr() + c_off, dP.data_ptr() + p_off).astype(np.uint64)
     dst_all = (dOut.data_ptr() + c_off).astype(np.uint64)
 
-    def run_server(ids, all_at_once=False):
-        srv = lz.Server(ctx, hbm_budget=budget, tick_bytes=tick_bytes)
+    def run_server(ids, load=0.7, all_at_once=False, policy="adaptive"):
+        srv = lz.Server(ctx, hbm_budget=budget, tick_bytes=tick_bytes, run_waves=run_waves, policy=policy)
         lead_ns = int(1.0e9) + 10_000 * len(ids)
         base = lz.now_ns() + lead_ns
-        arr = (base + np.round((tr.arrival_s[ids] - tr.arrival_s[ids[0]]) * 1e9)).astype(np.uint64)
+        # the trace's arrivals are drawn at the 0.7 rate; another fixed load rescales them
+        scale = q_ref / workloads.SERVE_QPS[load]
+        arr_s = (tr.arrival_s[ids] - tr.arrival_s[ids[0]]) * scale
+        arr = (base + np.round(arr_s * 1e9)).astype(np.uint64)
         if all_at_once:
             arr[:] = base
         t_sub = time.perf_counter()
@@ -552,33 +563,51 @@ def bench_serve(lz, torch, qps, count, plain_prefix, budget, tick_bytes=16):
         srv.close()
         span = (last_done - first_arr) / 1e9
         nbytes = int(sizes[ids].sum())
-        trace_s = 0.0 if all_at_once else float(tr.arrival_s[ids[-1]] - tr.arrival_s[ids[0]])
-        return dict(requests=len(ids), bytes=nbytes, GBps=nbytes / span / GB, offered_GBps=nbytes / max(trace_s, 1e-9) / GB,
-                    makespan_s=span, p50_ms=percentile(lat, 50), p99_ms=percentile(lat, 99), max_ms=float(np.max(lat)),
-                    all_ok=all(s == 0 for s in status), ticks=stats["ticks"], device_busy_ms=stats["busy_ms"],
-                    device_busy_frac=stats["busy_ms"] / 1e3 / span, peak_hbm_GB=stats["peak_hbm"] / GB,
-                    tick_bytes=tick_bytes, submit_s=submit_s, submitted_before_first_arrival=submitted_in_time)
+        r = dict(requests=len(ids), bytes=nbytes, GBps=nbytes / span / GB, makespan_s=span,
+                 p50_ms=percentile(lat, 50), p99_ms=percentile(lat, 99), max_ms=float(np.max(lat)),
+                 all_ok=all(s == 0 for s in status), ticks=stats["ticks"], device_busy_ms=stats["busy_ms"],
+                 device_busy_frac=stats["busy_ms"] / 1e3 / span, peak_hbm_GB=stats["peak_hbm"] / GB,
+                 tick_bytes=tick_bytes, policy=policy, submit_s=submit_s,
+                 submitted_before_first_arrival=submitted_in_time)
+        if not all_at_once:
+            r.update(load=load, qps=workloads.SERVE_QPS[load], offered_GBps=nbytes / float(arr_s[-1]) / GB)
+        return r
 
-    ids = np.arange(count)
-    log(f"serve: {count} requests, {tot / GB:.2f} GB, qps {qps:.0f}")
-    served = run_server(ids)
-    # bit-exactness of every response: expected = batched ciphertexts for encrypt requests and
-    # the original plaintexts (then 24 untouched zero bytes) for decrypt requests
-    torch.cuda.synchronize()
+    # expected bytes of every response: the batched ciphertexts for encrypt requests and the
+    # original plaintexts (then 24 untouched zero bytes) for decrypt requests
     E = dC.clone()
     for i in np.nonzero(dec)[0]:
         o, po, n = int(c_off[i]), int(p_off[i]), int(sizes[i])
         E[o:o + n] = dP[po:po + n]
         E[o + n:o + n + 24] = 0
-    served["bit_exact_vs_plain"] = bool(torch.equal(E, dOut))
+
+    def exact(ids):
+        torch.cuda.synchronize()
+        last = int(c_off[ids[-1]]) + int(sizes[ids[-1]]) + 24
+        ok = bool(torch.equal(E[:last], dOut[:last]))
+        dOut.zero_()
+        return ok
+
+    ids = np.arange(count)
+    log(f"serve: {count} requests, {tot / GB:.2f} GB, qps {q_ref:.0f} (0.7 of capacity)")
+    served = run_server(ids)
+    served["bit_exact_vs_plain"] = exact(ids)
+    # latency against offered load, on the first curve_requests requests of the trace
+    cids = ids[:min(count, curve_requests)]
+    curve, curve_all = [], []
+    for load in sorted(workloads.SERVE_QPS):
+        log(f"serve: load {load}, {len(cids)} requests")
+        curve.append(run_server(cids, load=load))
+        curve[-1]["bit_exact_vs_plain"] = exact(cids)
+        curve_all.append(run_server(cids, load=load, policy="all_chains"))
+        curve_all[-1]["bit_exact_vs_plain"] = exact(cids)
     # saturation: the first quarter of the requests all offered at once (the engine's peak rate)
     sat_ids = ids[:max(1, count // 4)]
-    dOut.zero_()
+    log(f"serve: saturated, {len(sat_ids)} requests")
     saturated = run_server(sat_ids, all_at_once=True)
-    torch.cuda.synchronize()
-    last = int(c_off[sat_ids[-1]]) + int(sizes[sat_ids[-1]]) + 24
-    saturated["bit_exact_vs_plain"] = bool(torch.equal(E[:last], dOut[:last]))
-    del saturated["offered_GBps"]
+    saturated["bit_exact_vs_plain"] = exact(sat_ids)
+    saturated_all = run_server(sat_ids, all_at_once=True, policy="all_chains")
+    saturated_all["bit_exact_vs_plain"] = exact(sat_ids)
     del E
     # plain path, one request at a time in arrival order, on a prefix of the trace
     k = min(plain_prefix, count)
@@ -613,9 +642,16 @@ def bench_serve(lz, torch, qps, count, plain_prefix, budget, tick_bytes=16):
                  p99_ms=percentile(lat, 99), bit_exact=outs_ok)
     served_prefix = run_server(pre)
     ctx.close()
-    return dict(qps=qps, requests=count, bytes=tot, mean_request_bytes=tot / count, prep_s=prep_s,
-                hbm_budget_GB=budget / GB, continuous=served, saturated=saturated, plain_per_request_prefix=plain,
-                continuous_same_prefix=served_prefix,
+    keep = ("load", "qps", "requests", "GBps", "offered_GBps", "p50_ms", "p99_ms", "max_ms", "ticks",
+            "device_busy_frac", "all_ok", "bit_exact_vs_plain")
+    return dict(config=dict(qps=workloads.SERVE_QPS, capacity_GBps=workloads.SERVE_CAPACITY_GBPS,
+                            mean_request_bytes=tot / count, hbm_budget_GB=budget / GB, tick_bytes=tick_bytes,
+                            run_waves=run_waves or 4),
+                requests=count, bytes=tot, prep_s=prep_s, continuous=served,
+                latency_curve=[{k_: c[k_] for k_ in keep} for c in curve],
+                latency_curve_all_chains=[{k_: c[k_] for k_ in keep} for c in curve_all],
+                saturated=saturated, saturated_all_chains=saturated_all,
+                plain_per_request_prefix=plain, continuous_same_prefix=served_prefix,
                 p99_speedup_vs_plain_on_prefix=plain["p99_ms"] / served_prefix["p99_ms"])
 
 
@@ -628,7 +664,8 @@ def main():
     ap.add_argument("--only", choices=["all", "plain", "batch", "serve", "variants", "stream", "diag", "copycal"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200_000)
-    ap.add_argument("--serve-qps", type=float, default=0.0, help="0 = 0.7 x plain-path capacity")
+    ap.add_argument("--serve-run-waves", type=int, default=0, help="most waves per SIMD of a serving tick (0 = 4)")
+    ap.add_argument("--serve-curve-requests", type=int, default=40_000)
     ap.add_argument("--serve-plain-prefix", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-tick-bytes", type=int, default=16)
@@ -714,17 +751,12 @@ def main():
         log("diagnostics ...")
         out["diagnostics"] = bench_diag(lz, torch)
     if args.only in ("all", "serve"):
-        from paper_1201_3114_amd import workloads
-
-        qps = args.serve_qps
-        if qps <= 0:
-            tr = workloads.serve_trace(count=args.serve_requests, qps=1.0)
-            mean_bytes = float(tr.sizes.mean())
-            per_dir = out.get("value", 0.9)
-            qps = 0.7 * per_dir * GB / mean_bytes
         log("served ...")
-        out["served"] = bench_serve(lz, torch, qps, args.serve_requests, args.serve_plain_prefix,
-                                    int(args.serve_budget_gb * GB), args.serve_tick_bytes)
+        sv = bench_serve(lz, torch, args.serve_requests, args.serve_plain_prefix, int(args.serve_budget_gb * GB),
+                         args.serve_tick_bytes, args.serve_run_waves, args.serve_curve_requests)
+        if "batched" in out:
+            sv["saturated_frac_of_batched"] = sv["saturated"]["GBps"] / out["batched"]["enc_dec_GBps"]
+        out["served"] = sv
     print(json.dumps(out))
 
 

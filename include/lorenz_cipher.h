@@ -264,12 +264,28 @@ int lz_decrypt_batch(lz_ctx *ctx, const lz_batch *batch, int32_t *d_status, void
 int lz_batch_launch(lz_batch *batch, void *stream);
 int lz_batch_destroy(lz_batch *batch);
 
-/* Autotuner: times candidate launch shapes (chains_per_lane x wg_size x tile
- * x waves_per_simd) of the batched kernel on a synthetic full-device batch
- * with the context's parameters, stores the fastest in the context and in
- * *best (may be NULL).  Synchronous; takes a few seconds.  When budget_ms > 0
- * the sweep stops after that much measured time. */
+/* Autotuner: chooses the launch shape of the batched (and plain) kernels on
+ * a synthetic batch of about 1.5 resident rounds of the device, with the
+ * context's parameters.  Stage 1 times every shape of the grid
+ * chains_per_lane {1,2,4} x waves_per_simd {1,2,4,8} (4 to 8 chains in flight
+ * per SIMD slot) x wg_size {64,128,256} x tile {16,32,64,128} that fits the
+ * device's LDS, at a tenth of n_it (the same per-byte loop in a tenth of the
+ * time); stage 2 times the three fastest at the context's n_it.  The winner
+ * goes to the context and to *best (may be NULL).  Synchronous; a few
+ * seconds at n_it = 3000.  When budget_ms > 0 stage 1 stops after that much
+ * measured time (the context's shape is timed first). */
 int lz_autotune(lz_ctx *ctx, double budget_ms, lz_launch *best);
+
+/* lz_autotune with a per-device cache: a text file of lines
+ * "<gfx arch> cus=<CUs> integrator=<i> n_it=<n> block_len=<b>\t<chains_per_lane>
+ * <wg_size> <tile> <waves_per_simd>\t<ms>".  path NULL = $LZ_TUNE_CACHE, else
+ * $HOME/.cache/lorenz_cipher/launch_shapes.tsv (no file without HOME).  A
+ * valid entry for this device and these parameters is used as is
+ * (*from_cache = 1); otherwise the shape is tuned and the entry written
+ * (*from_cache = 0; the file is rewritten through a temporary file and a
+ * rename, and a failure to write it is not an error).  from_cache may be
+ * NULL. */
+int lz_autotune_cached(lz_ctx *ctx, const char *path, double budget_ms, lz_launch *best, int *from_cache);
 
 /* ---- streaming: one message of unknown length, chunk by chunk -----------------
  * Encrypts (decrypt = 0) or decrypts one message given as a sequence of
@@ -308,13 +324,26 @@ int lz_stream_close(lz_stream *st);
  * A request loop on a library thread.  Requests are admitted in arrival order
  * while chain slots and the device-memory budget allow; their per-block chain
  * state (r, alpha, mu, Omega: an exact checkpoint) and byte buffers stay on
- * the device, and every tick advances all admitted chains by up to
- * tick_bytes bytes, so requests that arrive while others run join at the
- * next tick.  Results are bit-identical to the plain path. */
+ * the device.  Each tick advances chains by up to tick_bytes bytes, so
+ * requests that arrive while others run join at the next tick.
+ *
+ * Policy LZ_SERVE_ADAPTIVE (the default): a tick runs k waves per SIMD at
+ * most, chosen from the backlog (unfinished chains of admitted and waiting
+ * requests): 1 while the backlog is at most 3 waves per SIMD, 2 up to 6,
+ * then doubling up to run_waves.  Admitted requests join a tick in admission
+ * order, each with all of its unfinished chains or none, and later requests
+ * that fit fill the room an earlier one leaves (the first request with work
+ * always joins, so one larger than the cap still runs).  Policy
+ * LZ_SERVE_ALL_CHAINS: every tick runs every admitted chain.  Results are
+ * bit-identical to the plain path whatever the policy. */
+enum { LZ_SERVE_ADAPTIVE = 0, LZ_SERVE_ALL_CHAINS = 1 };
 typedef struct {
     uint64_t hbm_budget;  /* bytes of device memory for request buffers + chain state */
-    uint32_t max_chains;  /* chain slots resident on the device (0 = 4 waves per SIMD) */
+    uint32_t max_chains;  /* chain slots resident on the device (0 = 2 x run_waves waves
+                             per SIMD; LZ_SERVE_ALL_CHAINS: run_waves waves per SIMD) */
     uint32_t tick_bytes;  /* bytes per chain per tick (0 = 16)                        */
+    uint32_t run_waves;   /* most waves per SIMD one tick runs, 1..8 (0 = 4)          */
+    uint32_t policy;      /* LZ_SERVE_ADAPTIVE or LZ_SERVE_ALL_CHAINS                   */
 } lz_server_config;
 
 typedef struct {
@@ -330,8 +359,8 @@ typedef struct {
 /* Creates the server and starts its thread.  The budget covers everything the
  * server allocates on the device: chain slots (80 bytes each), request records,
  * the two tick slots' staging and a first-fit arena for request buffers (the
- * rest).  LZ_E_INVAL if the budget does not exceed the fixed part, or
- * tick_bytes > 2^20.  Request buffers in device memory are moved by a batched
+ * rest).  LZ_E_INVAL if the budget does not exceed the fixed part,
+ * tick_bytes > 2^20, run_waves > 8 or an unknown policy.  Request buffers in device memory are moved by a batched
  * copy kernel, host buffers (pageable or pinned) by hipMemcpyAsync. */
 int lz_server_create(lz_ctx *ctx, const lz_server_config *cfg, lz_server **out);
 

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "liblorenz_cipher.so")
 LZ_OK, LZ_E_INVAL, LZ_E_INTEGRITY, LZ_E_NOMEM, LZ_E_HIP, LZ_E_AGAIN, LZ_E_CANCELLED = 0, -1, -2, -3, -4, -5, -6
 TAG_BYTES = 24
 INTEGRATORS = {"euler": 0, "euler_fma": 1, "rk4": 2}
+SERVE_POLICIES = {"adaptive": 0, "all_chains": 1}
 
 u8p = ctypes.POINTER(ctypes.c_uint8)
 vp = ctypes.c_void_p
@@ -38,7 +39,8 @@ class Launch(ctypes.Structure):
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_chains", ctypes.c_uint32), ("tick_bytes", ctypes.c_uint32)]
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_chains", ctypes.c_uint32), ("tick_bytes", ctypes.c_uint32),
+                ("run_waves", ctypes.c_uint32), ("policy", ctypes.c_uint32)]
 
 
 class Completion(ctypes.Structure):
@@ -79,6 +81,8 @@ SIGNATURES = {
     "lz_decrypt_batch": (ctypes.c_int, [vp, vp, vp, vp]),
     "lz_batch_destroy": (ctypes.c_int, [vp]),
     "lz_autotune": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(Launch)]),
+    "lz_autotune_cached": (ctypes.c_int, [vp, ctypes.c_char_p, ctypes.c_double, ctypes.POINTER(Launch),
+                                          ctypes.POINTER(ctypes.c_int)]),
     "lz_server_create": (ctypes.c_int, [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
     "lz_server_submit": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.c_int, u8p, ctypes.c_size_t, vp,
                                         ctypes.c_uint64, vp, ctypes.c_uint64]),

@@ -109,6 +109,14 @@ class Context:
         check(B.lib.lz_autotune(self._h, budget_ms, ctypes.byref(l)))
         return LaunchShape.from_c(l)
 
+    def autotune_cached(self, path: str | None = None, budget_ms: float = 0.0) -> tuple[LaunchShape, bool]:
+        """lz_autotune_cached: (shape, True if it came from the per-device cache file)."""
+        l = B.Launch()
+        hit = ctypes.c_int(0)
+        check(B.lib.lz_autotune_cached(self._h, path.encode() if path is not None else None, budget_ms,
+                                       ctypes.byref(l), ctypes.byref(hit)))
+        return LaunchShape.from_c(l), bool(hit.value)
+
     # ---- plain path
     def encrypt(self, P: torch.Tensor, pw: bytes, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """C = E_pi(P) || tag, asynchronous on the stream."""
@@ -283,9 +291,10 @@ def packed_offsets(lens, extra: int = 0, align: int = 1):
 class Server:
     """Continuous-batching request loop (library thread); see lz_server_* in the header."""
 
-    def __init__(self, ctx: Context, hbm_budget: int, max_chains: int = 0, tick_bytes: int = 0):
+    def __init__(self, ctx: Context, hbm_budget: int, max_chains: int = 0, tick_bytes: int = 0, run_waves: int = 0,
+                 policy: str = "adaptive"):
         self.ctx = ctx
-        cfg = B.ServerConfig(hbm_budget, max_chains, tick_bytes)
+        cfg = B.ServerConfig(hbm_budget, max_chains, tick_bytes, run_waves, B.SERVE_POLICIES[policy])
         self._h = ctypes.c_void_p()
         check(B.lib.lz_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(self._h)))
 

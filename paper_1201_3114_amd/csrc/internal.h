@@ -95,6 +95,8 @@ struct DevInfo {
     int lds_per_wg_max;
 };
 
+constexpr int WAVE_LANES = 64;  // lanes of a gfx950 wavefront
+
 // ---- kernel launchers (kernels.hip) --------------------------------------------------
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, hipStream_t s);
 hipError_t launch_plain(const KernelShape &sh, const lz_key &key, const lz_params &prm, int decrypt,
@@ -177,6 +179,8 @@ struct lz_ctx {
     lz_params prm;
     lz::KernelShape shape;
     lz::DevInfo dev;
+    char arch[64];               // gcnArchName of the device
+    double tuned_ms;             // last autotune: time of the winning shape's launch
     unsigned long long *ws_tag;  // 3 words, plain path tag accumulator
     int32_t *ws_status;          // plain path status (synchronous decrypt)
     int32_t *host_status;        // pinned

@@ -7,11 +7,15 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <numeric>
 #include <string>
 #include <vector>
+
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include "internal.h"
 
@@ -162,6 +166,7 @@ extern "C" int lz_context_create(int device, const lz_params *prm, lz_ctx **out)
     c->prm = p;
     c->dev.cus = prop.multiProcessorCount;
     c->dev.lds_per_wg_max = (int)prop.sharedMemPerBlock;
+    std::snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
     // one chain per lane, 4 waves per workgroup, 128-byte tiles (one L2 line per chain per refill)
     c->shape = KernelShape{1, 256, 128, 4};
     if (!shape_valid(c->shape, c->dev)) c->shape = KernelShape{1, 64, 32, 4};
@@ -308,10 +313,14 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
 
-extern "C" int lz_batch_create(lz_ctx *c, int decrypt, size_t n_msg, const uint64_t *lens, const uint64_t *in_off,
-                               const uint64_t *out_off, const uint8_t *pw, const uint64_t *pw_off,
-                               const uint32_t *pw_len, const uint8_t *d_in, uint8_t *d_out, int32_t *d_status,
-                               const lz_launch *shape, lz_batch **out) {
+namespace {
+
+// lz_batch_create with the method parameters given explicitly (the autotuner ranks shapes on
+// a shorter n_it than the context's).
+int batch_create(lz_ctx *c, const lz_params &prm, int decrypt, size_t n_msg, const uint64_t *lens,
+                 const uint64_t *in_off, const uint64_t *out_off, const uint8_t *pw, const uint64_t *pw_off,
+                 const uint32_t *pw_len, const uint8_t *d_in, uint8_t *d_out, int32_t *d_status,
+                 const lz_launch *shape, lz_batch **out) {
     if (!out) return fail(LZ_E_INVAL, "out is NULL");
     *out = nullptr;
     if (!c || !lens || !in_off || !out_off || !pw || !pw_off || !pw_len || !d_in || !d_out)
@@ -320,15 +329,15 @@ extern "C" int lz_batch_create(lz_ctx *c, int decrypt, size_t n_msg, const uint6
     KernelShape sh = shape ? to_shape(*shape) : c->shape;
     if (!shape_valid(sh, c->dev)) return fail(LZ_E_INVAL, "launch shape out of range or over the LDS limit");
     LZ_HIP(hipSetDevice(c->device));
-    const uint32_t B = c->prm.block_len;
+    const uint32_t B = prm.block_len;
 
     std::vector<MsgDesc> md(n_msg);
     std::vector<uint64_t> prefix(n_msg + 1, 0);
     std::vector<uint32_t> tails;
     for (size_t i = 0; i < n_msg; ++i) {
-        if (int rc = check_blocks(c->prm, lens[i], nullptr)) return rc;
+        if (int rc = check_blocks(prm, lens[i], nullptr)) return rc;
         lz_key key;
-        if (int rc = lz_key_setup(pw + pw_off[i], pw_len[i], &c->prm, &key)) return rc;
+        if (int rc = lz_key_setup(pw + pw_off[i], pw_len[i], &prm, &key)) return rc;
         MsgDesc &m = md[i];
         std::memset(&m, 0, sizeof m);
         for (int j = 0; j < 3; ++j) {
@@ -402,7 +411,7 @@ extern "C" int lz_batch_create(lz_ctx *c, int decrypt, size_t n_msg, const uint6
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t e1 = launch_fill_u64(d.tag_acc, 3 * n_msg + 1, cap);
-        hipError_t e2 = e1 == hipSuccess ? launch_batch(sh, c->dev, c->prm, d, cap) : e1;
+        hipError_t e2 = e1 == hipSuccess ? launch_batch(sh, c->dev, prm, d, cap) : e1;
         hipError_t e3 = e2 == hipSuccess ? launch_batch_finalize(d, b->decrypt, cap) : e2;
         e = hipStreamEndCapture(cap, &b->graph);
         if (e3 != hipSuccess) e = e3;
@@ -418,8 +427,6 @@ extern "C" int lz_batch_create(lz_ctx *c, int decrypt, size_t n_msg, const uint6
     return LZ_OK;
 }
 
-namespace {
-
 // One replay of the batch graph on stream; for a decrypt batch the statuses go to d_status.
 int batch_replay(const lz_batch *b, int32_t *d_status, hipStream_t s) {
     LZ_HIP(hipSetDevice(b->ctx->device));
@@ -430,6 +437,18 @@ int batch_replay(const lz_batch *b, int32_t *d_status, hipStream_t s) {
 }
 
 }  // namespace
+
+extern "C" int lz_batch_create(lz_ctx *c, int decrypt, size_t n_msg, const uint64_t *lens, const uint64_t *in_off,
+                               const uint64_t *out_off, const uint8_t *pw, const uint64_t *pw_off,
+                               const uint32_t *pw_len, const uint8_t *d_in, uint8_t *d_out, int32_t *d_status,
+                               const lz_launch *shape, lz_batch **out) {
+    if (!c) {
+        if (out) *out = nullptr;
+        return fail(LZ_E_INVAL, "NULL argument");
+    }
+    return batch_create(c, c->prm, decrypt, n_msg, lens, in_off, out_off, pw, pw_off, pw_len, d_in, d_out, d_status,
+                        shape, out);
+}
 
 extern "C" int lz_encrypt_batch(lz_ctx *c, const lz_batch *b, void *stream) {
     if (!c || !b) return fail(LZ_E_INVAL, "NULL argument");
@@ -456,18 +475,51 @@ extern "C" int lz_batch_destroy(lz_batch *b) { return batch_free(b); }
 
 // ---- autotuner ---------------------------------------------------------------------------------
 
-extern "C" int lz_autotune(lz_ctx *c, double budget_ms, lz_launch *best) {
-    if (!c) return fail(LZ_E_INVAL, "ctx is NULL");
-    LZ_HIP(hipSetDevice(c->device));
+namespace {
+
+// The candidate grid: 1, 2 or 4 chains per lane and 1..8 resident waves per SIMD with 4 to 8
+// chains in flight per SIMD slot, 64-, 128- or 256-thread workgroups, 16- to 128-byte tiles.
+std::vector<KernelShape> shape_grid(const KernelShape &first, const DevInfo &dev) {
+    std::vector<KernelShape> g;
+    if (shape_valid(first, dev)) g.push_back(first);
+    for (int m : {1, 2, 4})
+        for (int wps : {1, 2, 4, 8})
+            for (int wg : {256, 128, 64})
+                for (int tile : {128, 64, 32, 16}) {
+                    if (m * wps < 4 || m * wps > 8) continue;
+                    const KernelShape sh{m, wg, tile, wps};
+                    if (!shape_valid(sh, dev)) continue;
+                    if (sh.m == first.m && sh.wg == first.wg && sh.tile == first.tile && sh.wps == first.wps) continue;
+                    g.push_back(sh);
+                }
+    return g;
+}
+
+// Synthetic batch of the autotuner: about 1.5 resident rounds of single-chain lanes at 4 waves
+// per SIMD, in messages of 64 full blocks, every fourth with a ragged tail, random bytes,
+// distinct 16-byte passwords.
+struct TuneBatch {
+    std::vector<uint64_t> lens, in_off, out_off, pw_off;
+    std::vector<uint32_t> pw_len;
+    std::vector<uint8_t> pw;
+    uint8_t *d_in = nullptr, *d_out = nullptr;
+    ~TuneBatch() {
+        if (d_in) (void)hipFree(d_in);
+        if (d_out) (void)hipFree(d_out);
+    }
+};
+
+int make_tune_batch(const lz_ctx *c, TuneBatch &t) {
     const uint32_t B = c->prm.block_len;
-    // synthetic batch: about 1.5 resident rounds of single-chain lanes at 4 waves per SIMD,
-    // in messages of 64 full blocks plus a ragged tail, random bytes, distinct passwords
     const uint64_t chains = (uint64_t)c->dev.cus * 4 * 4 * 64 * 3 / 2;
     const uint64_t per_msg = 64;
     const size_t n_msg = (size_t)((chains + per_msg - 1) / per_msg);
-    std::vector<uint64_t> lens(n_msg), in_off(n_msg), out_off(n_msg), pw_off(n_msg);
-    std::vector<uint32_t> pw_len(n_msg);
-    std::vector<uint8_t> pw(n_msg * 16);
+    t.lens.resize(n_msg);
+    t.in_off.resize(n_msg);
+    t.out_off.resize(n_msg);
+    t.pw_off.resize(n_msg);
+    t.pw_len.resize(n_msg);
+    t.pw.resize(n_msg * 16);
     uint64_t tot_in = 0, tot_out = 0;
     uint64_t st = 0x9E3779B97F4A7C15ull;
     auto rnd = [&]() {
@@ -477,77 +529,174 @@ extern "C" int lz_autotune(lz_ctx *c, double budget_ms, lz_launch *best) {
         return st;
     };
     for (size_t i = 0; i < n_msg; ++i) {
-        lens[i] = per_msg * B - (i % 4 == 3 ? (rnd() % B) : 0);
-        in_off[i] = tot_in;
-        out_off[i] = tot_out;
-        tot_in += lens[i];
-        tot_out += lens[i] + LZ_TAG_BYTES;
-        pw_off[i] = 16 * i;
-        pw_len[i] = 16;
-        for (int q = 0; q < 16; ++q) pw[16 * i + q] = (uint8_t)(32 + rnd() % 95);
+        t.lens[i] = per_msg * B - (i % 4 == 3 ? (rnd() % B) : 0);
+        t.in_off[i] = tot_in;
+        t.out_off[i] = tot_out;
+        tot_in += t.lens[i];
+        tot_out += t.lens[i] + LZ_TAG_BYTES;
+        t.pw_off[i] = 16 * i;
+        t.pw_len[i] = 16;
+        for (int q = 0; q < 16; ++q) t.pw[16 * i + q] = (uint8_t)(32 + rnd() % 95);
     }
-    uint8_t *d_in = nullptr, *d_out = nullptr;
-    LZ_HIP(hipMalloc(&d_in, tot_in));
-    hipError_t e = hipMalloc(&d_out, tot_out);
-    if (e != hipSuccess) {
-        hipFree(d_in);
-        return hip_fail(e, "hipMalloc(autotune)");
-    }
-    {
-        std::vector<uint8_t> h(tot_in);
-        for (auto &v : h) v = (uint8_t)rnd();
-        e = hipMemcpy(d_in, h.data(), tot_in, hipMemcpyHostToDevice);
-    }
-    hipStream_t s = nullptr;
-    hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreate(&t0);
-    if (e == hipSuccess) e = hipEventCreate(&t1);
-    KernelShape best_sh = c->shape;
-    double best_ms = 1e30, spent = 0;
-    const int ms_[] = {1, 2, 4};
-    const int wps_[] = {1, 2, 4, 8};
-    const int wg_[] = {64, 256};
-    const int tile_[] = {64, 128};
-    int rc = LZ_OK;
-    for (int m : ms_)
-        for (int wps : wps_)
-            for (int wg : wg_)
-                for (int tile : tile_) {
-                    if (e != hipSuccess || rc != LZ_OK) break;
-                    if (m * wps < 4 || m * wps > 8) continue;  // 4..8 chains in flight per SIMD slot
-                    KernelShape sh{m, wg, tile, wps};
-                    if (!shape_valid(sh, c->dev)) continue;
-                    if (budget_ms > 0 && spent > budget_ms) continue;
-                    lz_launch l = to_launch(sh);
-                    lz_batch *b = nullptr;
-                    rc = lz_batch_create(c, 0, n_msg, lens.data(), in_off.data(), out_off.data(), pw.data(),
-                                         pw_off.data(), pw_len.data(), d_in, d_out, nullptr, &l, &b);
-                    if (rc != LZ_OK) break;
-                    double ms = 0;
-                    rc = lz_batch_launch(b, s);  // warm-up
-                    if (rc == LZ_OK) e = hipEventRecord(t0, s);
-                    if (rc == LZ_OK && e == hipSuccess) rc = lz_batch_launch(b, s);
-                    if (rc == LZ_OK && e == hipSuccess) e = hipEventRecord(t1, s);
-                    if (rc == LZ_OK && e == hipSuccess) e = hipEventSynchronize(t1);
-                    float f = 0;
-                    if (rc == LZ_OK && e == hipSuccess) e = hipEventElapsedTime(&f, t0, t1);
-                    ms = f;
-                    spent += 2 * ms;
-                    lz_batch_destroy(b);
-                    if (rc == LZ_OK && e == hipSuccess && ms < best_ms) {
-                        best_ms = ms;
-                        best_sh = sh;
-                    }
-                }
-    if (t0) hipEventDestroy(t0);
-    if (t1) hipEventDestroy(t1);
-    if (s) hipStreamDestroy(s);
-    hipFree(d_in);
-    hipFree(d_out);
+    LZ_HIP(hipMalloc(&t.d_in, tot_in));
+    LZ_HIP(hipMalloc(&t.d_out, tot_out));
+    std::vector<uint8_t> h(tot_in);
+    for (auto &v : h) v = (uint8_t)rnd();
+    LZ_HIP(hipMemcpy(t.d_in, h.data(), tot_in, hipMemcpyHostToDevice));
+    return LZ_OK;
+}
+
+// Time of one launch of the tuning batch in shape sh with parameters prm (after `warm` untimed
+// launches); *ms = -1 if the shape cannot run.
+int time_shape(lz_ctx *c, const lz_params &prm, const TuneBatch &t, const KernelShape &sh, int warm, hipStream_t s,
+               hipEvent_t e0, hipEvent_t e1, double *ms) {
+    lz_launch l = to_launch(sh);
+    lz_batch *b = nullptr;
+    *ms = -1;
+    int rc = batch_create(c, prm, 0, t.lens.size(), t.lens.data(), t.in_off.data(), t.out_off.data(), t.pw.data(),
+                          t.pw_off.data(), t.pw_len.data(), t.d_in, t.d_out, nullptr, &l, &b);
     if (rc != LZ_OK) return rc;
-    if (e != hipSuccess) return hip_fail(e, "autotune");
+    for (int i = 0; i < warm && rc == LZ_OK; ++i) rc = lz_batch_launch(b, s);
+    hipError_t e = hipSuccess;
+    if (rc == LZ_OK) e = hipEventRecord(e0, s);
+    if (rc == LZ_OK && e == hipSuccess) rc = lz_batch_launch(b, s);
+    if (rc == LZ_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+    if (rc == LZ_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    float f = 0;
+    if (rc == LZ_OK && e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+    batch_free(b);
+    if (rc != LZ_OK) return rc;
+    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+    *ms = f;
+    return LZ_OK;
+}
+
+}  // namespace
+
+extern "C" int lz_autotune(lz_ctx *c, double budget_ms, lz_launch *best) {
+    if (!c) return fail(LZ_E_INVAL, "ctx is NULL");
+    LZ_HIP(hipSetDevice(c->device));
+    TuneBatch t;
+    if (int rc = make_tune_batch(c, t)) return rc;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int rc = e == hipSuccess ? LZ_OK : hip_fail(e, "autotune stream");
+    // stage 1: every shape of the grid at a tenth of n_it (the same per-byte loop, a tenth of the
+    // time), one untimed launch for each kernel instance's first use
+    lz_params quick = c->prm;
+    quick.n_it = c->prm.n_it >= 30 ? c->prm.n_it / 10 : c->prm.n_it;
+    const std::vector<KernelShape> grid = shape_grid(c->shape, c->dev);
+    std::vector<std::pair<double, KernelShape>> ranked;
+    double spent = 0;
+    bool warmed[5] = {false, false, false, false, false};
+    for (const KernelShape &sh : grid) {
+        if (rc != LZ_OK || (budget_ms > 0 && spent > budget_ms && !ranked.empty())) break;
+        double ms = -1;
+        rc = time_shape(c, quick, t, sh, warmed[sh.m] ? 0 : 1, s, e0, e1, &ms);
+        warmed[sh.m] = true;
+        if (rc == LZ_OK && ms > 0) {
+            spent += ms;
+            ranked.emplace_back(ms, sh);
+        }
+    }
+    // stage 2: the three fastest at the context's n_it
+    KernelShape best_sh = c->shape;
+    double best_ms = 1e30;
+    std::stable_sort(ranked.begin(), ranked.end(),
+                     [](const std::pair<double, KernelShape> &a, const std::pair<double, KernelShape> &b) {
+                         return a.first < b.first;
+                     });
+    for (size_t i = 0; i < ranked.size() && i < 3 && rc == LZ_OK; ++i) {
+        double ms = -1;
+        rc = time_shape(c, c->prm, t, ranked[i].second, 1, s, e0, e1, &ms);
+        if (rc == LZ_OK && ms > 0 && ms < best_ms) {
+            best_ms = ms;
+            best_sh = ranked[i].second;
+        }
+    }
+    if (e1) (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (s) (void)hipStreamDestroy(s);
+    if (rc != LZ_OK) return rc;
     c->shape = best_sh;
+    c->tuned_ms = best_ms < 1e30 ? best_ms : 0;
     if (best) *best = to_launch(best_sh);
+    return LZ_OK;
+}
+
+namespace {
+
+// Key of a tuned shape: the device (gfx arch, CU count) and the parameters that shape the kernel's
+// work (integrator, n_it, block_len).
+std::string tune_key(const lz_ctx *c) {
+    char k[256];
+    std::snprintf(k, sizeof k, "%s cus=%d integrator=%u n_it=%u block_len=%u", c->arch, c->dev.cus,
+                  (unsigned)c->prm.integrator, c->prm.n_it, c->prm.block_len);
+    return k;
+}
+
+std::string default_tune_path() {
+    if (const char *p = std::getenv("LZ_TUNE_CACHE")) return p;
+    const char *home = std::getenv("HOME");
+    if (!home || !*home) return "";
+    return std::string(home) + "/.cache/lorenz_cipher/launch_shapes.tsv";
+}
+
+}  // namespace
+
+extern "C" int lz_autotune_cached(lz_ctx *c, const char *path, double budget_ms, lz_launch *best, int *from_cache) {
+    if (!c) return fail(LZ_E_INVAL, "ctx is NULL");
+    if (from_cache) *from_cache = 0;
+    const std::string file = path ? std::string(path) : default_tune_path();
+    const std::string key = tune_key(c);
+    std::vector<std::string> lines;
+    if (!file.empty()) {
+        if (FILE *f = std::fopen(file.c_str(), "r")) {
+            char buf[512];
+            while (std::fgets(buf, sizeof buf, f)) {
+                std::string line(buf);
+                while (!line.empty() && (line.back() == '\n' || line.back() == '\r')) line.pop_back();
+                const size_t tab = line.find('\t');
+                if (tab != std::string::npos && line.compare(0, tab, key) == 0 && tab == key.size()) {
+                    KernelShape sh{};
+                    if (std::sscanf(line.c_str() + tab + 1, "%d %d %d %d", &sh.m, &sh.wg, &sh.tile, &sh.wps) == 4 &&
+                        shape_valid(sh, c->dev)) {
+                        std::fclose(f);
+                        c->shape = sh;
+                        if (best) *best = to_launch(sh);
+                        if (from_cache) *from_cache = 1;
+                        return LZ_OK;
+                    }
+                    continue;  // a damaged entry is dropped and tuned again
+                }
+                if (!line.empty()) lines.push_back(line);
+            }
+            std::fclose(f);
+        }
+    }
+    lz_launch l;
+    if (int rc = lz_autotune(c, budget_ms, &l)) return rc;
+    if (best) *best = l;
+    if (file.empty()) return LZ_OK;
+    // rewrite the file with this entry added, through a temporary file and a rename
+    const size_t slash = file.rfind('/');
+    if (slash != std::string::npos && slash > 0) {
+        const std::string dir = file.substr(0, slash);
+        for (size_t p = 1; p <= dir.size(); ++p)
+            if (p == dir.size() || dir[p] == '/') (void)mkdir(dir.substr(0, p).c_str(), 0755);
+    }
+    char entry[512];
+    std::snprintf(entry, sizeof entry, "%s\t%u %u %u %u\t%.3f", key.c_str(), l.chains_per_lane, l.wg_size, l.tile,
+                  l.waves_per_simd, c->tuned_ms);
+    lines.push_back(entry);
+    const std::string tmp = file + ".tmp." + std::to_string((long)getpid());
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return LZ_OK;  // the shape is tuned and set; only the cache could not be written
+    for (const std::string &line : lines) std::fprintf(f, "%s\n", line.c_str());
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), file.c_str()) != 0) std::remove(tmp.c_str());
     return LZ_OK;
 }

@@ -1,11 +1,22 @@
 // Continuous-batching request loop (serving).  Each admitted request gets one
 // chain slot per block (block b of the parallel version, Section 5), a
 // device-side request record and arena space for its input and output bytes.
-// Every tick advances all unfinished chains by up to tick_bytes bytes with
-// the exact per-chain checkpoint (r, alpha, mu, Omega) kept in device memory,
-// so a request's bytes do not depend on what else is admitted.  Requests that
-// arrive while a tick runs are admitted at the next tick boundary, as chain
-// slots and the device-memory budget allow (FIFO, no overtaking).
+// A tick advances chains by up to tick_bytes bytes with the exact per-chain
+// checkpoint (r, alpha, mu, Omega) kept in device memory, so a request's bytes
+// do not depend on what else is admitted or when its chains run.  Requests
+// that arrive while a tick runs are admitted at the next tick boundary, as
+// chain slots and the device-memory budget allow (FIFO, no overtaking).
+//
+// Every chain of a tick advances at the pace of the most loaded SIMD.  Under
+// the adaptive policy a tick holds at most k waves per SIMD, with k chosen
+// from the backlog (the unfinished chains of admitted and waiting requests):
+// one wave while the backlog is at most 3 waves per SIMD, so that each chain
+// runs at its single-wave pace and the rest wait their turn; two up to 6
+// waves; then doubling, up to run_waves, where a tick issues as densely as the
+// plain kernel.  The tick takes requests in admission order, each with all of
+// its unfinished chains or not at all, and fills the room a large request
+// leaves with later ones that fit.  The all-chains policy runs every admitted
+// chain in every tick.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -90,7 +101,7 @@ struct Request {
     uint32_t req_slot = 0;
     uint32_t nb = 0;
     std::vector<uint32_t> slots;  // chain slot of block b
-    size_t active_idx = 0;
+    bool released = false;    // resources returned; leaves the active list at the next compaction
     uint64_t arena_off = 0, arena_bytes = 0;
     uint32_t ticks_full = 0, ticks_tail = 0;  // ticks until full / tail chains finish
     uint32_t ticks_run = 0;
@@ -108,6 +119,8 @@ uint64_t in_len(const Request &r) { return r.decrypt ? r.n + LZ_TAG_BYTES : r.n;
 uint64_t out_len(const Request &r) { return r.decrypt ? r.n : r.n + LZ_TAG_BYTES; }
 
 uint64_t pieces_of(uint64_t bytes) { return (bytes + COPY_PIECE_BYTES - 1) / COPY_PIECE_BYTES; }
+
+uint64_t chains_of(const Request &r, uint32_t block_len) { return r.n == 0 ? 1 : (r.n + block_len - 1) / block_len; }
 
 // Device memory of any device is copied by kernels; everything else (pageable or
 // pinned host memory) by hipMemcpyAsync.
@@ -163,6 +176,8 @@ struct lz_server {
     lz_server_config cfg;
     KernelShape shape;
     uint32_t max_chains, max_reqs, max_new;
+    uint64_t simd_chains;  // chains of one wave on every SIMD of the device
+    uint64_t waiting_chains = 0;  // chains of the requests in `waiting`
     // device memory
     uint8_t *arena_mem = nullptr;
     ChainSlot *slots = nullptr;
@@ -181,8 +196,8 @@ struct lz_server {
     std::vector<uint32_t> free_slots;
     std::vector<uint32_t> free_reqs;
     std::vector<Request *> by_slot;
-    std::vector<Request *> active;
-    std::deque<Request *> waiting;  // arrived, not admitted (FIFO)
+    std::vector<Request *> active;  // admitted, in admission order
+    std::deque<Request *> waiting;  // arrived, not admitted (FIFO); their chains: waiting_chains
     uint64_t hbm_fixed = 0;
     uint64_t tick_seq = 0, done_seq = 0;  // last tick queued, last tick completed (ticks complete in order)
     // shared with submitters / pollers
@@ -222,10 +237,11 @@ void admit(lz_server *s, std::vector<Request *> &admitted) {
     uint64_t staged_chains = 0, staged_pieces = 0;
     while (!s->waiting.empty() && admitted.size() < s->max_new) {
         Request *r = s->waiting.front();
-        const uint64_t nb64 = r->n == 0 ? 1 : (r->n + B - 1) / B;
+        const uint64_t nb64 = chains_of(*r, B);
         const uint64_t bytes = ((in_len(*r) + 255) / 256 + (out_len(*r) + 255) / 256) * 256;
         if (nb64 > s->max_chains || bytes > s->arena.size()) {  // can never fit
             s->waiting.pop_front();
+            s->waiting_chains -= nb64;
             finish(s, r, LZ_E_NOMEM, lz_now_ns());
             continue;
         }
@@ -237,6 +253,7 @@ void admit(lz_server *s, std::vector<Request *> &admitted) {
         uint64_t off;
         if (!s->arena.alloc(bytes, off)) break;
         s->waiting.pop_front();
+        s->waiting_chains -= nb64;
         r->slots.assign(s->free_slots.end() - nb, s->free_slots.end());
         s->free_slots.resize(s->free_slots.size() - nb);
         staged_chains += nb;
@@ -265,6 +282,7 @@ uint8_t *req_in(lz_server *s, const Request *r) { return s->arena_mem + r->arena
 uint8_t *req_out(lz_server *s, const Request *r) { return req_in(s, r) + (in_len(*r) + 255) / 256 * 256; }
 
 void release(lz_server *s, Request *r);
+void compact_active(lz_server *s);
 
 // Reads a finished tick's completions, zeroes failed decryptions, copies the
 // outputs out, frees the requests' slots and memory and reports them.
@@ -322,24 +340,26 @@ int complete_tick(lz_server *s, TickSlot &t) {
     if (int rc = flush_out()) return rc;
     LZ_HIP(hipStreamSynchronize(cs));
     const uint64_t now = lz_now_ns();
-    for (auto &f : fin) {
-        release(s, f.first);
-        finish(s, f.first, f.second, now);
-    }
+    for (auto &f : fin) release(s, f.first);
+    compact_active(s);
+    for (auto &f : fin) finish(s, f.first, f.second, now);
     return LZ_OK;
 }
 
-// Frees an admitted request's chain slots, request slot and memory and takes it off
-// the active list (its chains are in no tick still in flight).
+// Frees an admitted request's chain slots, request slot and memory (its chains are in
+// no tick still in flight) and marks it for compact_active.
 void release(lz_server *s, Request *r) {
     s->arena.release(r->arena_off, r->arena_bytes);
     s->free_slots.insert(s->free_slots.end(), r->slots.begin(), r->slots.end());
     s->free_reqs.push_back(r->req_slot);
     s->by_slot[r->req_slot] = nullptr;
-    Request *last = s->active.back();  // swap-remove
-    s->active[r->active_idx] = last;
-    last->active_idx = r->active_idx;
-    s->active.pop_back();
+    r->released = true;
+}
+
+// Takes the released requests off the active list, keeping the admission order.
+void compact_active(lz_server *s) {
+    s->active.erase(std::remove_if(s->active.begin(), s->active.end(), [](const Request *r) { return r->released; }),
+                    s->active.end());
 }
 
 // Applies the cancellations queued by lz_server_cancel: a request not yet admitted
@@ -357,6 +377,7 @@ void apply_cancels(lz_server *s) {
         if (w != s->waiting.end()) {
             Request *r = *w;
             s->waiting.erase(w);
+            s->waiting_chains -= chains_of(*r, s->ctx->prm.block_len);
             finish(s, r, LZ_E_CANCELLED, lz_now_ns());
             continue;
         }
@@ -383,12 +404,15 @@ void apply_cancels(lz_server *s) {
 // Completes the cancelled active requests whose last tick has completed.
 void release_cancelled(lz_server *s) {
     const uint64_t now = lz_now_ns();
-    for (size_t i = s->active.size(); i-- > 0;) {
-        Request *r = s->active[i];
+    std::vector<Request *> gone;
+    for (Request *r : s->active) {
         if (!r->cancelled || r->last_tick > s->done_seq) continue;
         release(s, r);
-        finish(s, r, LZ_E_CANCELLED, now);
+        gone.push_back(r);
     }
+    if (gone.empty()) return;
+    compact_active(s);
+    for (Request *r : gone) finish(s, r, LZ_E_CANCELLED, now);
 }
 
 // One scheduling step: admit into the free tick slot, queue its tick, then
@@ -433,7 +457,6 @@ int server_step(lz_server *s) {
             n_idx += r->nb;
             if (in_len(*r) && r->src_dev) add_pieces(t.h_in, n_in, r->src, req_in(s, r), in_len(*r));
             else if (in_len(*r)) LZ_HIP(hipMemcpyAsync(req_in(s, r), r->src, in_len(*r), hipMemcpyDefault, pre));
-            r->active_idx = s->active.size();
             s->active.push_back(r);
         }
         if (n_in) {
@@ -448,12 +471,28 @@ int server_step(lz_server *s) {
     // the chains that still have bytes to process: each request's full chains until they end,
     // its last chain until it ends (the tick count of each is known at admission)
     const uint32_t T = s->cfg.tick_bytes, B = s->ctx->prm.block_len;
+    auto unfinished = [&](const Request *r) -> uint32_t {
+        const uint32_t tr = r->ticks_run;
+        return (tr < r->ticks_full ? r->nb - 1 : 0) + (tr < r->ticks_tail ? 1 : 0);
+    };
+    // waves per SIMD of this tick, from the backlog
+    uint64_t backlog = s->waiting_chains;
+    for (const Request *r : s->active)
+        if (!r->cancelled) backlog += unfinished(r);
+    uint32_t k = 1;
+    while (k < s->cfg.run_waves && backlog > 3 * s->simd_chains * k) k = std::min(2 * k, s->cfg.run_waves);
+    const uint64_t cap = s->cfg.policy == LZ_SERVE_ALL_CHAINS ? s->max_chains
+                                                                : std::min<uint64_t>(k * s->simd_chains, s->max_chains);
+    // requests join in admission order, all their unfinished chains or none, up to the cap; the
+    // first request with work always joins, so one larger than the cap still runs
     uint32_t n_list = 0;
     uint64_t tick_bytes = 0;
     const uint64_t seq = s->tick_seq + 1;
     for (Request *r : s->active) {
         if (r->cancelled) continue;
         const uint32_t tr = r->ticks_run;
+        const uint32_t want = unfinished(r);
+        if (want == 0 || (n_list && (uint64_t)n_list + want > cap)) continue;
         if (tr < r->ticks_full) {
             std::memcpy(t.h_list + n_list, r->slots.data(), (r->nb - 1) * sizeof(uint32_t));
             n_list += r->nb - 1;
@@ -513,6 +552,7 @@ void server_loop(lz_server *s) {
                 while (!s->pending.empty() && s->pending.front()->arrival_ns <= now) {
                     std::pop_heap(s->pending.begin(), s->pending.end(), ArrivalLater());
                     s->waiting.push_back(s->pending.back());
+                    s->waiting_chains += chains_of(*s->waiting.back(), s->ctx->prm.block_len);
                     s->pending.pop_back();
                 }
                 if (busy(s) || !s->cancels.empty()) break;
@@ -594,13 +634,23 @@ extern "C" int lz_server_create(lz_ctx *c, const lz_server_config *cfg, lz_serve
         delete s;
         return fail(LZ_E_INVAL, "tick_bytes must be <= 2^20");
     }
-    s->max_chains = cfg->max_chains ? cfg->max_chains : (uint32_t)c->dev.cus * 4 * 4 * 64;
+    if (s->cfg.run_waves > 8 || s->cfg.policy > LZ_SERVE_ALL_CHAINS) {
+        delete s;
+        return fail(LZ_E_INVAL, "run_waves must be <= 8 and policy LZ_SERVE_ADAPTIVE or LZ_SERVE_ALL_CHAINS");
+    }
+    if (s->cfg.run_waves == 0) s->cfg.run_waves = 4;
+    s->simd_chains = (uint64_t)c->dev.cus * 4 * WAVE_LANES;
+    // admitted chains: adaptive, twice the largest tick, so that a tick can be filled from requests
+    // behind a large one; all chains, the largest tick
+    const uint64_t def_chains = (s->cfg.policy == LZ_SERVE_ALL_CHAINS ? 1 : 2) * s->cfg.run_waves * s->simd_chains;
+    s->max_chains = cfg->max_chains ? cfg->max_chains : (uint32_t)def_chains;
     s->max_reqs = s->max_chains;
     s->max_new = std::min<uint32_t>(s->max_reqs, 2048);  // admissions per tick (staging size)
     int tile = 16;
     while (tile < (int)s->cfg.tick_bytes && tile < 128) tile *= 2;
     s->shape = KernelShape{1, 256, tile, 4};
     if (!shape_valid(s->shape, c->dev)) s->shape = KernelShape{1, 64, 16, 4};
+
     // fixed device memory: chain slots, request records, and per tick slot the list, the
     // completion queue and the staging of admitted requests
     const uint64_t per_tick = (uint64_t)s->max_chains * 4 * 2 + ((uint64_t)s->max_reqs + 2) * 4 +

@@ -74,6 +74,15 @@ def tamper_plan(ct_lens, frac: float = 0.1, seed: int | None = None):
     return idx, offs, vals
 
 
+# Offered loads of the serving runs, fixed: QPS = load x capacity / mean request size, with the
+# capacity 0.90 GB/s per direction of the plain path at 64 MiB on one MI355X (encrypt 0.8998 GB/s)
+# and the mean request size 50,115.4 bytes of the 200,000-request trace below (seed 104).
+SERVE_CAPACITY_GBPS = 0.90
+SERVE_MEAN_REQUEST_BYTES = 50115.4
+SERVE_QPS = {load: round(load * SERVE_CAPACITY_GBPS * 1e9 / SERVE_MEAN_REQUEST_BYTES, 1)
+             for load in (0.3, 0.5, 0.7, 0.9)}
+
+
 @dataclass
 class ServeTrace:
     arrival_s: np.ndarray    # seconds from the trace start

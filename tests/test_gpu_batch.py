@@ -210,3 +210,35 @@ def test_autotune_picks_a_valid_shape_and_keeps_results(lz):
         assert np.array_equal(C[int(out_off[i]):int(out_off[i]) + sizes[i] + 24], want), i
         if sizes[i]:
             assert np.array_equal(host(ctx.encrypt(to_dev(P), pws[i])), want), i
+
+
+def test_autotune_cache_per_device(lz, tmp_path):
+    """lz_autotune_cached tunes once and writes one entry keyed by the device and the parameters; the
+    next call (another context) takes the shape from the file; another n_it is another entry; a damaged
+    entry is dropped and tuned again."""
+    path = str(tmp_path / "shapes.tsv")
+    ctx = lz.Context(0, lz.params(n_it=20))
+    shape, hit = ctx.autotune_cached(path)
+    assert not hit and ctx.get_launch() == shape
+    lines = open(path).read().splitlines()
+    say("cache after tuning:", lines)
+    assert len(lines) == 1 and "n_it=20" in lines[0] and "gfx" in lines[0]
+    key, val, ms = lines[0].split("\t")
+    assert [int(v) for v in val.split()] == [shape.chains_per_lane, shape.wg_size, shape.tile, shape.waves_per_simd]
+    assert float(ms) > 0
+    ctx2 = lz.Context(0, lz.params(n_it=20))
+    shape2, hit2 = ctx2.autotune_cached(path)
+    assert hit2 and shape2 == shape and ctx2.get_launch() == shape
+    ctx3 = lz.Context(0, lz.params(n_it=21))
+    _, hit3 = ctx3.autotune_cached(path)
+    assert not hit3 and len(open(path).read().splitlines()) == 2
+    # damage the n_it=20 entry: an invalid tile
+    text = open(path).read().replace(val, "1 256 100 4")
+    open(path, "w").write(text)
+    ctx4 = lz.Context(0, lz.params(n_it=20))
+    shape4, hit4 = ctx4.autotune_cached(path)
+    assert not hit4 and shape4.tile in (16, 32, 64, 128)
+    lines = open(path).read().splitlines()
+    assert len(lines) == 2 and sum("n_it=20" in l for l in lines) == 1 and "1 256 100 4" not in open(path).read()
+    for c in (ctx, ctx2, ctx3, ctx4):
+        c.close()

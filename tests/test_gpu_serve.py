@@ -298,6 +298,8 @@ def test_server_and_stream_argument_errors(lz):
         lz.Server(ctx, hbm_budget=1 << 16)                    # smaller than the fixed part
     with pytest.raises(lz.LorenzError):
         lz.Server(ctx, hbm_budget=1 << 30, tick_bytes=(1 << 20) + 1)
+    with pytest.raises(lz.LorenzError):
+        lz.Server(ctx, hbm_budget=1 << 30, run_waves=9)                     # more than 8 waves per SIMD
     srv = lz.Server(ctx, hbm_budget=1 << 28, max_chains=1024, tick_bytes=16)
     buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
     with pytest.raises(lz.LorenzError):
@@ -343,3 +345,65 @@ def test_serve_slot_reuse_stress(lz, max_chains, budget, tick):
         assert got[r["id"]][1] == 0, r["id"]
         n_out = r["n"] if r["dec"] else r["n"] + 24
         assert np.array_equal(host(r["dst"])[:n_out], _expected(ctx, r)), (r["id"], r["n"], r["dec"])
+
+
+# (policy, run_waves, chains of each request in units of one wave per SIMD, ticks, requests that finish last)
+TICK_CASES = [
+    # one wave per SIMD at most: A, C and D share the first 16 ticks, B (over the cap) runs alone after them
+    ("adaptive", 1, [0.5, 1.0625, 0.25, 3], 32, {1}),
+    # backlog 1.8 waves (at most 3): one wave per SIMD, the same schedule
+    ("adaptive", 4, [0.5, 1.0625, 0.25, 3], 32, {1}),
+    # every admitted chain in every tick
+    ("all_chains", 4, [0.5, 1.0625, 0.25, 3], 16, set()),
+    # backlog 2.7 waves: one wave per SIMD, the requests one after another
+    ("adaptive", 4, [0.9, 0.9, 0.9], 48, {1, 2}),
+    # backlog 3.6 waves: two waves per SIMD for A and B; then 1.8 waves: one wave, C, then D
+    ("adaptive", 4, [0.9, 0.9, 0.9, 0.9], 48, {2, 3}),
+    # backlog 6.3 waves: four waves per SIMD for A..D; then 2.7 waves: one wave, E, F, G in turn
+    ("adaptive", 4, [0.9] * 7, 64, {4, 5, 6}),
+]
+
+
+@pytest.mark.parametrize("policy,run_waves,units,ticks,last", TICK_CASES)
+def test_serve_tick_cap_and_backfill(lz, policy, run_waves, units, ticks, last):
+    """More chains than one tick may run: a tick holds 1 wave per SIMD while the backlog is at most 3
+    waves, 2 up to 6 waves, then up to run_waves; requests join it in admission order, whole or not at
+    all, later ones fill the room an earlier one leaves, and a request larger than the cap still runs.
+    An integer entry of `units` is a chain count, a fraction is that part of one wave on every SIMD."""
+    import torch
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    wave = 4 * 64 * cus
+    ctx = lz.Context(0, lz.params(n_it=3))
+    rng = np.random.default_rng(460 + run_waves + len(units) + len(policy))
+    B = 256
+    reqs = []
+    for i, u in enumerate(units):
+        nb = u if isinstance(u, int) else int(u * wave)
+        n = nb * B - int(rng.integers(0, B))
+        pw = bytes(rng.integers(32, 127, 20, dtype=np.uint8))
+        P = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda")
+        dec = i % 2 == 1
+        if dec:
+            src, dst = ctx.encrypt(P, pw), torch.zeros(n, dtype=torch.uint8, device="cuda")
+        else:
+            src, dst = P, torch.zeros(n + 24, dtype=torch.uint8, device="cuda")
+        reqs.append(dict(id=i, n=n, pw=pw, P=P, dec=dec, src=src, dst=dst))
+    torch.cuda.synchronize()
+    srv = lz.Server(ctx, hbm_budget=4 << 30, tick_bytes=16, run_waves=run_waves, policy=policy)
+    at = lz.now_ns() + 20_000_000
+    srv.submit_many([r["id"] for r in reqs], [r["dec"] for r in reqs], [r["pw"] for r in reqs],
+                    [r["src"].data_ptr() for r in reqs], [r["n"] for r in reqs], [r["dst"].data_ptr() for r in reqs],
+                    [at] * len(reqs))
+    got = _drain(srv, len(reqs), timeout_s=120)
+    st = srv.stats()
+    srv.close()
+    say(f"{policy}, run_waves {run_waves}, units {units}: ticks {st['ticks']}, done ns", {i: got[i][4] - at for i in got})
+    for r in reqs:
+        assert got[r["id"]][1] == 0, r["id"]
+        n_out = r["n"] if r["dec"] else r["n"] + 24
+        assert torch.equal(r["dst"][:n_out], torch.from_numpy(_expected(ctx, r)).cuda()), r["id"]
+    assert st["ticks"] == ticks
+    done = {i: got[i][4] for i in got}
+    if last:
+        assert max(done[i] for i in done if i not in last) < min(done[i] for i in last)
