@@ -51,29 +51,32 @@ def fp64_ops_per_byte(n_it: int, integrator: str = "euler") -> int:
 
 
 def kernel_stamp() -> str:
-    """First 16 hex digits of sha256 over the kernel and runtime sources and the build script
-    (its compiler flags shape the kernels' code)."""
+    """First 16 hex digits of sha256 over the kernel source and the build script (its compiler
+    flags shape the kernels' code)."""
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("csrc/kernels.hip", "csrc/runtime.cpp", "build.py"):
+    for f in ("csrc/kernels.hip", "build.py"):
         with open(os.path.join(ROOT, "paper_1201_3114_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def profiled_traffic():
+def profiled_traffic(launch):
     """HBM bytes per plain-kernel launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None when the kernel sources have
-    changed since the counters were taken."""
+    (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None when the kernel's code or the launch
+    shape differ from those the counters were taken with."""
     path = os.path.join(ROOT, "profiles", "plain_kernel_64MiB.md")
     try:
         text = open(path).read()
     except OSError:
         return None
     fields = dict(line.split(":", 1) for line in text.splitlines()
-                  if line.startswith(("kernel_source_stamp:", "traffic_bytes_per_launch:")))
+                  if line.startswith(("kernel_source_stamp:", "traffic_bytes_per_launch:", "launch_shape:")))
     if fields.get("kernel_source_stamp", "").strip() != kernel_stamp():
+        return None
+    shape = " ".join(str(launch[k]) for k in ("chains_per_lane", "wg_size", "tile"))
+    if fields.get("launch_shape", "").strip() != shape:
         return None
     try:
         return int(fields["traffic_bytes_per_launch"].strip())
@@ -727,7 +730,7 @@ def main():
                    host_buffers_GBps=2 * n / (plain["pcie_ms"] / 1e3) / GB,
                    latency_64KiB_ms={"encrypt": plain["lat64"][0], "decrypt": plain["lat64"][1]},
                    roofline={"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VALU_OPS_PEAK / 1e12,
-                             "unit": "TFLOP/s", "frac": achieved / FP64_VALU_OPS_PEAK, "traffic": profiled_traffic(),
+                             "unit": "TFLOP/s", "frac": achieved / FP64_VALU_OPS_PEAK, "traffic": profiled_traffic(vars(sh)),
                              "traffic_unit": "bytes per launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)",
                              "algorithmic_bytes_per_launch": 2 * n + 24,
                              "kernel": "plain_kernel (binary64 VALU, one op per lane per clock)",

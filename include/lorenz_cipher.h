@@ -166,7 +166,10 @@ int lz_context_destroy(lz_ctx *ctx);
 int lz_context_params(const lz_ctx *ctx, lz_params *out);
 
 /* Sets (shape non-NULL) the launch shape used by the plain path and by
- * batches created later, after validating it; LZ_E_INVAL if out of range. */
+ * batches created later, after validating it; LZ_E_INVAL if out of range.
+ * The plain path takes chains_per_lane > 1 only for a message of at least
+ * 2 x chains_per_lane waves' worth of blocks per SIMD (more chains per lane
+ * lengthen each chain's latency); smaller messages run one chain per lane. */
 int lz_context_set_launch(lz_ctx *ctx, const lz_launch *shape);
 int lz_context_get_launch(const lz_ctx *ctx, lz_launch *out);
 

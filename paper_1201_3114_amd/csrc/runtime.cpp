@@ -80,6 +80,15 @@ lz_launch to_launch(const KernelShape &s) {
     return l;
 }
 
+// Launch shape of the plain path for a message of nb blocks: several chains per lane trade each
+// chain's latency for issue density, so they are used only when the message gives every SIMD at
+// least two waves of them.
+KernelShape plain_shape(const lz_ctx *c, uint64_t nb) {
+    KernelShape sh = c->shape;
+    if (sh.m > 1 && nb < (uint64_t)sh.m * c->dev.cus * 4 * WAVE_LANES * 2) sh.m = 1;
+    return sh;
+}
+
 // Orders a call on stream s after the previous call that used the same
 // workspace (possibly on another stream).
 int order_after(hipStream_t s, hipStream_t &last_stream, hipEvent_t ev, bool &has_last) {
@@ -229,12 +238,13 @@ extern "C" int lz_context_get_launch(const lz_ctx *c, lz_launch *out) {
 extern "C" int lz_encrypt_key(lz_ctx *c, const lz_key *key, const uint8_t *d_P, size_t n, uint8_t *d_C,
                               void *stream) {
     if (!c || !key || !d_C || (!d_P && n)) return fail(LZ_E_INVAL, "NULL argument");
-    if (int rc = check_blocks(c->prm, n, nullptr)) return rc;
+    uint64_t nb = 0;
+    if (int rc = check_blocks(c->prm, n, &nb)) return rc;
     hipStream_t s = (hipStream_t)stream;
     LZ_HIP(hipSetDevice(c->device));
     if (int rc = order_after(s, c->last_stream, c->last_event, c->has_last)) return rc;
     LZ_HIP(launch_fill_u64(c->ws_tag, 3, s));
-    LZ_HIP(launch_plain(c->shape, *key, c->prm, 0, d_P, d_C, n, c->ws_tag, s));
+    LZ_HIP(launch_plain(plain_shape(c, nb), *key, c->prm, 0, d_P, d_C, n, c->ws_tag, s));
     LZ_HIP(launch_plain_finalize(0, c->ws_tag, nullptr, d_C + n, nullptr, nullptr, n, s));
     return record(s, c->last_stream, c->last_event, c->has_last);
 }
@@ -244,14 +254,15 @@ extern "C" int lz_decrypt_key(lz_ctx *c, const lz_key *key, const uint8_t *d_C, 
     if (!c || !key || !d_C) return fail(LZ_E_INVAL, "NULL argument");
     if (n_c < LZ_TAG_BYTES) return fail(LZ_E_INVAL, "ciphertext shorter than the 24-byte tag");
     const size_t n = n_c - LZ_TAG_BYTES;
-    if (int rc = check_blocks(c->prm, n, nullptr)) return rc;
+    uint64_t nb = 0;
+    if (int rc = check_blocks(c->prm, n, &nb)) return rc;
     if (!d_P && n) return fail(LZ_E_INVAL, "NULL plaintext buffer");
     hipStream_t s = (hipStream_t)stream;
     LZ_HIP(hipSetDevice(c->device));
     if (int rc = order_after(s, c->last_stream, c->last_event, c->has_last)) return rc;
     int32_t *st = d_status ? d_status : c->ws_status;
     LZ_HIP(launch_fill_u64(c->ws_tag, 3, s));
-    LZ_HIP(launch_plain(c->shape, *key, c->prm, 1, d_C, d_P, n, c->ws_tag, s));
+    LZ_HIP(launch_plain(plain_shape(c, nb), *key, c->prm, 1, d_C, d_P, n, c->ws_tag, s));
     LZ_HIP(launch_plain_finalize(1, c->ws_tag, d_C + n, nullptr, st, d_P, n, s));
     if (d_status) return record(s, c->last_stream, c->last_event, c->has_last);
     LZ_HIP(hipMemcpyAsync(c->host_status, c->ws_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));

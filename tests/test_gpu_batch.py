@@ -232,8 +232,9 @@ def test_autotune_cache_per_device(lz, tmp_path):
     ctx3 = lz.Context(0, lz.params(n_it=21))
     _, hit3 = ctx3.autotune_cached(path)
     assert not hit3 and len(open(path).read().splitlines()) == 2
-    # damage the n_it=20 entry: an invalid tile
-    text = open(path).read().replace(val, "1 256 100 4")
+    # damage the n_it=20 entry (only that line): an invalid tile
+    text = "".join((l.replace(val, "1 256 100 4") if "n_it=20" in l else l) + "\n"
+                   for l in open(path).read().splitlines())
     open(path, "w").write(text)
     ctx4 = lz.Context(0, lz.params(n_it=20))
     shape4, hit4 = ctx4.autotune_cached(path)
