@@ -718,6 +718,146 @@ __global__ __launch_bounds__(DIAG_WG) void fft_pass_kernel(const In *src, uint32
 
 // ---- the same pass by mixed-radix FFT, for lengths 2^a 3^b 5^c --------------------------
 //
+// ---- 1024-point pass: one wave per column, three register stages -----------------------
+//
+// With n = t + 64 j and k = k1 + 16 k2 (t, k2 < 64; j, k1 < 16),
+//   X[k1 + 16 k2] = sum_t W_64^{t k2} [W_1024^{t k1} sum_j x[t + 64 j] W_16^{j k1}],
+// and the 64-point DFTs over t split again as t = a + 4 b, k2 = c + 16 d (a, d < 4; b, c < 16):
+//   Y[c + 16 d] = sum_a W_4^{a d} [W_64^{a c} sum_b y[a + 4 b] W_16^{b c}].
+// Lane t of a column's wave loads x[t + 64 j] (16 values), takes their 16-point DFT in registers
+// and the twiddles W_1024^{t k1}; through LDS, lane (k1, a) = (t / 4, t % 4) takes the 16 values
+// y[a + 4 b] of its k1, their 16-point DFT and the twiddles W_64^{a c}; through LDS again, each
+// lane takes four 4-point DFTs over a and stores X[k1 + 16 c + 256 d], 64 consecutive outputs per
+// store.  The LDS row strides (68 and 258 entries of 16 bytes) put the 8 lanes of each 128-byte
+// LDS cycle on distinct banks in every exchange.  The workgroup makes the quarter twiddle table
+// W^b, b < 256, while its loads are in flight.  A 16-point DFT is 4 x 4: 4-point DFTs, the
+// twiddles W_16^{n2 k1}, 4-point DFTs.
+constexpr uint32_t FFT1K = 1024;
+constexpr int FFT1K_COLS = DIAG_WG / 64;  // columns per workgroup, one per wave
+constexpr int FFT1K_S1 = 68;              // LDS row stride of the stage-1 output (rows k1)
+constexpr int FFT1K_S2 = 258;             // LDS row stride of the stage-2 output (rows a)
+constexpr int FFT1K_WAVE = 16 * FFT1K_S1; // LDS entries per wave (the stage-2 output fits in them)
+
+static_assert(DIAG_WG == FFT1K / 4, "one quarter-table entry per thread");
+
+// Orders a wave's LDS accesses before and after this point for the compiler; the wave's own
+// LDS operations complete in order, so its lanes then see each other's stores.
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__host__ __device__ constexpr size_t fft1k_lds() { return ((size_t)FFT1K_COLS * FFT1K_WAVE + FFT1K / 4) * 16; }
+
+// z (sign i)^q
+__device__ __forceinline__ double2 rot_q(double2 z, uint32_t q, double sign) {
+    switch (q & 3) {
+        case 0: return z;
+        case 1: return make_double2(-sign * z.y, sign * z.x);
+        case 2: return make_double2(-z.x, -z.y);
+        default: return make_double2(sign * z.y, -sign * z.x);
+    }
+}
+
+// W^j, j < 1024, from the quarter table q[b] = W^b (b < 256)
+__device__ __forceinline__ double2 tw1k(const double2 *q, uint32_t j, double sign) {
+    return rot_q(q[j & 255], j >> 8, sign);
+}
+
+__device__ __forceinline__ void dft4(double2 &a0, double2 &a1, double2 &a2, double2 &a3, double sign) {
+    const double2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = rot_q(csub(a1, a3), 1, sign);
+    a0 = cadd(t0, t2);
+    a1 = cadd(t1, t3);
+    a2 = csub(t0, t2);
+    a3 = csub(t1, t3);
+}
+
+// v[k] <- sum_n v[n] W_16^{n k}, W_16 = e^{sign 2 pi i / 16}
+__device__ __forceinline__ void dft16(double2 (&v)[16], double sign) {
+    constexpr double C1 = 0.92387953251128674;  // cos(pi / 8)
+    constexpr double S1 = 0.38268343236508977;  // sin(pi / 8)
+    constexpr double R2 = 0.70710678118654752;  // cos(pi / 4)
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[4 + n2], v[8 + n2], v[12 + n2], sign);
+    // v[4 k1 + n2] now holds A[n2][k1]; twiddles W_16^{n2 k1}
+    v[5] = cmul(v[5], make_double2(C1, sign * S1));     // n2 = 1, k1 = 1
+    v[9] = cmul(v[9], make_double2(R2, sign * R2));     // 1, 2
+    v[13] = cmul(v[13], make_double2(S1, sign * C1));   // 1, 3
+    v[6] = cmul(v[6], make_double2(R2, sign * R2));     // 2, 1
+    v[10] = rot_q(v[10], 1, sign);                      // 2, 2
+    v[14] = cmul(v[14], make_double2(-R2, sign * R2));  // 2, 3
+    v[7] = cmul(v[7], make_double2(S1, sign * C1));     // 3, 1
+    v[11] = cmul(v[11], make_double2(-R2, sign * R2));  // 3, 2
+    v[15] = cmul(v[15], make_double2(-C1, -sign * S1)); // 3, 3
+    double2 u[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        double2 a0 = v[4 * k1], a1 = v[4 * k1 + 1], a2 = v[4 * k1 + 2], a3 = v[4 * k1 + 3];
+        dft4(a0, a1, a2, a3, sign);
+        u[k1] = a0;
+        u[k1 + 4] = a1;
+        u[k1 + 8] = a2;
+        u[k1 + 12] = a3;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = u[k];
+}
+
+template <typename In, int E>
+__global__ __launch_bounds__(DIAG_WG) void fft1k_pass_kernel(const In *src, uint32_t M, double sign, PassOut dst) {
+    extern __shared__ double2 fbuf[];
+    const uint32_t lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    double2 *L = fbuf + (size_t)wave * FFT1K_WAVE;
+    double2 *q = fbuf + (size_t)FFT1K_COLS * FFT1K_WAVE;
+    // consecutive column groups on the same XCD (workgroups are dealt to the 8 XCDs in turn)
+    uint32_t g = blockIdx.x;
+    if (gridDim.x % 8 == 0) g = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    const uint32_t col = g * FFT1K_COLS + wave;
+    const bool live = col < M;
+    In x[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        if (live) x[j] = src[(size_t)(lane + 64 * j) * M + col];
+    {
+        double sn, cs;
+        sincospi(2.0 * (double)threadIdx.x / (double)FFT1K, &sn, &cs);
+        q[threadIdx.x] = make_double2(cs, sign * sn);
+    }
+    __syncthreads();
+    if (!live) return;
+    double2 v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = dft_value(x[j]);
+    // stage 1: 16-point DFT over j, twiddles W^{t k1}
+    dft16(v, sign);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) L[k1 * FFT1K_S1 + lane] = k1 ? cmul(v[k1], tw1k(q, lane * k1, sign)) : v[0];
+    wave_fence();
+    // stage 2: lane (k1, a) takes y[a + 4 b][k1], a 16-point DFT over b, twiddles W_64^{a c}
+    const uint32_t k1 = lane >> 2, a = lane & 3;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) v[b] = L[k1 * FFT1K_S1 + a + 4 * b];
+    wave_fence();
+    dft16(v, sign);
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        L[a * FFT1K_S2 + c * 16 + k1] = (a && c) ? cmul(v[c], tw1k(q, 16 * a * c, sign)) : v[c];
+    wave_fence();
+    // stage 3: 4-point DFTs over a of pairs p = 16 c + k1 = 64 i + lane; X[p + 256 d]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t p = 64 * i + lane;
+        double2 a0 = L[p], a1 = L[FFT1K_S2 + p], a2 = L[2 * FFT1K_S2 + p], a3 = L[3 * FFT1K_S2 + p];
+        dft4(a0, a1, a2, a3, sign);
+        const size_t o = (size_t)col * FFT1K + p;
+        pass_store<E>(dst, o, a0.x, a0.y);
+        pass_store<E>(dst, o + 256, a1.x, a1.y);
+        pass_store<E>(dst, o + 512, a2.x, a2.y);
+        pass_store<E>(dst, o + 768, a3.x, a3.y);
+    }
+}
+
 // Lengths N <= FFT_MAX whose only prime factors are 2, 3 and 5 (and that are not
 // powers of two) run as Stockham stages of radix 5, 3, 4 and 2 in turn (the radix
 // of each stage in FftPlan).  A radix-R stage with stride s, n = N / s, reads
@@ -1058,7 +1198,14 @@ bool fft_ok(const lz_ctx *c, uint32_t N) {
 template <typename In, int E>
 int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, const double2 *tw, double sign,
                     PassOut out, hipStream_t s) {
-    if (fft_ok(c, N)) {
+    if (N == FFT1K && fft1k_lds() <= (size_t)c->dev.lds_per_wg_max) {
+        const size_t lds = fft1k_lds();
+        if (lds > 65536)
+            LZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&fft1k_pass_kernel<In, E>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        const uint32_t groups = (M + FFT1K_COLS - 1) / FFT1K_COLS;
+        hipLaunchKernelGGL((fft1k_pass_kernel<In, E>), dim3(groups), dim3(DIAG_WG), lds, s, src, M, sign, out);
+    } else if (fft_ok(c, N)) {
         uint32_t logN = 0;
         while ((1u << logN) < N) ++logN;
         const uint32_t per_wg = N > FFT_WG_ELEMS ? N : FFT_WG_ELEMS;

@@ -247,13 +247,15 @@ def _power_tol(x):
 
 @pytest.mark.parametrize("h,w", [(1, 1), (1, 37), (29, 1), (2, 2), (8, 8), (64, 64), (67, 131), (128, 200),
                                  (512, 512), (3, 4096), (4096, 3), (2048, 2048), (2, 8192), (1000, 24),
-                                 (768, 960), (45, 81), (7, 250), (4050, 2)])
+                                 (768, 960), (45, 81), (7, 250), (4050, 2), (1024, 1024), (1024, 7), (6, 1024),
+                                 (1024, 1), (1024, 4093)])
 def test_power_spectrum_2d(lz, ctx, h, w):
-    """All three routes of a pass: the power-of-two FFT up to 4096 (2, 8, 64, 128, 512, 2048, 4096,
-    and the 1 x 1 identity), the mixed-radix FFT for lengths with no prime factor above 5 (3, 24, 45,
-    81, 200, 250, 768, 960, 1000, 4050: radix 5, 3, 4, 2 stages, 4050 needing 130 KB of LDS), and the
-    direct DFT on the matrix cores for the others (7, 29, 37, 67, 131) and for 8192, above the FFTs'
-    limit; several cases mix them."""
+    """All routes of a pass: the 1024-point pass of one wave per column (1024; with 1, 6, 7, 1024 and
+    4093 columns, so some workgroups have idle waves), the power-of-two FFT up to 4096 (2, 8, 64, 128,
+    512, 2048, 4096, and the 1 x 1 identity), the mixed-radix FFT for lengths with no prime factor above
+    5 (3, 24, 45, 81, 200, 250, 768, 960, 1000, 4050: radix 5, 3, 4, 2 stages, 4050 needing 130 KB of
+    LDS), and the direct DFT on the matrix cores for the others (7, 29, 37, 67, 131, 4093) and for 8192,
+    above the FFTs' limit; several cases mix them."""
     rng = np.random.default_rng(100 + h * 7 + w)
     x = rng.integers(0, 256, (h, w), dtype=np.uint8)
     say("power spectrum", h, w)
