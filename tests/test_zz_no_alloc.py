@@ -1,4 +1,5 @@
-"""lz_decrypt_noalloc (no context, static device scratch) against lz_decrypt, through the C ABI.
+"""lz_decrypt_noalloc (no context, static device scratch) against lz_decrypt, through the C ABI,
+called directly and replayed from a captured HIP graph.
 
 Both entry points run the same kernels; the no-allocation one keeps the tag accumulator in a
 static device array that every call on the GPU shares.  Each check runs two no-allocation calls
@@ -144,3 +145,71 @@ def test_noalloc_rejects_before_running(env):
     assert b"blocks" in B.lib.lz_last_error()
     torch.cuda.synchronize()
     assert int(st.cpu()[0]) == 99 and bool((out == 7).all())
+
+
+GPW = b"graph-captured decrypt"
+
+
+@pytest.mark.gpu
+def test_noalloc_decrypt_in_a_graph_replays_exactly():
+    """One capture of two no-allocation decrypts (an untouched ciphertext, then an altered one); five
+    replays with eager work between them (new ciphertext bytes copied into the captured input buffers
+    and the outputs poisoned); every replay's plaintexts and statuses equal lz_decrypt's on the same
+    bytes."""
+    need_gpu()
+    import torch
+
+    import paper_1201_3114_amd as lz
+    from paper_1201_3114_amd import binding as B
+
+    prm = lz.params(n_it=40)
+    ctx = lz.Context(0, prm)
+    rng = np.random.default_rng(930)
+    n1, n2 = 70 * 256 + 11, 3 * 256 + 5
+    C1 = torch.empty(n1 + 24, dtype=torch.uint8, device="cuda")
+    C2 = torch.empty(n2 + 24, dtype=torch.uint8, device="cuda")
+    out1 = torch.empty(n1, dtype=torch.uint8, device="cuda")
+    out2 = torch.empty(n2, dtype=torch.uint8, device="cuda")
+    st = torch.empty(2, dtype=torch.int32, device="cuda")
+    buf, npw = B.pw_buf(GPW)
+
+    def decrypt_both():
+        s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        for C, out, i in ((C1, out1, 0), (C2, out2, 1)):
+            rc = B.lib.lz_decrypt_noalloc(ctypes.byref(prm), buf, npw, ctypes.c_void_p(C.data_ptr()), C.numel(),
+                                          ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.data_ptr() + 4 * i), s)
+            assert rc == 0, B.lib.lz_last_error()
+
+    def fresh_inputs(k):
+        P1 = torch.from_numpy(rng.integers(0, 256, n1, dtype=np.uint8)).cuda()
+        P2 = torch.from_numpy(rng.integers(0, 256, n2, dtype=np.uint8)).cuda()
+        C1.copy_(ctx.encrypt(P1, GPW))
+        C2.copy_(ctx.encrypt(P2, GPW))
+        C2[(37 * k) % (n2 + 24)] ^= 1 + k  # the second message altered, a different byte each time
+        return P1
+
+    fresh_inputs(0)
+    decrypt_both()  # first call on the device outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        decrypt_both()
+    torch.cuda.synchronize()
+    for k in range(1, 6):
+        P1 = fresh_inputs(k)
+        out1.fill_(0xAB)
+        out2.fill_(0xAB)
+        st.fill_(12345)
+        g.replay()
+        torch.cuda.synchronize()
+        ref1 = torch.empty(n1, dtype=torch.uint8, device="cuda")
+        ref2 = torch.empty(n2, dtype=torch.uint8, device="cuda")
+        rst = torch.empty(2, dtype=torch.int32, device="cuda")
+        ctx.decrypt(C1, GPW, out=ref1, status=rst[0:1])
+        ctx.decrypt(C2, GPW, out=ref2, status=rst[1:2])
+        torch.cuda.synchronize()
+        say(f"replay {k}: statuses {st.tolist()} (lz_decrypt {rst.tolist()})")
+        assert st.tolist() == rst.tolist() == [0, B.LZ_E_INTEGRITY]
+        assert torch.equal(out1, ref1) and torch.equal(out1, P1)
+        assert torch.equal(out2, ref2) and bool((out2 == 0).all())
+    ctx.close()
