@@ -118,7 +118,7 @@ __device__ T block_sum(T v, T *red) {
 // bytes: each workgroup adds its sums plus 256 times its bytes' total, one atomic
 // per lag, into copy b mod DIAG_MERGE of the context's merge buffer (eight tables
 // spread the device atomics of hundreds of workgroups), and lagsum_fix_kernel
-// adds up the copies, clears them and applies the rest.
+// adds up the copies, clears them and applies the rest, one workgroup per window.
 //
 // A task is a chunk of MC_ROWS rows, staged in LDS column by column (lt[c][r],
 // row stride a multiple of 16) together with the rows the shifted operands reach
@@ -136,12 +136,13 @@ __device__ T block_sum(T v, T *red) {
 // chain heads add the 32-bit sums (at most 4 lanes x 2048 rows x 16384 < 2^31)
 // into 64-bit LDS lag counters, no two of them on one lag.
 constexpr uint32_t MC_ROWS = 2048;
+constexpr int MC_SU = 4;  // staging steps of a thread whose loads are issued together
 
 struct McShape {
     uint32_t nt, ntg, rs, stride;  // column tiles, tile groups of 8, row splits, LDS column stride (bytes)
 };
 
-// L: the window's last lag relative to its first, k_lo (a multiple of MC_WINDOW); the column
+// L: the window's last lag relative to its first, k_lo (a multiple of 256); the column
 // tiles start k_lo / 16 rows further on, so the staged rows reach that much further
 constexpr uint32_t MC_WINDOW = 4096;
 
@@ -157,6 +158,19 @@ __host__ __device__ inline McShape mc_shape(uint32_t L, uint32_t k_lo) {
 size_t lagsum_mc_lds_bytes(uint32_t L, uint32_t k_lo) {
     const McShape m = mc_shape(L, k_lo);
     return ((size_t)(L + 1) * 8 + 15) / 16 * 16 + (size_t)16 * m.stride;
+}
+
+// The last lag of the window that starts at k_lo (relative to k_lo): MC_WINDOW lags, or fewer
+// (down to 256, in steps of 256) while two workgroups of its launch would not fit the LDS of one
+// CU (the staged rows reach k_lo / 16 rows past the chunk, so far windows need more LDS; one
+// workgroup per CU would leave half of them waiting for a second round).
+uint32_t mc_window_last(uint32_t max_lag, uint32_t k_lo, size_t lds_per_cu) {
+    // the kernel's byte-total reduction, and 1 KB: two workgroups of exactly half the CU's LDS each
+    // were measured to run one at a time, two of 80,128 bytes together
+    constexpr size_t STATIC_LDS = sizeof(unsigned long long) * DIAG_WG + 1024;
+    uint32_t Lw = max_lag - k_lo < MC_WINDOW - 1 ? max_lag - k_lo : MC_WINDOW - 1;
+    while (Lw >= 256 && 2 * (lagsum_mc_lds_bytes(Lw, k_lo) + STATIC_LDS) > lds_per_cu) Lw -= 256;
+    return Lw;
 }
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -180,42 +194,58 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_mc_kernel(const uint8_t *data,
     for (uint64_t task = blockIdx.x; task < tasks; task += gridDim.x) {
         const uint64_t row0 = task * MC_ROWS;
         __syncthreads();  // the previous task's operand reads are done
-        // stage: a thread takes rows 4e..4e+3 (four 16-byte loads), and each column's four bytes of
-        // them become one LDS word lt[c][4e .. 4e+3]
-        for (uint32_t e = threadIdx.x; e < ms.stride / 4; e += DIAG_WG) {
-            uint32_t w[4][4];
+        // stage: a thread takes rows 4e..4e+3 (four 16-byte loads) for e = threadIdx.x + DIAG_WG u,
+        // and each column's four bytes of them become one LDS word lt[c][4e .. 4e+3]; the loads of
+        // up to MC_SU values of e are in flight together before the first is used
+        const uint32_t ne = ms.stride / 4;
+        for (uint32_t e0 = threadIdx.x; e0 < ne; e0 += DIAG_WG * MC_SU) {
+            uint4 ld[MC_SU][4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint64_t i0 = (row0 + 4 * e + j) * 16;
-                if (aligned16 && i0 + 16 <= n) {
-                    const uint4 v = *reinterpret_cast<const uint4 *>(data + i0);
-                    w[j][0] = v.x, w[j][1] = v.y, w[j][2] = v.z, w[j][3] = v.w;
-                    if (4 * e + j < MC_ROWS)
-                        for (int q = 0; q < 4; ++q) tsum += __builtin_amdgcn_udot4(w[j][q], 0x01010101u, 0u, false);
+            for (int u = 0; u < MC_SU; ++u)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) w[j][q] ^= 0x80808080u;
-                } else {
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t e = e0 + u * DIAG_WG;
+                    const uint64_t i0 = (row0 + 4 * (uint64_t)e + j) * 16;
+                    ld[u][j] = (e < ne && aligned16 && i0 + 16 <= n) ? *reinterpret_cast<const uint4 *>(data + i0)
+                                                                      : make_uint4(0, 0, 0, 0);
+                }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        uint32_t v = 0;
-                        for (int b = 0; b < 4; ++b) {
-                            const uint64_t i = i0 + 4 * q + b;
-                            if (i < n) {
-                                const uint32_t x = data[i];
-                                if (4 * e + j < MC_ROWS) tsum += x;
-                                v |= (x ^ 0x80u) << (8 * b);
+            for (int u = 0; u < MC_SU; ++u) {
+                const uint32_t e = e0 + u * DIAG_WG;
+                if (e >= ne) break;
+                uint32_t w[4][4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint64_t i0 = (row0 + 4 * (uint64_t)e + j) * 16;
+                    if (aligned16 && i0 + 16 <= n) {
+                        w[j][0] = ld[u][j].x, w[j][1] = ld[u][j].y, w[j][2] = ld[u][j].z, w[j][3] = ld[u][j].w;
+                        if (4 * e + j < MC_ROWS)
+                            for (int q = 0; q < 4; ++q) tsum += __builtin_amdgcn_udot4(w[j][q], 0x01010101u, 0u, false);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) w[j][q] ^= 0x80808080u;
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            uint32_t v = 0;
+                            for (int b = 0; b < 4; ++b) {
+                                const uint64_t i = i0 + 4 * q + b;
+                                if (i < n) {
+                                    const uint32_t x = data[i];
+                                    if (4 * e + j < MC_ROWS) tsum += x;
+                                    v |= (x ^ 0x80u) << (8 * b);
+                                }
                             }
+                            w[j][q] = v;
                         }
-                        w[j][q] = v;
                     }
                 }
-            }
-            uint32_t *lt32 = reinterpret_cast<uint32_t *>(lt);
+                uint32_t *lt32 = reinterpret_cast<uint32_t *>(lt);
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const int q = c / 4, sh = 8 * (c % 4);
-                lt32[(c * ms.stride) / 4 + e] = ((w[0][q] >> sh) & 0xFFu) | (((w[1][q] >> sh) & 0xFFu) << 8) |
-                                                (((w[2][q] >> sh) & 0xFFu) << 16) | (((w[3][q] >> sh) & 0xFFu) << 24);
+                for (int c = 0; c < 16; ++c) {
+                    const int q = c / 4, sh = 8 * (c % 4);
+                    lt32[(c * ms.stride) / 4 + e] = ((w[0][q] >> sh) & 0xFFu) | (((w[1][q] >> sh) & 0xFFu) << 8) |
+                                                    (((w[2][q] >> sh) & 0xFFu) << 16) | (((w[3][q] >> sh) & 0xFFu) << 24);
+                }
             }
         }
         __syncthreads();
@@ -278,9 +308,9 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_mc_kernel(const uint8_t *data,
 
 // S_k = raw_k - 128 (P_k + Q_k) - 16384 max(n - k, 0) for k <= L, raw_k the sum of the
 // merge copies (cleared here for the next call), with P_k and Q_k the sums of the first
-// and the last min(k, n) bytes (one workgroup, one window of 4096 lags at a time: thread
-// t holds values kb + 16t .. kb + 16t + 15 of both ends, then a block-wide scan, and the
-// totals carry over to the next window).
+// and the last min(k, n) bytes (one workgroup per window of 4096 lags: it first sums the
+// first and the last kb bytes of its window's start kb, then thread t holds values
+// kb + 16t .. kb + 16t + 15 of both ends, and a block-wide scan gives the rest).
 __global__ __launch_bounds__(DIAG_WG) void lagsum_fix_kernel(const uint8_t *data, uint64_t n, uint32_t L,
                                                              unsigned long long *merge, unsigned long long *sums,
                                                              unsigned long long *total) {
@@ -288,7 +318,7 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_fix_kernel(const uint8_t *data
     __shared__ uint32_t scan[2][DIAG_WG];
     __shared__ unsigned long long raw[MC_WINDOW];
     const uint32_t t = threadIdx.x;
-    if (t < 64) {  // wave 0: the byte total over the copies (cleared), written to *total when asked for
+    if (blockIdx.x == 0 && t < 64) {  // wave 0: the byte total over the copies (cleared), to *total when asked for
         unsigned long long v = 0;
         if (t < DIAG_MERGE) {
             v = merge[(size_t)t * (L + 2) + L + 1];
@@ -297,10 +327,26 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_fix_kernel(const uint8_t *data
         for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
         if (t == 0 && total) *total = v;
     }
+    const uint32_t kb = blockIdx.x * MC_WINDOW;  // this workgroup's lags kb .. ke
+    if (kb > L) return;
+    const uint32_t ke = L - kb < MC_WINDOW - 1 ? L : kb + MC_WINDOW - 1;
     unsigned long long c0 = 0, c1 = 0;  // sums of the first and of the last kb bytes
-    for (uint32_t kb = 0; kb <= L; kb += MC_WINDOW) {  // lags kb .. ke, one window at a time
-        const uint32_t ke = L - kb < MC_WINDOW - 1 ? L : kb + MC_WINDOW - 1;
-        __syncthreads();  // the previous window's reads of raw and scan are done
+    {
+        __shared__ unsigned long long base[2][DIAG_WG];
+        unsigned long long b0 = 0, b1 = 0;
+        const uint64_t m = kb < n ? kb : n;
+        for (uint64_t j = t; j < m; j += DIAG_WG) b0 += data[j], b1 += data[n - 1 - j];
+        base[0][t] = b0;
+        base[1][t] = b1;
+        __syncthreads();
+        for (int w = DIAG_WG / 2; w > 0; w >>= 1) {
+            if ((int)t < w) base[0][t] += base[0][t + w], base[1][t] += base[1][t + w];
+            __syncthreads();
+        }
+        c0 = base[0][0];
+        c1 = base[1][0];
+    }
+    {
         // the copies' sums, lag k on thread k mod 256 (all loads of a thread issued together)
         for (uint32_t k0 = kb; k0 <= ke; k0 += DIAG_WG * 4) {
             unsigned long long part[4][DIAG_MERGE];
@@ -354,8 +400,6 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_fix_kernel(const uint8_t *data
             p0 += v[0][u];
             p1 += v[1][u];
         }
-        c0 += scan[0][DIAG_WG - 1];
-        c1 += scan[1][DIAG_WG - 1];
     }
 }
 
@@ -1029,11 +1073,11 @@ namespace {
 // (diag_begin) and records the event afterwards itself.
 int lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, unsigned long long *sums,
              unsigned long long *total, hipStream_t s, bool ordered = false) {
-    // the matrix-core route, one launch per window of MC_WINDOW lags, when each fits in LDS
+    // the matrix-core route, one launch per window of up to MC_WINDOW lags, when each fits in LDS
     size_t mc_lds = 0;
-    for (uint32_t k_lo = 0; k_lo <= max_lag; k_lo += MC_WINDOW) {
-        const uint32_t Lw = max_lag - k_lo < MC_WINDOW - 1 ? max_lag - k_lo : MC_WINDOW - 1;
-        const size_t b = lagsum_mc_lds_bytes(Lw, k_lo);
+    const size_t lds_cu = (size_t)c->dev.lds_per_wg_max;  // gfx950: a workgroup may take the whole CU's LDS
+    for (uint32_t k_lo = 0; k_lo <= max_lag; k_lo += mc_window_last(max_lag, k_lo, lds_cu) + 1) {
+        const size_t b = lagsum_mc_lds_bytes(mc_window_last(max_lag, k_lo, lds_cu), k_lo);
         mc_lds = b > mc_lds ? b : mc_lds;
     }
     if (mc_lds > (size_t)c->dev.lds_per_wg_max) return fail(LZ_E_INVAL, "lag sums need more LDS than the device has");
@@ -1044,18 +1088,19 @@ int lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, unsig
         char *ws;
         if (!ordered)
             if (int rc = diag_begin(c, s, 0, &ws)) return rc;
-        const uint64_t tasks = ((n + 15) / 16 + MC_ROWS - 1) / MC_ROWS;
-        const uint64_t blocks = tasks < (uint64_t)c->dev.cus * 2 ? tasks : (uint64_t)c->dev.cus * 2;
         if (mc_lds > 65536)
             LZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&lagsum_mc_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)mc_lds));
-        for (uint32_t k_lo = 0; k_lo <= max_lag; k_lo += MC_WINDOW) {
-            const uint32_t Lw = max_lag - k_lo < MC_WINDOW - 1 ? max_lag - k_lo : MC_WINDOW - 1;
+        const uint64_t tasks = ((n + 15) / 16 + MC_ROWS - 1) / MC_ROWS;
+        const uint64_t blocks = tasks < (uint64_t)c->dev.cus * 2 ? tasks : (uint64_t)c->dev.cus * 2;
+        for (uint32_t k_lo = 0; k_lo <= max_lag;) {
+            const uint32_t Lw = mc_window_last(max_lag, k_lo, lds_cu);
             hipLaunchKernelGGL(lagsum_mc_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), lagsum_mc_lds_bytes(Lw, k_lo),
                                s, d_data, (uint64_t)n, Lw, k_lo, max_lag, c->diag_merge);
+            k_lo += Lw + 1;
         }
-        hipLaunchKernelGGL(lagsum_fix_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag,
-                           c->diag_merge, sums, total);
+        hipLaunchKernelGGL(lagsum_fix_kernel, dim3(max_lag / MC_WINDOW + 1), dim3(DIAG_WG), 0, s, d_data,
+                           (uint64_t)n, max_lag, c->diag_merge, sums, total);
         LZ_HIP(hipGetLastError());
         return ordered ? LZ_OK : diag_end(c, s);
     }

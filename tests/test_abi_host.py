@@ -201,6 +201,12 @@ int main(void) {
     if (lz_decrypt_batch(NULL, NULL, NULL, NULL) != LZ_E_INVAL) return 8;
     p.dt = LZ_MAX_DT * 1.0000001;
     if (lz_params_check(&p) != LZ_E_INVAL) return 9;
+    /* the entry point without allocation rejects a missing status word before any HIP call */
+    if (lz_decrypt_noalloc(NULL, (const uint8_t *)"pw", 2, (const uint8_t *)&k, 64, (uint8_t *)&k, NULL, NULL)
+        != LZ_E_INVAL) return 10;
+    if (lz_autotune_cached(NULL, NULL, 0.0, NULL, NULL) != LZ_E_INVAL) return 11;
+    if (sizeof(lz_server_config) != 24 || LZ_SERVE_ADAPTIVE != 0 || LZ_SERVE_ALL_CHAINS != 1) return 12;
+    if (LZ_NOALLOC_SCRATCH_BYTES < 3 * sizeof(uint64_t)) return 13;
     printf("ok\n");
     return 0;
 }

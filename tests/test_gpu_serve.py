@@ -300,6 +300,14 @@ def test_server_and_stream_argument_errors(lz):
         lz.Server(ctx, hbm_budget=1 << 30, tick_bytes=(1 << 20) + 1)
     with pytest.raises(lz.LorenzError):
         lz.Server(ctx, hbm_budget=1 << 30, run_waves=9)                     # more than 8 waves per SIMD
+    import ctypes
+
+    from paper_1201_3114_amd import binding as B
+
+    bad = B.ServerConfig(1 << 30, 0, 16, 0, 2)                              # no such policy
+    h = ctypes.c_void_p()
+    assert B.lib.lz_server_create(ctx.handle, ctypes.byref(bad), ctypes.byref(h)) == B.LZ_E_INVAL
+    assert b"policy" in B.lib.lz_last_error() and not h.value
     srv = lz.Server(ctx, hbm_budget=1 << 28, max_chains=1024, tick_bytes=16)
     buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
     with pytest.raises(lz.LorenzError):
