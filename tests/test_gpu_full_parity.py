@@ -7,7 +7,10 @@
 * the 4,096-message batch (log-uniform 1 KiB..1 MiB, own passwords) at n_it = 30: every
   message's ciphertext and tag, one persistent launch;
 * its integrity variant: 409 ciphertexts with one altered byte; every status against the
-  oracle's decrypt, every released plaintext against the oracle's.
+  oracle's decrypt, every released plaintext against the oracle's;
+* the same batch under every launch shape the autotuner can choose (the benchmark times the
+  shape it picks on the device at hand): each shape's ciphertexts equal the ones checked
+  against the oracle, and its decrypt returns the plaintexts.
 
 The oracle runs block ranges on up to 16 host threads and the tests print a line per slice.
 """
@@ -175,3 +178,57 @@ def test_batch_integrity_every_status(lz, batch_n30):
             say(f"  {i + 1} statuses checked, {len(wrong)} differ ({time.time() - t0:.0f} s)")
     assert not wrong, f"{len(wrong)} messages differ from the oracle, first {wrong[:8]}"
     assert int((status == -2).sum()) == len(idx) and int((status == 0).sum()) == n_msg - len(idx)
+
+
+def tuner_grid():
+    """The launch shapes the autotuner times: chains per lane m in 1, 2, 4 and resident waves per
+    SIMD w with 4 <= m * w <= 8, workgroups of 64..256 lanes, 16..128-byte tiles (the context's
+    default shape is one of them)."""
+    for m in (1, 2, 4):
+        for w in (1, 2, 4, 8):
+            if not 4 <= m * w <= 8:
+                continue
+            for wg in (256, 128, 64):
+                for tile in (128, 64, 32, 16):
+                    yield m, wg, tile, w
+
+
+@pytest.mark.gpu
+def test_batch_every_tuner_shape(lz, batch_n30):
+    """The full 4,096-message batch at n_it = 30 under each of the 72 shapes: the ciphertexts and
+    tags equal the oracle-checked ones of the default shape, byte for byte, and the batched decrypt
+    returns every plaintext with status 0. A shape the device cannot hold is rejected at creation."""
+    import torch
+
+    ctx, wl, in_off, out_off, C = batch_n30
+    sizes = wl.sizes
+    d_in = to_dev(wl.data)
+    d_want = to_dev(C)
+    d_out = torch.empty_like(d_want)
+    d_back = torch.empty_like(d_in)
+    st = torch.empty(len(sizes), dtype=torch.int32, device="cuda")
+    assert ctx.get_launch() in [lz.LaunchShape(*g) for g in tuner_grid()]
+    ran, rejected, t0 = 0, [], time.time()
+    for g in tuner_grid():
+        sh = lz.LaunchShape(*g)
+        try:
+            be = lz.Batch(ctx, False, sizes, wl.passwords, d_in, in_off, d_out, out_off, shape=sh)
+        except lz.LorenzError:
+            rejected.append(g)
+            continue
+        d_out.fill_(0)
+        be.encrypt()
+        be.close()
+        assert torch.equal(d_out, d_want), f"shape {g}: ciphertexts differ"
+        d_back.fill_(0)
+        st.fill_(7)
+        bd = lz.Batch(ctx, True, sizes, wl.passwords, d_out, out_off, d_back, in_off, d_status=st, shape=sh)
+        bd.decrypt(st)
+        bd.close()
+        assert torch.equal(d_back, d_in), f"shape {g}: plaintexts differ"
+        assert int((st != 0).sum()) == 0, f"shape {g}: a status is not 0"
+        ran += 1
+        if ran % 12 == 0:
+            say(f"  {ran} shapes equal ({time.time() - t0:.0f} s)")
+    say(f"  {ran} shapes ran, {len(rejected)} rejected: {rejected}")
+    assert ran + len(rejected) == 72 and ran >= 48
