@@ -386,6 +386,10 @@ def bench_diag(lz, torch, reps=5):
     n16, L = 16 * MiB, 256
     ms = timed(lambda: lz.autocorrelation(ctx, x[:n16], L))
     res["autocorrelation_16MiB_lag256"] = dict(ms=ms, int_MAC_per_s=n16 * (L + 1) / ms * 1e3)
+    # lags up to 256: 32-byte rows, nine tiles of 32 x 32 x 32 int8 products, one launch
+    ms = timed(lambda: lz.lag_sums(ctx, x[:n16], L))
+    res["lag_sums_16MiB_lag256"] = dict(ms=ms, int_MAC_per_s=n16 * (L + 1) / ms * 1e3,
+                                        hbm_GBps=n16 / ms / 1e6)
     L = 16384  # the largest lag count: four windows of 4096 lags on the int8 matrix cores
     ms = timed(lambda: lz.lag_sums(ctx, x[:n16], L))
     res["lag_sums_16MiB_lag16384"] = dict(ms=ms, int_MAC_per_s=n16 * (L + 1) / ms * 1e3)

@@ -306,6 +306,272 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_mc_kernel(const uint8_t *data,
     if (k_lo == 0 && threadIdx.x == 0 && tot) atomicAdd(&copy[L_all + 1], tot);
 }
 
+// ---- the lag sums for lags up to 256: 32-byte rows, 32 x 32 x 32 int8 products ----------------
+//
+// The same sums with the bytes as rows of 32: G_t[c][j] = sum_r x'[32 r + c] x'[32 (r + t) + j]
+// (c, j < 32) holds lag k = 32 t + j - c, and tiles t = 0 .. NT - 1 with NT = (L + 31) / 32 + 1
+// cover lags 0..L with no tile to spare (nine for L = 256).  One v_mfma_i32_32x32x32_i8 takes 32
+// rows: lane l supplies column l % 32 of rows 16 (l / 32) .. + 15 as its 16 operand bytes, A
+// unshifted and B shifted by t rows, so the same LDS column serves both and B comes from one
+// 24-byte read by alignbyte.  The result's register i in lane l is G[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
+//
+// Wave w of the four takes tiles w, w + 4, ... (F = NT / 4 of them, all the task's rows: every
+// such tile of the wave has the same shift w mod 4 within a word) and the S = NT mod 4 last tiles
+// over its quarter of the rows, so each wave does the same number of products and holds only
+// F + S accumulators.  A task is LS_ROWS rows of 32 bytes, staged column by column (a thread
+// transposes pieces of 4 rows x LS_CB bytes with byte permutes) with the LS_HALO rows after it
+// that the shifted operands reach.  The next task's loads are issued before the current task's
+// products, and the accumulators stay in registers over LS_FLUSH tasks of the workgroup (each
+// accumulator then sums at most LS_FLUSH x LS_ROWS products of at most 2^14, below 2^31) before
+// the diagonals are added into the LDS lag counters.  Each workgroup adds its sums plus 256 times
+// its bytes' total into copy b mod LS_COPIES of the merge buffer (the lags' adds of hundreds of
+// workgroups, spread over more copies than the kernel above uses).
+constexpr uint32_t LS_ROWS = 512;
+// staging: a thread takes LS_EV pieces of 4 rows x LS_CB bytes (LS_CB = 32: whole rows)
+constexpr uint32_t LS_CB = LS_ROWS >= 1024 ? 32 : LS_ROWS * 32 / 1024;
+constexpr uint32_t LS_EV = LS_ROWS * 32 / (4 * LS_CB) / DIAG_WG;
+static_assert(LS_CB == 32 || LS_CB == 16 || LS_CB == 8, "piece width");
+static_assert(LS_EV * DIAG_WG * 4 * LS_CB == LS_ROWS * 32, "every thread stages whole pieces");
+constexpr uint32_t LS_HALO = 8;                 // rows past a task read by the shifted operands
+constexpr uint32_t LS_STRIDE = LS_ROWS + 16;    // LDS bytes per column, an odd multiple of 16
+constexpr uint32_t LS_FLUSH = 64;               // tasks between flushes: 64 x 512 x 2^14 = 2^29
+constexpr uint32_t LS_MAX_NT = 9;               // lags up to 256
+// merge copies: workgroup b adds into copy b mod LS_COPIES (hundreds of workgroups add to each lag)
+constexpr uint32_t LS_COPIES = 32;
+static_assert((size_t)LS_COPIES * (32 * (LS_MAX_NT - 1) + 2) <= DIAG_MERGE_WORDS, "merge buffer too small");
+static_assert(LS_ROWS % 128 == 0 && LS_ROWS >= 128, "whole 32-row blocks for each of the four waves");
+static_assert((uint64_t)LS_FLUSH * LS_ROWS * 16384 < (1ull << 31), "32-bit accumulators");
+
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+__device__ inline uint4 ls_load16(const uint8_t *data, uint64_t n, uint64_t i0, bool aligned16, uint32_t nb) {
+    // bytes i0 .. i0 + nb - 1 (nb = 8 or 16, i0 a multiple of nb) as x - 128 (XOR 0x80), 0 past n
+    if (aligned16 && i0 + nb <= n) {
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (nb == 16) {
+            v = *reinterpret_cast<const uint4 *>(data + i0);
+        } else {
+            const uint2 u = *reinterpret_cast<const uint2 *>(data + i0);
+            v.x = u.x, v.y = u.y;
+        }
+        v.x ^= 0x80808080u, v.y ^= 0x80808080u, v.z ^= 0x80808080u, v.w ^= 0x80808080u;
+        return v;
+    }
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (uint32_t b = 0; b < nb; ++b)
+        if (i0 + b < n) w[b / 4] |= ((uint32_t)data[i0 + b] ^ 0x80u) << (8 * (b % 4));
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+template <int NT>
+__global__ __launch_bounds__(DIAG_WG) __attribute__((amdgpu_waves_per_eu(2))) void lagsum_small_kernel(const uint8_t *data, uint64_t n, uint32_t L,
+                                                                unsigned long long *merge) {
+    static_assert(NT >= 1 && NT <= (int)LS_MAX_NT, "tiles");
+    constexpr int F = NT / 4, S = NT % 4;  // tiles per wave over all rows; tiles shared out by rows
+    __shared__ __align__(16) uint8_t lt[32 * LS_STRIDE];
+    // lag counters for k = -32 .. 32 NT - 1: the diagonals of every tile land in range, so the
+    // flush adds without a test (the counters outside 0..L are never read)
+    __shared__ unsigned long long acc_all[32 * NT + 32];
+    __shared__ long long wred[DIAG_WG / 64];
+    unsigned long long *acc = acc_all + 32;
+    for (uint32_t k = threadIdx.x; k < 32 * NT + 32; k += DIAG_WG) acc_all[k] = 0;
+    const uint32_t t = threadIdx.x, lane = t % 64, col = lane % 32, h = lane / 32;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(t / 64);
+    const bool aligned16 = (reinterpret_cast<uintptr_t>(data) & 15) == 0;
+    const uint64_t nrows = (n + 31) / 32, tasks = (nrows + LS_ROWS - 1) / LS_ROWS;
+    v16i d[F + S];
+#pragma unroll
+    for (int q = 0; q < F + S; ++q) d[q] = (v16i){};
+    // piece p = t + DIAG_WG v: rows 4 (p / PQ) .. + 3, bytes LS_CB (p % PQ) .. + LS_CB - 1 of each
+    // (PQ = 32 / LS_CB pieces per 4 rows), as LS_CB / 4 words per row: pw[v][row][word]; thread
+    // t < 2 LS_HALO also one half row of the halo
+    constexpr uint32_t PQ = 32 / LS_CB, PW = LS_CB / 4;
+    uint32_t pw[LS_EV][4][PW];
+    uint4 ph = make_uint4(0, 0, 0, 0);
+    auto load = [&](uint64_t task) {
+        const uint64_t b0 = task * LS_ROWS * 32;
+#pragma unroll
+        for (uint32_t v = 0; v < LS_EV; ++v) {
+            const uint32_t pc = t + DIAG_WG * v, e = pc / PQ, cb = LS_CB * (pc % PQ);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (uint32_t hw = 0; hw < PW; hw += 4) {
+                    const uint4 x = ls_load16(data, n, b0 + (4 * (uint64_t)e + r) * 32 + cb + 4 * hw, aligned16, PW >= 4 ? 16 : 4 * PW);
+                    pw[v][r][hw] = x.x;
+                    if (PW > 1) pw[v][r][hw + 1] = x.y;
+                    if (PW > 2) pw[v][r][hw + 2] = x.z;
+                    if (PW > 3) pw[v][r][hw + 3] = x.w;
+                }
+        }
+        if (t < 2 * LS_HALO) ph = ls_load16(data, n, b0 + (uint64_t)(LS_ROWS + t / 2) * 32 + 16 * (t % 2), aligned16, 16);
+    };
+    int tsum = 0;  // this thread's share of sum (x - 128) over the tasks' own rows
+    // lag of d[q][i]: 32 tile + col - (8 (i / 4) + 4 h + i % 4), tile = wave + 4 q (q < F) or 4 F + q - F
+    unsigned long long *diag = acc + (int)col - 4 * (int)h;
+    auto flush = [&]() {
+#pragma unroll
+        for (int q = 0; q < F + S; ++q)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int tile_off = q < F ? 32 * 4 * q : 32 * (4 * F + q - F);
+                unsigned long long *p = (q < F ? diag + 32 * (int)wave : diag) + (tile_off - 8 * (i / 4) - i % 4);
+                atomicAdd(p, (unsigned long long)(long long)d[q][i]);
+                d[q][i] = 0;
+            }
+    };
+    if (blockIdx.x < tasks) load(blockIdx.x);
+    for (uint64_t first = blockIdx.x; first < tasks; first += (uint64_t)LS_FLUSH * gridDim.x) {
+        const uint64_t stop =
+            tasks - first < (uint64_t)LS_FLUSH * gridDim.x ? tasks : first + (uint64_t)LS_FLUSH * gridDim.x;
+        for (uint64_t task = first; task < stop; task += gridDim.x) {
+            __syncthreads();  // the previous task's operand reads are done
+            uint32_t *lt32 = reinterpret_cast<uint32_t *>(lt);
+#pragma unroll
+            for (uint32_t v = 0; v < LS_EV; ++v) {
+                const uint32_t pc = t + DIAG_WG * v, e = pc / PQ, cb = LS_CB * (pc % PQ);
+#pragma unroll
+                for (uint32_t w = 0; w < PW; ++w) {
+                    uint32_t r[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        r[q] = pw[v][q][w];
+                        tsum = __builtin_amdgcn_sdot4((int)r[q], 0x01010101, tsum, false);
+                    }
+                    // 4 x 4 byte transpose: column cb + 4 w + b gets bytes b of rows 0..3
+                    const uint32_t lo01 = __byte_perm(r[0], r[1], 0x5140), hi01 = __byte_perm(r[0], r[1], 0x7362);
+                    const uint32_t lo23 = __byte_perm(r[2], r[3], 0x5140), hi23 = __byte_perm(r[2], r[3], 0x7362);
+                    const uint32_t c0 = cb + 4 * w;
+                    lt32[(c0 + 0) * (LS_STRIDE / 4) + e] = __byte_perm(lo01, lo23, 0x5410);
+                    lt32[(c0 + 1) * (LS_STRIDE / 4) + e] = __byte_perm(lo01, lo23, 0x7632);
+                    lt32[(c0 + 2) * (LS_STRIDE / 4) + e] = __byte_perm(hi01, hi23, 0x5410);
+                    lt32[(c0 + 3) * (LS_STRIDE / 4) + e] = __byte_perm(hi01, hi23, 0x7632);
+                }
+            }
+            if (t < 2 * LS_HALO) {
+                const uint32_t w4[4] = {ph.x, ph.y, ph.z, ph.w};
+#pragma unroll
+                for (int b = 0; b < 16; ++b)
+                    lt[(16 * (t % 2) + b) * LS_STRIDE + LS_ROWS + t / 2] = (uint8_t)(w4[b / 4] >> (8 * (b % 4)));
+            }
+            __syncthreads();
+            if (task + gridDim.x < tasks) load(task + gridDim.x);  // in flight during the products
+            const uint8_t *cp = lt + col * LS_STRIDE + 16 * h;
+            if (F > 0) {
+                // all row blocks, tiles wave + 4 q: B words q .. q + 4 shifted by wave bytes; the next
+                // block's words are read before this one's products
+                uint4 av = *reinterpret_cast<const uint4 *>(cp);
+                uint2 ex = *reinterpret_cast<const uint2 *>(cp + 16);
+                for (uint32_t rb = 0; rb < LS_ROWS; rb += 32) {
+                    const uint32_t w[6] = {av.x, av.y, av.z, av.w, ex.x, ex.y};
+                    if (rb + 32 < LS_ROWS) {
+                        av = *reinterpret_cast<const uint4 *>(cp + rb + 32);
+                        ex = *reinterpret_cast<const uint2 *>(cp + rb + 48);
+                    }
+                    const v4i a = (v4i){(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+#pragma unroll
+                    for (int q = 0; q < F; ++q) {
+                        v4i b;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) b[j] = (int)__builtin_amdgcn_alignbyte(w[q + j + 1], w[q + j], wave);
+                        d[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, d[q], 0, 0, 0);
+                    }
+                }
+            }
+            if (S > 0) {
+                // this wave's quarter of the row blocks, the last S tiles 4 F + j: B words F .. F + 4
+                for (uint32_t rb = wave * (LS_ROWS / 4); rb < (wave + 1) * (LS_ROWS / 4); rb += 32) {
+                    const uint4 av = *reinterpret_cast<const uint4 *>(cp + rb);
+                    const uint4 bw = *reinterpret_cast<const uint4 *>(cp + rb + 4 * F);
+                    const uint32_t b4 = *reinterpret_cast<const uint32_t *>(cp + rb + 4 * F + 16);
+                    const uint32_t w[5] = {bw.x, bw.y, bw.z, bw.w, b4};
+                    const v4i a = (v4i){(int)av.x, (int)av.y, (int)av.z, (int)av.w};
+#pragma unroll
+                    for (int j = 0; j < S; ++j) {
+                        v4i b;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            b[u] = j == 0 ? (int)w[u] : (int)__builtin_amdgcn_alignbyte(w[u + 1], w[u], j);
+                        d[F + j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, d[F + j], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        flush();
+    }
+    // the bytes' total: sum (x - 128) over the own rows plus 128 per own byte
+    unsigned long long nb = 0;
+    for (uint64_t tk = blockIdx.x; tk < tasks; tk += gridDim.x) {
+        const uint64_t b0 = tk * LS_ROWS * 32, b1 = b0 + LS_ROWS * 32;
+        nb += (b1 < n ? b1 : n) - b0;
+    }
+    long long ws = tsum;
+    for (int o = 32; o > 0; o >>= 1) ws += __shfl_down(ws, o, 64);
+    if (lane == 0) wred[wave] = ws;
+    __syncthreads();  // also: every wave's flush is done
+    const unsigned long long tot =
+        (unsigned long long)(wred[0] + wred[1] + wred[2] + wred[3]) + 128ull * nb;
+    unsigned long long *copy = merge + (size_t)(blockIdx.x % LS_COPIES) * (L + 2);
+    for (uint32_t k = t; k <= L; k += DIAG_WG) {
+        const unsigned long long v = acc[k] + 256ull * tot;
+        if (v) atomicAdd(&copy[k], v);
+    }
+    if (t == 0 && tot) atomicAdd(&copy[L + 1], tot);
+}
+
+// The correction for L <= 256 (one window, one workgroup of LS_FIX_WG threads): thread k takes
+// lag k, sums its LS_COPIES merge copies (all loads issued before the first is used) and clears
+// them; the first and last L bytes are loaded at the same time, and P_k + Q_k comes from one scan
+// of x_j + x_{n-1-j} (a wave scan by shuffles, then the wave totals through LDS).
+constexpr int LS_FIX_WG = 512;
+static_assert(LS_FIX_WG > 32 * (LS_MAX_NT - 1) && LS_FIX_WG >= (int)LS_COPIES, "a thread per lag and per copy");
+__global__ __launch_bounds__(LS_FIX_WG) void lagsum_fix_small_kernel(const uint8_t *data, uint64_t n, uint32_t L,
+                                                                     unsigned long long *merge,
+                                                                     unsigned long long *sums,
+                                                                     unsigned long long *total) {
+    __shared__ uint32_t wsum[LS_FIX_WG / 64];
+    __shared__ unsigned long long tsum[LS_FIX_WG / 64];
+    const uint32_t k = threadIdx.x, lane = k % 64, wave = k / 64;
+    const size_t cs = (size_t)L + 2;  // copy stride: lags 0..L, then the byte total
+    unsigned long long part[LS_COPIES];
+#pragma unroll
+    for (uint32_t c = 0; c < LS_COPIES; ++c) part[c] = k <= L ? merge[c * cs + k] : 0ull;
+    unsigned long long tc = k < LS_COPIES ? merge[k * cs + L + 1] : 0ull;
+    const uint32_t x = k < L && k < n ? (uint32_t)data[k] + data[n - 1 - k] : 0u;  // j = k < L <= 256
+    // inclusive scan of x over the block
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if ((int)lane >= o) inc += y;
+    }
+    for (int o = 32; o > 0; o >>= 1) tc += __shfl_down(tc, o, 64);
+    if (lane == 63) wsum[wave] = inc;
+    if (lane == 0) tsum[wave] = tc;
+    __syncthreads();
+    uint32_t before = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < LS_FIX_WG / 64; ++w) before += w < wave ? wsum[w] : 0u;
+    if (k <= L) {
+        // P_k + Q_k: the bytes j < k of both ends
+        const unsigned long long pq = before + inc - x;
+        unsigned long long raw = 0;
+#pragma unroll
+        for (uint32_t c = 0; c < LS_COPIES; ++c) {
+            raw += part[c];
+            merge[c * cs + k] = 0;
+        }
+        const unsigned long long m = k < n ? n - k : 0;
+        sums[k] = raw - 128ull * pq - 16384ull * m;
+    }
+    if (k < LS_COPIES) merge[k * cs + L + 1] = 0;
+    if (k == 0 && total) {
+        unsigned long long tt = 0;
+        for (uint32_t w = 0; w < LS_FIX_WG / 64; ++w) tt += tsum[w];
+        *total = tt;
+    }
+}
+
 // S_k = raw_k - 128 (P_k + Q_k) - 16384 max(n - k, 0) for k <= L, raw_k the sum of the
 // merge copies (cleared here for the next call), with P_k and Q_k the sums of the first
 // and the last min(k, n) bytes (one workgroup per window of 4096 lags: it first sums the
@@ -1088,6 +1354,26 @@ int lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, unsig
         char *ws;
         if (!ordered)
             if (int rc = diag_begin(c, s, 0, &ws)) return rc;
+        if (max_lag <= 32 * (LS_MAX_NT - 1)) {  // up to 256 lags: 32-byte rows, one launch
+            const uint32_t nt = (max_lag + 31) / 32 + 1;
+            void (*kern)(const uint8_t *, uint64_t, uint32_t, unsigned long long *) =
+                nt == 1 ? lagsum_small_kernel<1> : nt == 2 ? lagsum_small_kernel<2> : nt == 3 ? lagsum_small_kernel<3>
+                : nt == 4 ? lagsum_small_kernel<4> : nt == 5 ? lagsum_small_kernel<5> : nt == 6 ? lagsum_small_kernel<6>
+                : nt == 7 ? lagsum_small_kernel<7> : nt == 8 ? lagsum_small_kernel<8> : lagsum_small_kernel<9>;
+            // resident workgroups only, as many tasks each (rounds = tasks / slots, rounded up)
+            int per_cu = 0;
+            LZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, DIAG_WG, 0));
+            if (per_cu < 1) per_cu = 1;
+            const uint64_t tasks = ((n + 31) / 32 + LS_ROWS - 1) / LS_ROWS;
+            const uint64_t slots = (uint64_t)c->dev.cus * (uint64_t)per_cu;
+            const uint64_t rounds = (tasks + slots - 1) / slots;
+            const unsigned blocks = (unsigned)((tasks + rounds - 1) / rounds);
+            hipLaunchKernelGGL(kern, dim3(blocks), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag, c->diag_merge);
+            hipLaunchKernelGGL(lagsum_fix_small_kernel, dim3(1), dim3(LS_FIX_WG), 0, s, d_data, (uint64_t)n, max_lag,
+                               c->diag_merge, sums, total);
+            LZ_HIP(hipGetLastError());
+            return ordered ? LZ_OK : diag_end(c, s);
+        }
         if (mc_lds > 65536)
             LZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&lagsum_mc_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)mc_lds));

@@ -101,11 +101,13 @@ def test_entropy(lz, ctx, kind):
 @pytest.mark.parametrize("n,L", [(0, 5), (1, 0), (10, 20), (5000, 300), (200_003, 256), (1_000_000, 1000),
                                  (50_000, 4095), (50_000, 4096), (30_001, 16384), (3, 16384), (15, 1), (16, 16),
                                  (65_537, 127), (98_309, 511), (100_003, 8191), (100_003, 8192), (77_777, 12289),
-                                 (20_000, 16383)])
+                                 (20_000, 16383), (31, 255), (33, 32), (64, 33), (2_000_037, 256), (1_048_576, 224),
+                                 (32_800, 225), (40_000, 257)])
 def test_lag_sums_exact(lz, ctx, n, L):
-    """The lags run on the matrix cores (bytes offset by -128, then corrected exactly) in windows of 4096
-    lags, one launch each, whose sums the correction kernel takes window by window: window edges, lags
-    beyond n and partial 16-byte rows are compared exactly."""
+    """The lags run on the matrix cores (bytes offset by -128, then corrected exactly): up to lag 256 on
+    32-byte rows in one launch (1 to 9 column tiles), beyond that in windows of 4096 lags, one launch
+    each, whose sums the correction kernel takes window by window. Tile and window edges, lags beyond n
+    and partial rows are compared exactly."""
     rng = np.random.default_rng(90 + n)
     x = rng.integers(0, 256, n, dtype=np.uint8)
     got = host(lz.lag_sums(ctx, _dev(x), L)).astype(np.int64)
@@ -167,10 +169,10 @@ def test_histogram_and_lag_sums_past_4GiB(lz, ctx):
     say("histogram and lag sums of", n, "bytes")
     h = host(lz.histogram(ctx, big)).astype(np.int64)
     assert np.array_equal(h, _ramp_histogram(n))
-    L = 300
-    got = host(lz.lag_sums(ctx, big, L))
-    for k in range(L + 1):
-        assert int(got[k]) == _ramp_lag_sum(n, k), k
+    for L in (256, 300):  # 32-byte rows (512 tasks per workgroup, partial sums flushed on the way), 16-byte rows
+        got = host(lz.lag_sums(ctx, big, L))
+        for k in range(L + 1):
+            assert int(got[k]) == _ramp_lag_sum(n, k), (L, k)
     got = host(lz.lag_sums(ctx, big, 4200))  # two lag windows
     for k in (0, 1, 255, 4095, 4096, 4097, 4111, 4199, 4200):
         assert int(got[k]) == _ramp_lag_sum(n, k), k
@@ -178,10 +180,11 @@ def test_histogram_and_lag_sums_past_4GiB(lz, ctx):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("L", [0, 100, 4095])
+@pytest.mark.parametrize("L", [0, 100, 256, 4095])
 def test_lag_sums_unaligned_and_many_tasks(lz, ctx, L):
     """A data pointer off 4-byte alignment (byte loads when staging), and 40 MiB + 3 bytes: more
-    2048-row tasks than workgroups on a 256-CU device, so workgroups take several tasks in turn.
+    tasks than workgroups on a 256-CU device, so workgroups take several tasks in turn (with the
+    next task's loads in flight for lags up to 256).
     The large case is checked exactly at sampled lags (a lag sum is a plain dot product)."""
     import torch
 
