@@ -108,209 +108,22 @@ __device__ T block_sum(T v, T *red) {
 
 // ---- the lag sums on the matrix cores ----------------------------------------------------
 //
-// With the bytes laid out as rows of 16, S_k is a sum along the diagonals of
-// G[c][j] = sum_r x[16 r + c] x[16 r + j] (c < 16, j < L + 16; lag k = j - c):
-// an integer matrix product with the rows as its inner dimension, which runs on
-// v_mfma_i32_16x16x64_i8 (64 rows per instruction).  The matrix cores take signed
-// bytes, so the kernel works with x - 128 (byte XOR 0x80; 0 past n) and
+// With the bytes laid out as rows of 32, S_k is a sum along the diagonals of the integer matrix
+// products G_t[c][j] = sum_r x[32 r + c] x[32 (r + t) + j] (c, j < 32; lag k = 32 t + j - c), with
+// the rows as their inner dimension, which run on v_mfma_i32_32x32x32_i8.  The matrix cores take
+// signed bytes, so the kernels work with x' = x - 128 (byte XOR 0x80; 0 past n) and
 //   S_k = S'_k + 256 T - 128 (P_k + Q_k) - 16384 max(n - k, 0),
-// T the byte total, P_k and Q_k the sums of the first and the last min(k, n)
-// bytes: each workgroup adds its sums plus 256 times its bytes' total, one atomic
-// per lag, into copy b mod DIAG_MERGE of the context's merge buffer (eight tables
-// spread the device atomics of hundreds of workgroups), and lagsum_fix_kernel
-// adds up the copies, clears them and applies the rest, one workgroup per window.
+// T the byte total, P_k and Q_k the sums of the first and the last min(k, n) bytes: each workgroup
+// adds its sums plus 256 times its bytes' total, one atomic per lag, into one of several copies
+// of the context's merge buffer (the copies spread the device atomics of hundreds of
+// workgroups), and a correction kernel adds up the copies, clears them and applies the rest.
 //
-// A task is a chunk of MC_ROWS rows, staged in LDS column by column (lt[c][r],
-// row stride a multiple of 16) together with the rows the shifted operands reach
-// past it.  Matrix-core operands (lane l, g = l / 16, byte t < 16): A = x'[row
-// rb + 16g + t, column l % 16], B = x'[row rb + jt + 16g + t, column l % 16] for
-// column tile jt, both 16 consecutive bytes of one LDS column; the result holds
-// G[4g + i][16 jt + l % 16] in its i-th register.  A lane reads 24 bytes of its
-// column once per row block and tile group and forms the B operands of the
-// group's eight tiles (shifts 0..7) with alignbyte; all eight run (a group past
-// the last tile reads the same in-range bytes) and the extra tiles are dropped.
-// A work item is one tile group over all the chunk's rows, or over a half or a
-// quarter of them when there are two groups or one (so that four waves have
-// work).  At its end the lanes whose results lie on the same diagonals (lane l
-// and l + 20: column + 4, row + 4) add theirs up in two shuffle steps, and the 28
-// chain heads add the 32-bit sums (at most 4 lanes x 2048 rows x 16384 < 2^31)
-// into 64-bit LDS lag counters, no two of them on one lag.
-constexpr uint32_t MC_ROWS = 2048;
-constexpr int MC_SU = 4;  // staging steps of a thread whose loads are issued together
-
-struct McShape {
-    uint32_t nt, ntg, rs, stride;  // column tiles, tile groups of 8, row splits, LDS column stride (bytes)
-};
-
-// L: the window's last lag relative to its first, k_lo (a multiple of 256); the column
-// tiles start k_lo / 16 rows further on, so the staged rows reach that much further
-constexpr uint32_t MC_WINDOW = 4096;
-
-__host__ __device__ inline McShape mc_shape(uint32_t L, uint32_t k_lo) {
-    McShape m;
-    m.nt = (L + 15) / 16 + 1;
-    m.ntg = (m.nt + 7) / 8;
-    m.rs = m.ntg >= 3 ? 1 : 4 / m.ntg;
-    m.stride = MC_ROWS + k_lo / 16 + 16 * ((m.ntg + 1) / 2);
-    return m;
-}
-
-size_t lagsum_mc_lds_bytes(uint32_t L, uint32_t k_lo) {
-    const McShape m = mc_shape(L, k_lo);
-    return ((size_t)(L + 1) * 8 + 15) / 16 * 16 + (size_t)16 * m.stride;
-}
-
-// The last lag of the window that starts at k_lo (relative to k_lo): MC_WINDOW lags, or fewer
-// (down to 256, in steps of 256) while two workgroups of its launch would not fit the LDS of one
-// CU (the staged rows reach k_lo / 16 rows past the chunk, so far windows need more LDS; one
-// workgroup per CU would leave half of them waiting for a second round).
-uint32_t mc_window_last(uint32_t max_lag, uint32_t k_lo, size_t lds_per_cu) {
-    // the kernel's byte-total reduction, and 1 KB: two workgroups of exactly half the CU's LDS each
-    // were measured to run one at a time, two of 80,128 bytes together
-    constexpr size_t STATIC_LDS = sizeof(unsigned long long) * DIAG_WG + 1024;
-    uint32_t Lw = max_lag - k_lo < MC_WINDOW - 1 ? max_lag - k_lo : MC_WINDOW - 1;
-    while (Lw >= 256 && 2 * (lagsum_mc_lds_bytes(Lw, k_lo) + STATIC_LDS) > lds_per_cu) Lw -= 256;
-    return Lw;
-}
-
 typedef int v4i __attribute__((ext_vector_type(4)));
-
-__global__ __launch_bounds__(DIAG_WG) void lagsum_mc_kernel(const uint8_t *data, uint64_t n, uint32_t L,
-                                                             uint32_t k_lo, uint32_t L_all,
-                                                             unsigned long long *merge) {
-    extern __shared__ uint32_t lds[];
-    const McShape ms = mc_shape(L, k_lo);
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(lds);
-    uint8_t *lt = reinterpret_cast<uint8_t *>(lds) + ((size_t)(L + 1) * 8 + 15) / 16 * 16;
-    for (uint32_t k = threadIdx.x; k <= L; k += DIAG_WG) acc[k] = 0;
-    const uint32_t lane = threadIdx.x % 64;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // uniform: scalar branches
-    const uint32_t col = lane % 16, g = lane / 16;
-    const uint64_t nrows = (n + 15) / 16;
-    const uint64_t tasks = (nrows + MC_ROWS - 1) / MC_ROWS;
-    const uint32_t items = ms.ntg * ms.rs, rows_per_item = MC_ROWS / ms.rs;
-    const bool aligned16 = (reinterpret_cast<uintptr_t>(data) & 15) == 0;
-    unsigned long long tsum = 0;  // this thread's share of the bytes of the tasks' own rows
-    for (uint64_t task = blockIdx.x; task < tasks; task += gridDim.x) {
-        const uint64_t row0 = task * MC_ROWS;
-        __syncthreads();  // the previous task's operand reads are done
-        // stage: a thread takes rows 4e..4e+3 (four 16-byte loads) for e = threadIdx.x + DIAG_WG u,
-        // and each column's four bytes of them become one LDS word lt[c][4e .. 4e+3]; the loads of
-        // up to MC_SU values of e are in flight together before the first is used
-        const uint32_t ne = ms.stride / 4;
-        for (uint32_t e0 = threadIdx.x; e0 < ne; e0 += DIAG_WG * MC_SU) {
-            uint4 ld[MC_SU][4];
-#pragma unroll
-            for (int u = 0; u < MC_SU; ++u)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t e = e0 + u * DIAG_WG;
-                    const uint64_t i0 = (row0 + 4 * (uint64_t)e + j) * 16;
-                    ld[u][j] = (e < ne && aligned16 && i0 + 16 <= n) ? *reinterpret_cast<const uint4 *>(data + i0)
-                                                                      : make_uint4(0, 0, 0, 0);
-                }
-#pragma unroll
-            for (int u = 0; u < MC_SU; ++u) {
-                const uint32_t e = e0 + u * DIAG_WG;
-                if (e >= ne) break;
-                uint32_t w[4][4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint64_t i0 = (row0 + 4 * (uint64_t)e + j) * 16;
-                    if (aligned16 && i0 + 16 <= n) {
-                        w[j][0] = ld[u][j].x, w[j][1] = ld[u][j].y, w[j][2] = ld[u][j].z, w[j][3] = ld[u][j].w;
-                        if (4 * e + j < MC_ROWS)
-                            for (int q = 0; q < 4; ++q) tsum += __builtin_amdgcn_udot4(w[j][q], 0x01010101u, 0u, false);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) w[j][q] ^= 0x80808080u;
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            uint32_t v = 0;
-                            for (int b = 0; b < 4; ++b) {
-                                const uint64_t i = i0 + 4 * q + b;
-                                if (i < n) {
-                                    const uint32_t x = data[i];
-                                    if (4 * e + j < MC_ROWS) tsum += x;
-                                    v |= (x ^ 0x80u) << (8 * b);
-                                }
-                            }
-                            w[j][q] = v;
-                        }
-                    }
-                }
-                uint32_t *lt32 = reinterpret_cast<uint32_t *>(lt);
-#pragma unroll
-                for (int c = 0; c < 16; ++c) {
-                    const int q = c / 4, sh = 8 * (c % 4);
-                    lt32[(c * ms.stride) / 4 + e] = ((w[0][q] >> sh) & 0xFFu) | (((w[1][q] >> sh) & 0xFFu) << 8) |
-                                                    (((w[2][q] >> sh) & 0xFFu) << 16) | (((w[3][q] >> sh) & 0xFFu) << 24);
-                }
-            }
-        }
-        __syncthreads();
-        for (uint32_t item = wave; item < items; item += DIAG_WG / 64) {
-            const uint32_t tg = item / ms.rs, rsub = item % ms.rs;
-            v4i d[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) d[t] = (v4i){0, 0, 0, 0};
-            const uint32_t r_end = (rsub + 1) * rows_per_item;
-            for (uint32_t rb = rsub * rows_per_item; rb < r_end; rb += 64) {
-                const uint8_t *colp = lt + (size_t)col * ms.stride;
-                const uint4 av = *reinterpret_cast<const uint4 *>(colp + rb + 16 * g);
-                const v4i a = (v4i){(int)av.x, (int)av.y, (int)av.z, (int)av.w};
-                const uint8_t *bp = colp + rb + k_lo / 16 + 8 * tg + 16 * g;
-                const uint2 w01 = *reinterpret_cast<const uint2 *>(bp);
-                const uint2 w23 = *reinterpret_cast<const uint2 *>(bp + 8);
-                const uint2 w45 = *reinterpret_cast<const uint2 *>(bp + 16);
-                const uint32_t w[6] = {w01.x, w01.y, w23.x, w23.y, w45.x, w45.y};
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    v4i b;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        b[j] = (int)__builtin_amdgcn_alignbyte(w[t / 4 + j + 1], w[t / 4 + j], t % 4);
-                    d[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, d[t], 0, 0, 0);
-                }
-            }
-            // lane l holds lags 16 jt + (l % 16) - 4 (l / 16) - i; lanes l, l + 20, l + 40, l + 60 hold the same
-            const bool has20 = g < 3 && col < 12, has40 = g < 2 && col < 8;
-            const bool head = g == 0 || col < 4;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const uint32_t jt = 8 * tg + t;
-                if (jt >= ms.nt) continue;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    int v = d[t][i];
-                    const int v20 = __shfl(v, (int)lane + 20 < 64 ? (int)lane + 20 : (int)lane, 64);
-                    v += has20 ? v20 : 0;
-                    const int v40 = __shfl(v, (int)lane + 40 < 64 ? (int)lane + 40 : (int)lane, 64);
-                    v += has40 ? v40 : 0;
-                    const int k = (int)(16 * jt + col) - (int)(4 * g + i);
-                    if (head && k >= 0 && k <= (int)L && v != 0) atomicAdd(&acc[k], (unsigned long long)(long long)v);
-                }
-            }
-        }
-    }
-    // 256 T: the block's byte total, added to every lag with the block's sums
-    __shared__ unsigned long long tred[DIAG_WG];
-    const unsigned long long tot = block_sum<unsigned long long>(tsum, tred);
-    __syncthreads();
-    // copy layout: lags 0..L_all, then the byte total (added by the first window only)
-    unsigned long long *copy = merge + (size_t)(blockIdx.x % DIAG_MERGE) * (L_all + 2);
-    for (uint32_t k = threadIdx.x; k <= L; k += DIAG_WG) {
-        const unsigned long long v = acc[k] + 256ull * tot;
-        if (v) atomicAdd(&copy[k_lo + k], v);
-    }
-    if (k_lo == 0 && threadIdx.x == 0 && tot) atomicAdd(&copy[L_all + 1], tot);
-}
 
 // ---- the lag sums for lags up to 256: 32-byte rows, 32 x 32 x 32 int8 products ----------------
 //
-// The same sums with the bytes as rows of 32: G_t[c][j] = sum_r x'[32 r + c] x'[32 (r + t) + j]
-// (c, j < 32) holds lag k = 32 t + j - c, and tiles t = 0 .. NT - 1 with NT = (L + 31) / 32 + 1
-// cover lags 0..L with no tile to spare (nine for L = 256).  One v_mfma_i32_32x32x32_i8 takes 32
+// Tiles t = 0 .. NT - 1 with NT = (L + 31) / 32 + 1 cover lags 0..L with no tile to spare (nine
+// for L = 256).  One v_mfma_i32_32x32x32_i8 takes 32
 // rows: lane l supplies column l % 32 of rows 16 (l / 32) .. + 15 as its 16 operand bytes, A
 // unshifted and B shifted by t rows, so the same LDS column serves both and B comes from one
 // 24-byte read by alignbyte.  The result's register i in lane l is G[8 (i / 4) + 4 (l / 32) + i % 4][l % 32].
@@ -519,6 +332,181 @@ __global__ __launch_bounds__(DIAG_WG) __attribute__((amdgpu_waves_per_eu(2))) vo
     if (t == 0 && tot) atomicAdd(&copy[L + 1], tot);
 }
 
+// ---- the lag sums past lag 256: windows of lags on 32-byte rows ---------------------------------
+//
+// One launch per window of lags k_lo .. k_lo + Lw (k_lo a multiple of 32, Lw < LW_WINDOW): the
+// products of the kernel above, B taken from the rows k_lo / 32 further on.  A task stages its own
+// LW_ROWS rows (region A) and, apart, the rows from k_lo / 32 on that its shifted operands read
+// (region B, LW_ROWS + LW_BHALO rows), so a window's LDS does not grow with k_lo.  A window has up
+// to 129 tiles: the two waves w and w + 4 take the tiles t = s + 4 f (s = w mod 4: one shift within
+// a word for all of them), split near the middle of f, each in items of up to LW_IT consecutive f
+// over all the task's rows; at the end of an item its accumulators are added into the LDS lag
+// counters (unconditionally: counters for relative lags -32 .. 32 NT - 1).  Each workgroup adds
+// its sums plus 256 times its bytes' total into copy b mod DIAG_MERGE of the merge buffer (the
+// first window also the total), and lagsum_fix_kernel applies the correction.
+constexpr uint32_t LW_ROWS = 1024;
+constexpr int LW_WG = 512;
+constexpr uint32_t LW_IT = 4;                                 // tiles per item
+constexpr uint32_t LW_WINDOW = 4096;                          // lags per window at most
+constexpr uint32_t LW_MAX_NT = LW_WINDOW / 32 + 1;            // 129 tiles
+constexpr uint32_t LW_MAX_F = (LW_MAX_NT + 3) / 4;            // tiles of one residue mod 4
+// B bytes read by an item at f0 (a multiple of 4): 4 f0 + 16 h + up to 32 past the row block
+constexpr uint32_t LW_BHALO = 4 * LW_IT * ((LW_MAX_F - 1) / LW_IT) + 48;
+// LDS bytes per column: the next odd multiple of 16 above the rows (no bank conflicts between columns)
+constexpr uint32_t lw_stride(uint32_t rows) { return (rows / 16 + 1) % 2 ? (rows / 16 + 1) * 16 : (rows / 16 + 2) * 16; }
+constexpr uint32_t LW_ASTRIDE = lw_stride(LW_ROWS), LW_BSTRIDE = lw_stride(LW_ROWS + LW_BHALO);
+constexpr uint32_t LW_APIECES = LW_ROWS / 4, LW_BPIECES = (LW_ROWS + LW_BHALO) / 4;  // 4 rows x 32 bytes
+constexpr uint32_t LW_PV = (LW_APIECES + LW_BPIECES + LW_WG - 1) / LW_WG;  // pieces per thread
+static_assert(LW_ROWS % 32 == 0 && (uint64_t)LW_ROWS * 16384 < (1ull << 31), "32-bit accumulators per item");
+static_assert((size_t)DIAG_MERGE * (16384 + 2) <= DIAG_MERGE_WORDS, "merge buffer too small");
+
+// bytes of rows 4e .. 4e + 3 (w[r][word], 8 words a row) written transposed: column c of the
+// region gets the word of rows 4e..4e+3 at word index e
+__device__ inline void ls_put_rows4(uint32_t *region32, uint32_t stride_words, uint32_t e, const uint32_t (&w)[4][8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t lo01 = __byte_perm(w[0][q], w[1][q], 0x5140), hi01 = __byte_perm(w[0][q], w[1][q], 0x7362);
+        const uint32_t lo23 = __byte_perm(w[2][q], w[3][q], 0x5140), hi23 = __byte_perm(w[2][q], w[3][q], 0x7362);
+        region32[(4 * q + 0) * stride_words + e] = __byte_perm(lo01, lo23, 0x5410);
+        region32[(4 * q + 1) * stride_words + e] = __byte_perm(lo01, lo23, 0x7632);
+        region32[(4 * q + 2) * stride_words + e] = __byte_perm(hi01, hi23, 0x5410);
+        region32[(4 * q + 3) * stride_words + e] = __byte_perm(hi01, hi23, 0x7632);
+    }
+}
+
+// One item: tiles sh + 4 (f0 + q), q < NV, over all LW_ROWS rows of the staged task (ap: the
+// lane's A column at its 16-row half, bp: its B column from byte 4 f0 on, so tile q's B operand is
+// the words q .. q + 4 shifted by sh bytes), then its accumulators added into the lag counters
+// (diag: the lag counter of d[0][0] for this lane).
+template <int NV>
+__device__ __forceinline__ void lw_item(const uint8_t *ap, const uint8_t *bp, uint32_t sh, unsigned long long *diag) {
+    constexpr int NB = (NV + 7) / 4;  // 16-byte B reads per row block: words 0 .. NV + 3
+    v16i d[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) d[q] = (v16i){};
+    // row blocks of 32; the next block's words are read before this one's products
+    uint4 av = *reinterpret_cast<const uint4 *>(ap);
+    uint4 bw[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) bw[u] = *reinterpret_cast<const uint4 *>(bp + 16 * u);
+#pragma unroll 2
+    for (uint32_t rb = 0; rb < LW_ROWS; rb += 32) {
+        uint32_t w[4 * NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) w[4 * u] = bw[u].x, w[4 * u + 1] = bw[u].y, w[4 * u + 2] = bw[u].z, w[4 * u + 3] = bw[u].w;
+        const v4i a = (v4i){(int)av.x, (int)av.y, (int)av.z, (int)av.w};
+        if (rb + 32 < LW_ROWS) {
+            av = *reinterpret_cast<const uint4 *>(ap + rb + 32);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) bw[u] = *reinterpret_cast<const uint4 *>(bp + rb + 32 + 16 * u);
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            v4i b;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = (int)__builtin_amdgcn_alignbyte(w[q + j + 1], w[q + j], sh);
+            d[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, d[q], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) atomicAdd(diag + (128 * q - 8 * (i / 4) - i % 4), (unsigned long long)(long long)d[q][i]);
+}
+
+__global__ __launch_bounds__(LW_WG) void lagsum_wide_kernel(const uint8_t *data, uint64_t n, uint32_t Lw,
+                                                              uint32_t k_lo, uint32_t L_all,
+                                                              unsigned long long *merge) {
+    __shared__ __align__(16) uint8_t la[32 * LW_ASTRIDE];
+    __shared__ __align__(16) uint8_t lb[32 * LW_BSTRIDE];
+    __shared__ unsigned long long cnt_all[32 * LW_MAX_NT + 32];
+    __shared__ long long wred[LW_WG / 64];
+    const uint32_t NT = (Lw + 31) / 32 + 1;
+    unsigned long long *cnt = cnt_all + 32;
+    const uint32_t t = threadIdx.x, lane = t % 64, col = lane % 32, h = lane / 32;
+    for (uint32_t k = t; k < 32 * NT + 32; k += LW_WG) cnt_all[k] = 0;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(t / 64), sh = wave % 4, half = wave / 4;
+    const uint32_t F = NT > sh ? (NT - sh + 3) / 4 : 0;  // tiles sh, sh + 4, ... below NT
+    const bool aligned16 = (reinterpret_cast<uintptr_t>(data) & 15) == 0;
+    const uint64_t nrows = (n + 31) / 32, tasks = (nrows + LW_ROWS - 1) / LW_ROWS, bshift = k_lo / 32;
+    // piece p = t + LW_WG v: rows 4p .. 4p + 3 of region A (p < LW_APIECES), else rows
+    // 4 (p - LW_APIECES) .. + 3 of region B; pw[v][row][word]
+    uint32_t pw[LW_PV][4][8];
+    auto load = [&](uint64_t task) {
+#pragma unroll
+        for (uint32_t v = 0; v < LW_PV; ++v) {
+            const uint32_t p = t + LW_WG * v;
+            const uint64_t r0 = p < LW_APIECES ? task * LW_ROWS + 4 * (uint64_t)p
+                                               : task * LW_ROWS + bshift + 4 * (uint64_t)(p - LW_APIECES);
+            const bool live = p < LW_APIECES + LW_BPIECES;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const uint4 x = live ? ls_load16(data, n, (r0 + r) * 32 + 16 * q, aligned16, 16) : make_uint4(0, 0, 0, 0);
+                    pw[v][r][4 * q + 0] = x.x, pw[v][r][4 * q + 1] = x.y, pw[v][r][4 * q + 2] = x.z, pw[v][r][4 * q + 3] = x.w;
+                }
+        }
+    };
+    int tsum = 0;  // this thread's share of sum (x - 128) over the tasks' own rows
+    if (blockIdx.x < tasks) load(blockIdx.x);
+    for (uint64_t task = blockIdx.x; task < tasks; task += gridDim.x) {
+        __syncthreads();  // the previous task's operand reads are done
+#pragma unroll
+        for (uint32_t v = 0; v < LW_PV; ++v) {
+            const uint32_t p = t + LW_WG * v;
+            if (p < LW_APIECES) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) tsum = __builtin_amdgcn_sdot4((int)pw[v][r][q], 0x01010101, tsum, false);
+                ls_put_rows4(reinterpret_cast<uint32_t *>(la), LW_ASTRIDE / 4, p, pw[v]);
+            } else if (p < LW_APIECES + LW_BPIECES) {
+                ls_put_rows4(reinterpret_cast<uint32_t *>(lb), LW_BSTRIDE / 4, p - LW_APIECES, pw[v]);
+            }
+        }
+        __syncthreads();
+        if (task + gridDim.x < tasks) load(task + gridDim.x);  // in flight during the products
+        // this wave's tiles sh + 4 f for f in [fs, fe): the two waves of a shift split its F tiles near
+        // the middle, at a multiple of 4 (16-byte aligned B reads), in items of up to LW_IT
+        const uint8_t *ap = la + col * LW_ASTRIDE + 16 * h;
+        const uint32_t fsplit = 4 * ((F + 4) / 8), fs = half ? fsplit : 0, fe = half ? F : fsplit;
+        for (uint32_t f0 = fs; f0 < fe; f0 += LW_IT) {
+            const uint32_t nv = fe - f0 < LW_IT ? fe - f0 : LW_IT;
+            const uint8_t *bp = lb + col * LW_BSTRIDE + 16 * h + 16 * (f0 / 4);  // 16-byte aligned
+            unsigned long long *diag = cnt + 32 * (sh + 4 * f0) + (int)col - 4 * (int)h;
+            static_assert(LW_IT == 4, "one instantiation per item width");
+            switch (nv) {
+                case 4: lw_item<4>(ap, bp, sh, diag); break;
+                case 3: lw_item<3>(ap, bp, sh, diag); break;
+                case 2: lw_item<2>(ap, bp, sh, diag); break;
+                default: lw_item<1>(ap, bp, sh, diag); break;
+            }
+        }
+    }
+    // the bytes' total: sum (x - 128) over the own rows plus 128 per own byte
+    unsigned long long nb = 0;
+    for (uint64_t tk = blockIdx.x; tk < tasks; tk += gridDim.x) {
+        const uint64_t b0 = tk * LW_ROWS * 32, b1 = b0 + LW_ROWS * 32;
+        nb += (b1 < n ? b1 : n) - b0;
+    }
+    long long ws = tsum;
+    for (int o = 32; o > 0; o >>= 1) ws += __shfl_down(ws, o, 64);
+    if (lane == 0) wred[wave] = ws;
+    __syncthreads();  // also: every wave's counter adds are done
+    long long all = 0;
+#pragma unroll
+    for (int w = 0; w < LW_WG / 64; ++w) all += wred[w];
+    const unsigned long long tot = (unsigned long long)all + 128ull * nb;
+    // copy layout: lags 0..L_all, then the byte total (added by the first window only)
+    unsigned long long *copy = merge + (size_t)(blockIdx.x % DIAG_MERGE) * (L_all + 2);
+    for (uint32_t r = t; r <= Lw; r += LW_WG) {
+        const unsigned long long v = cnt[r] + 256ull * tot;
+        if (v) atomicAdd(&copy[k_lo + r], v);
+    }
+    if (k_lo == 0 && t == 0 && tot) atomicAdd(&copy[L_all + 1], tot);
+}
+
 // The correction for L <= 256 (one window, one workgroup of LS_FIX_WG threads): thread k takes
 // lag k, sums its LS_COPIES merge copies (all loads issued before the first is used) and clears
 // them; the first and last L bytes are loaded at the same time, and P_k + Q_k comes from one scan
@@ -572,100 +560,87 @@ __global__ __launch_bounds__(LS_FIX_WG) void lagsum_fix_small_kernel(const uint8
     }
 }
 
-// S_k = raw_k - 128 (P_k + Q_k) - 16384 max(n - k, 0) for k <= L, raw_k the sum of the
-// merge copies (cleared here for the next call), with P_k and Q_k the sums of the first
-// and the last min(k, n) bytes (one workgroup per window of 4096 lags: it first sums the
-// first and the last kb bytes of its window's start kb, then thread t holds values
-// kb + 16t .. kb + 16t + 15 of both ends, and a block-wide scan gives the rest).
+// S_k = raw_k - 128 (P_k + Q_k) - 16384 max(n - k, 0) for k <= L, raw_k the sum of the merge
+// copies (cleared here for the next call), P_k and Q_k the sums of the first and the last min(k, n)
+// bytes.  Workgroup b takes lags kb = FIX_LAGS b .. kb + FIX_LAGS - 1, a lag per thread: it adds
+// up the first and the last min(kb, n) bytes (16-byte loads where aligned), then scans
+// x_j + x_{n-1-j} over its own lags (a wave scan by shuffles, the wave totals through LDS); every
+// load of a thread is issued before the first is used.  The first workgroup also writes the
+// byte total when asked for.
+constexpr int FIX_LAGS = DIAG_WG;
+
+// sum of data[lo, hi) over the block: each thread adds its 16-byte chunks and the unaligned ends
+__device__ inline unsigned long long fix_range_part(const uint8_t *data, uint64_t lo, uint64_t hi) {
+    if (lo >= hi) return 0;
+    const uintptr_t base = reinterpret_cast<uintptr_t>(data);
+    uint64_t a = ((base + lo + 15) & ~(uintptr_t)15) - base;  // first 16-byte aligned index >= lo
+    if (a > hi) a = hi;
+    uint64_t z = ((base + hi) & ~(uintptr_t)15) - base;        // last aligned index <= hi
+    if (z < a) z = a;
+    unsigned long long s = 0;
+    const uint32_t t = threadIdx.x;
+    if (t < a - lo) s += data[lo + t];   // head, under 16 bytes
+    if (t < hi - z) s += data[z + t];    // tail, under 16 bytes
+    constexpr int U = 4;                 // chunks in flight per thread
+    for (uint64_t c0 = a + 16 * (uint64_t)t; c0 < z; c0 += (uint64_t)16 * DIAG_WG * U) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t c = c0 + (uint64_t)16 * DIAG_WG * u;
+            v[u] = c < z ? *reinterpret_cast<const uint4 *>(data + c) : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            s += __builtin_amdgcn_udot4(v[u].x, 0x01010101u, 0u, false) + __builtin_amdgcn_udot4(v[u].y, 0x01010101u, 0u, false) +
+                 __builtin_amdgcn_udot4(v[u].z, 0x01010101u, 0u, false) + __builtin_amdgcn_udot4(v[u].w, 0x01010101u, 0u, false);
+    }
+    return s;
+}
+
 __global__ __launch_bounds__(DIAG_WG) void lagsum_fix_kernel(const uint8_t *data, uint64_t n, uint32_t L,
                                                              unsigned long long *merge, unsigned long long *sums,
                                                              unsigned long long *total) {
-    constexpr uint32_t SEG = MC_WINDOW / DIAG_WG;  // 16
-    __shared__ uint32_t scan[2][DIAG_WG];
-    __shared__ unsigned long long raw[MC_WINDOW];
-    const uint32_t t = threadIdx.x;
-    if (blockIdx.x == 0 && t < 64) {  // wave 0: the byte total over the copies (cleared), to *total when asked for
-        unsigned long long v = 0;
-        if (t < DIAG_MERGE) {
-            v = merge[(size_t)t * (L + 2) + L + 1];
-            merge[(size_t)t * (L + 2) + L + 1] = 0;
-        }
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-        if (t == 0 && total) *total = v;
+    __shared__ unsigned long long wtot[DIAG_WG / 64];
+    __shared__ uint32_t wscan[DIAG_WG / 64];
+    const uint32_t t = threadIdx.x, lane = t % 64, wave = t / 64;
+    const uint32_t kb = blockIdx.x * FIX_LAGS, k = kb + t;
+    const size_t cs = (size_t)L + 2;  // copy stride: lags 0..L, then the byte total
+    unsigned long long part[DIAG_MERGE], tc = 0;
+#pragma unroll
+    for (int c = 0; c < DIAG_MERGE; ++c) part[c] = k <= L ? merge[c * cs + k] : 0ull;
+    if (blockIdx.x == 0 && t < DIAG_MERGE) tc = merge[t * cs + L + 1];
+    const uint32_t x = k < L && k < n ? (uint32_t)data[k] + data[n - 1 - k] : 0u;  // j = k, for the lags above k
+    const uint64_t m = kb < n ? kb : n;
+    unsigned long long base = fix_range_part(data, 0, m) + fix_range_part(data, n - m, n);
+    // the block's sums: base over all threads, wave scans of x
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if ((int)lane >= o) inc += y;
     }
-    const uint32_t kb = blockIdx.x * MC_WINDOW;  // this workgroup's lags kb .. ke
-    if (kb > L) return;
-    const uint32_t ke = L - kb < MC_WINDOW - 1 ? L : kb + MC_WINDOW - 1;
-    unsigned long long c0 = 0, c1 = 0;  // sums of the first and of the last kb bytes
-    {
-        __shared__ unsigned long long base[2][DIAG_WG];
-        unsigned long long b0 = 0, b1 = 0;
-        const uint64_t m = kb < n ? kb : n;
-        for (uint64_t j = t; j < m; j += DIAG_WG) b0 += data[j], b1 += data[n - 1 - j];
-        base[0][t] = b0;
-        base[1][t] = b1;
-        __syncthreads();
-        for (int w = DIAG_WG / 2; w > 0; w >>= 1) {
-            if ((int)t < w) base[0][t] += base[0][t + w], base[1][t] += base[1][t + w];
-            __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) base += __shfl_down(base, o, 64);
+    for (int o = 32; o > 0; o >>= 1) tc += __shfl_down(tc, o, 64);
+    if (lane == 63) wscan[wave] = inc;
+    if (lane == 0) wtot[wave] = base;
+    __syncthreads();
+    unsigned long long pq = 0;  // P_k + Q_k: the bytes j < k of both ends
+#pragma unroll
+    for (uint32_t w = 0; w < DIAG_WG / 64; ++w) pq += wtot[w] + (w < wave ? wscan[w] : 0u);
+    pq += inc - x;
+    if (k <= L) {
+        unsigned long long raw = 0;
+#pragma unroll
+        for (int c = 0; c < DIAG_MERGE; ++c) {
+            raw += part[c];
+            merge[c * cs + k] = 0;
         }
-        c0 = base[0][0];
-        c1 = base[1][0];
+        const unsigned long long mk = k < n ? n - k : 0;
+        sums[k] = raw - 128ull * pq - 16384ull * mk;
     }
-    {
-        // the copies' sums, lag k on thread k mod 256 (all loads of a thread issued together)
-        for (uint32_t k0 = kb; k0 <= ke; k0 += DIAG_WG * 4) {
-            unsigned long long part[4][DIAG_MERGE];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t k = k0 + q * DIAG_WG + t;
-#pragma unroll
-                for (int c = 0; c < DIAG_MERGE; ++c) part[q][c] = k <= ke ? merge[(size_t)c * (L + 2) + k] : 0ull;
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t k = k0 + q * DIAG_WG + t;
-                if (k > ke) continue;
-                unsigned long long r = 0;
-#pragma unroll
-                for (int c = 0; c < DIAG_MERGE; ++c) {
-                    r += part[q][c];
-                    merge[(size_t)c * (L + 2) + k] = 0;
-                }
-                raw[k - kb] = r;
-            }
-        }
-        uint32_t v[2][SEG], tot[2] = {0, 0};
-#pragma unroll
-        for (uint32_t u = 0; u < SEG; ++u) {
-            const uint64_t j = (uint64_t)kb + t * SEG + u;
-            v[0][u] = j < n ? data[j] : 0u;          // x_j
-            v[1][u] = j < n ? data[n - 1 - j] : 0u;  // x_{n-1-j}
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < SEG; ++u) tot[0] += v[0][u], tot[1] += v[1][u];
-        scan[0][t] = tot[0];
-        scan[1][t] = tot[1];
-        __syncthreads();
-        for (uint32_t d = 1; d < DIAG_WG; d <<= 1) {  // inclusive scan (Hillis-Steele)
-            const uint32_t a0 = t >= d ? scan[0][t - d] : 0u, a1 = t >= d ? scan[1][t - d] : 0u;
-            __syncthreads();
-            scan[0][t] += a0;
-            scan[1][t] += a1;
-            __syncthreads();
-        }
-        // sums of the first and the last kb + 16 t values
-        unsigned long long p0 = c0 + (scan[0][t] - tot[0]), p1 = c1 + (scan[1][t] - tot[1]);
-#pragma unroll
-        for (uint32_t u = 0; u < SEG; ++u) {
-            const uint32_t k = kb + t * SEG + u;
-            if (k <= ke) {
-                const unsigned long long m = k < n ? n - k : 0;
-                sums[k] = raw[k - kb] - 128ull * (p0 + p1) - 16384ull * m;
-            }
-            p0 += v[0][u];
-            p1 += v[1][u];
-        }
+    if (blockIdx.x == 0) {
+        if (t < DIAG_MERGE) merge[t * cs + L + 1] = 0;
+        if (t == 0 && total) *total = tc;
     }
 }
 
@@ -1339,53 +1314,49 @@ namespace {
 // (diag_begin) and records the event afterwards itself.
 int lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, unsigned long long *sums,
              unsigned long long *total, hipStream_t s, bool ordered = false) {
-    // the matrix-core route, one launch per window of up to MC_WINDOW lags, when each fits in LDS
-    size_t mc_lds = 0;
-    const size_t lds_cu = (size_t)c->dev.lds_per_wg_max;  // gfx950: a workgroup may take the whole CU's LDS
-    for (uint32_t k_lo = 0; k_lo <= max_lag; k_lo += mc_window_last(max_lag, k_lo, lds_cu) + 1) {
-        const size_t b = lagsum_mc_lds_bytes(mc_window_last(max_lag, k_lo, lds_cu), k_lo);
-        mc_lds = b > mc_lds ? b : mc_lds;
-    }
-    if (mc_lds > (size_t)c->dev.lds_per_wg_max) return fail(LZ_E_INVAL, "lag sums need more LDS than the device has");
     if (n > 0) {
-        // the workgroups' sums meet in the context's merge copies, which the fix kernel adds up,
-        // writes to d_sums and clears: calls on different streams are ordered
-        static_assert((size_t)DIAG_MERGE * (16384 + 2) <= DIAG_MERGE_WORDS, "merge buffer too small");
+        // the workgroups' sums meet in the context's merge copies, which the correction kernel adds
+        // up, writes to d_sums and clears: calls on different streams are ordered
         char *ws;
         if (!ordered)
             if (int rc = diag_begin(c, s, 0, &ws)) return rc;
-        if (max_lag <= 32 * (LS_MAX_NT - 1)) {  // up to 256 lags: 32-byte rows, one launch
+        // resident workgroups only, as many tasks each (rounds = tasks / slots, rounded up)
+        auto grid = [&](const void *kern, int wg, uint64_t tasks, unsigned *blocks) -> int {
+            int per_cu = 0;
+            LZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, wg, 0));
+            if (per_cu < 1) return fail(LZ_E_INVAL, "lag sums need more LDS or registers than the device has");
+            const uint64_t slots = (uint64_t)c->dev.cus * (uint64_t)per_cu;
+            const uint64_t rounds = (tasks + slots - 1) / slots;
+            *blocks = (unsigned)((tasks + rounds - 1) / rounds);
+            return LZ_OK;
+        };
+        unsigned blocks = 0;
+        if (max_lag <= 32 * (LS_MAX_NT - 1)) {  // up to 256 lags: one launch
             const uint32_t nt = (max_lag + 31) / 32 + 1;
             void (*kern)(const uint8_t *, uint64_t, uint32_t, unsigned long long *) =
                 nt == 1 ? lagsum_small_kernel<1> : nt == 2 ? lagsum_small_kernel<2> : nt == 3 ? lagsum_small_kernel<3>
                 : nt == 4 ? lagsum_small_kernel<4> : nt == 5 ? lagsum_small_kernel<5> : nt == 6 ? lagsum_small_kernel<6>
                 : nt == 7 ? lagsum_small_kernel<7> : nt == 8 ? lagsum_small_kernel<8> : lagsum_small_kernel<9>;
-            // resident workgroups only, as many tasks each (rounds = tasks / slots, rounded up)
-            int per_cu = 0;
-            LZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, DIAG_WG, 0));
-            if (per_cu < 1) per_cu = 1;
-            const uint64_t tasks = ((n + 31) / 32 + LS_ROWS - 1) / LS_ROWS;
-            const uint64_t slots = (uint64_t)c->dev.cus * (uint64_t)per_cu;
-            const uint64_t rounds = (tasks + slots - 1) / slots;
-            const unsigned blocks = (unsigned)((tasks + rounds - 1) / rounds);
+            if (int rc = grid(reinterpret_cast<const void *>(kern), DIAG_WG, ((n + 31) / 32 + LS_ROWS - 1) / LS_ROWS, &blocks))
+                return rc;
             hipLaunchKernelGGL(kern, dim3(blocks), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag, c->diag_merge);
             hipLaunchKernelGGL(lagsum_fix_small_kernel, dim3(1), dim3(LS_FIX_WG), 0, s, d_data, (uint64_t)n, max_lag,
                                c->diag_merge, sums, total);
             LZ_HIP(hipGetLastError());
             return ordered ? LZ_OK : diag_end(c, s);
         }
-        if (mc_lds > 65536)
-            LZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&lagsum_mc_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)mc_lds));
-        const uint64_t tasks = ((n + 15) / 16 + MC_ROWS - 1) / MC_ROWS;
-        const uint64_t blocks = tasks < (uint64_t)c->dev.cus * 2 ? tasks : (uint64_t)c->dev.cus * 2;
-        for (uint32_t k_lo = 0; k_lo <= max_lag;) {
-            const uint32_t Lw = mc_window_last(max_lag, k_lo, lds_cu);
-            hipLaunchKernelGGL(lagsum_mc_kernel, dim3((unsigned)blocks), dim3(DIAG_WG), lagsum_mc_lds_bytes(Lw, k_lo),
-                               s, d_data, (uint64_t)n, Lw, k_lo, max_lag, c->diag_merge);
-            k_lo += Lw + 1;
+        // windows of at most LW_WINDOW lags, as even as 32-lag steps allow, one launch each
+        const uint64_t lags = (uint64_t)max_lag + 1, nwin = (lags + LW_WINDOW - 1) / LW_WINDOW;
+        const uint32_t W = (uint32_t)(((lags + nwin - 1) / nwin + 31) / 32 * 32);
+        if (int rc = grid(reinterpret_cast<const void *>(&lagsum_wide_kernel), LW_WG,
+                          ((n + 31) / 32 + LW_ROWS - 1) / LW_ROWS, &blocks))
+            return rc;
+        for (uint32_t k_lo = 0; k_lo <= max_lag; k_lo += W) {
+            const uint32_t Lw = max_lag - k_lo < W - 1 ? max_lag - k_lo : W - 1;
+            hipLaunchKernelGGL(lagsum_wide_kernel, dim3(blocks), dim3(LW_WG), 0, s, d_data, (uint64_t)n, Lw, k_lo,
+                               max_lag, c->diag_merge);
         }
-        hipLaunchKernelGGL(lagsum_fix_kernel, dim3(max_lag / MC_WINDOW + 1), dim3(DIAG_WG), 0, s, d_data,
+        hipLaunchKernelGGL(lagsum_fix_kernel, dim3(max_lag / FIX_LAGS + 1), dim3(DIAG_WG), 0, s, d_data,
                            (uint64_t)n, max_lag, c->diag_merge, sums, total);
         LZ_HIP(hipGetLastError());
         return ordered ? LZ_OK : diag_end(c, s);
