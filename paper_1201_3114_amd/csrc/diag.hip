@@ -157,6 +157,15 @@ static_assert((uint64_t)LS_FLUSH * LS_ROWS * 16384 < (1ull << 31), "32-bit accum
 
 typedef int v16i __attribute__((ext_vector_type(16)));
 
+// Raw bytes i0 .. i0 + nb - 1 loaded one by one, 0x80 for bytes at or past n (the XOR with 0x80
+// that turns the others into x - 128 then makes them 0).
+__device__ inline uint4 ls_bytes(const uint8_t *data, uint64_t n, uint64_t i0, uint32_t nb) {
+    uint32_t w[4] = {0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u};
+    for (uint32_t b = 0; b < nb; ++b)
+        if (i0 + b < n) w[b / 4] = (w[b / 4] & ~(0xFFu << (8 * (b % 4)))) | ((uint32_t)data[i0 + b] << (8 * (b % 4)));
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 __device__ inline uint4 ls_load16(const uint8_t *data, uint64_t n, uint64_t i0, bool aligned16, uint32_t nb) {
     // bytes i0 .. i0 + nb - 1 (nb = 8 or 16, i0 a multiple of nb) as x - 128 (XOR 0x80), 0 past n
     if (aligned16 && i0 + nb <= n) {
@@ -196,28 +205,73 @@ __global__ __launch_bounds__(DIAG_WG) __attribute__((amdgpu_waves_per_eu(2))) vo
 #pragma unroll
     for (int q = 0; q < F + S; ++q) d[q] = (v16i){};
     // piece p = t + DIAG_WG v: rows 4 (p / PQ) .. + 3, bytes LS_CB (p % PQ) .. + LS_CB - 1 of each
-    // (PQ = 32 / LS_CB pieces per 4 rows), as LS_CB / 4 words per row: pw[v][row][word]; thread
-    // t < 2 LS_HALO also one half row of the halo
-    constexpr uint32_t PQ = 32 / LS_CB, PW = LS_CB / 4;
+    // (PQ = 32 / LS_CB pieces per 4 rows), as LS_CB / 4 raw words per row: pw[v][row][word]; every
+    // thread also one half row of the halo (thread t mod 2 LS_HALO's).  Each load is issued
+    // unconditionally, from offset 0 when its bytes are not all inside aligned data (bit set in
+    // redo); those are fetched again byte by byte when the task is staged, where the thread waits
+    // for its loads anyway.
+    constexpr uint32_t PQ = 32 / LS_CB, PW = LS_CB / 4, NL = 4 * LS_EV * ((PW + 3) / 4);  // loads per task
+    static_assert(NL < 32, "one redo bit per load and the halo");
+    const bool vec = aligned16 && n >= 16;
     uint32_t pw[LS_EV][4][PW];
     uint4 ph = make_uint4(0, 0, 0, 0);
+    uint32_t redo = 0;
+    auto piece_at = [&](uint64_t b0, uint32_t v, int r, uint32_t hw) -> uint64_t {
+        const uint32_t pc = t + DIAG_WG * v;
+        return b0 + (4 * (uint64_t)(pc / PQ) + r) * 32 + LS_CB * (pc % PQ) + 4 * hw;
+    };
+    auto halo_at = [&](uint64_t b0) -> uint64_t {
+        return b0 + (uint64_t)(LS_ROWS + (t % (2 * LS_HALO)) / 2) * 32 + 16 * (t % 2);
+    };
+    auto put = [&](uint32_t v, int r, uint32_t hw, const uint4 &x) {
+        pw[v][r][hw] = x.x;
+        if (PW > 1) pw[v][r][hw + 1] = x.y;
+        if (PW > 2) pw[v][r][hw + 2] = x.z;
+        if (PW > 3) pw[v][r][hw + 3] = x.w;
+    };
     auto load = [&](uint64_t task) {
         const uint64_t b0 = task * LS_ROWS * 32;
+        if (!vec) {  // misaligned data or under 16 bytes: every load byte by byte (no offset-0 load)
+            redo = (2u << NL) - 1;
+            return;
+        }
+        redo = 0;
+        uint32_t k = 0;
 #pragma unroll
-        for (uint32_t v = 0; v < LS_EV; ++v) {
-            const uint32_t pc = t + DIAG_WG * v, e = pc / PQ, cb = LS_CB * (pc % PQ);
+        for (uint32_t v = 0; v < LS_EV; ++v)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (uint32_t hw = 0; hw < PW; hw += 4) {
-                    const uint4 x = ls_load16(data, n, b0 + (4 * (uint64_t)e + r) * 32 + cb + 4 * hw, aligned16, PW >= 4 ? 16 : 4 * PW);
-                    pw[v][r][hw] = x.x;
-                    if (PW > 1) pw[v][r][hw + 1] = x.y;
-                    if (PW > 2) pw[v][r][hw + 2] = x.z;
-                    if (PW > 3) pw[v][r][hw + 3] = x.w;
+                for (uint32_t hw = 0; hw < PW; hw += 4, ++k) {
+                    const uint64_t i0 = piece_at(b0, v, r, hw);
+                    const bool in = i0 + 4 * (PW >= 4 ? 4 : PW) <= n;
+                    redo |= in ? 0u : 1u << k;
+                    const uint8_t *src = data + (in ? i0 : 0);
+                    if (PW >= 4) {
+                        put(v, r, hw, *reinterpret_cast<const uint4 *>(src));
+                    } else {
+                        const uint2 u = *reinterpret_cast<const uint2 *>(src);
+                        put(v, r, hw, make_uint4(u.x, u.y, 0u, 0u));
+                    }
                 }
-        }
-        if (t < 2 * LS_HALO) ph = ls_load16(data, n, b0 + (uint64_t)(LS_ROWS + t / 2) * 32 + 16 * (t % 2), aligned16, 16);
+        const uint64_t hb = halo_at(b0);
+        const bool in = hb + 16 <= n;
+        redo |= in ? 0u : 1u << NL;
+        ph = *reinterpret_cast<const uint4 *>(data + (in ? hb : 0));
+    };
+    // the loads that were not all inside aligned data, byte by byte (tail and misaligned data only)
+    auto fixup = [&](uint64_t task) {
+        if (!redo) return;
+        const uint64_t b0 = task * LS_ROWS * 32;
+        uint32_t k = 0;
+#pragma unroll
+        for (uint32_t v = 0; v < LS_EV; ++v)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (uint32_t hw = 0; hw < PW; hw += 4, ++k)
+                    if (redo >> k & 1) put(v, r, hw, ls_bytes(data, n, piece_at(b0, v, r, hw), PW >= 4 ? 16 : 4 * PW));
+        if (redo >> NL & 1) ph = ls_bytes(data, n, halo_at(b0), 16);
     };
     int tsum = 0;  // this thread's share of sum (x - 128) over the tasks' own rows
     // lag of d[q][i]: 32 tile + col - (8 (i / 4) + 4 h + i % 4), tile = wave + 4 q (q < F) or 4 F + q - F
@@ -238,6 +292,7 @@ __global__ __launch_bounds__(DIAG_WG) __attribute__((amdgpu_waves_per_eu(2))) vo
         const uint64_t stop =
             tasks - first < (uint64_t)LS_FLUSH * gridDim.x ? tasks : first + (uint64_t)LS_FLUSH * gridDim.x;
         for (uint64_t task = first; task < stop; task += gridDim.x) {
+            fixup(task);
             __syncthreads();  // the previous task's operand reads are done
             uint32_t *lt32 = reinterpret_cast<uint32_t *>(lt);
 #pragma unroll
@@ -248,7 +303,7 @@ __global__ __launch_bounds__(DIAG_WG) __attribute__((amdgpu_waves_per_eu(2))) vo
                     uint32_t r[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        r[q] = pw[v][q][w];
+                        r[q] = pw[v][q][w] ^ 0x80808080u;
                         tsum = __builtin_amdgcn_sdot4((int)r[q], 0x01010101, tsum, false);
                     }
                     // 4 x 4 byte transpose: column cb + 4 w + b gets bytes b of rows 0..3
@@ -262,7 +317,7 @@ __global__ __launch_bounds__(DIAG_WG) __attribute__((amdgpu_waves_per_eu(2))) vo
                 }
             }
             if (t < 2 * LS_HALO) {
-                const uint32_t w4[4] = {ph.x, ph.y, ph.z, ph.w};
+                const uint32_t w4[4] = {ph.x ^ 0x80808080u, ph.y ^ 0x80808080u, ph.z ^ 0x80808080u, ph.w ^ 0x80808080u};
 #pragma unroll
                 for (int b = 0; b < 16; ++b)
                     lt[(16 * (t % 2) + b) * LS_STRIDE + LS_ROWS + t / 2] = (uint8_t)(w4[b / 4] >> (8 * (b % 4)));
