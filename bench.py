@@ -308,6 +308,25 @@ def bench_streaming(lz, torch):
         ms = e[0].elapsed_time(e[1])
         res[f"chunks_of_{chunk}"] = dict(updates=(n + chunk - 1) // chunk, ms=ms, encrypt_GBps=n / ms / 1e6,
                                          equals_one_shot=bool(torch.equal(out, one)))
+    # deferred updates: small chunks staged and run together (64 MiB of staging), flushed at the end
+    for chunk in ((1 << 20) + 1, (64 << 10) + 1):
+        out.zero_()
+        st = lz.Stream(ctx, False, pw)
+        st.update_deferred(dP[:1], out=out[:1])  # allocates the staging buffer outside the timed region
+        st.close()
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        st = lz.Stream(ctx, False, pw)
+        for a in range(0, n, chunk):
+            b = min(a + chunk, n)
+            st.update_deferred(dP[a:b], out=out[a:b])
+        out[n:] = st.finish()
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        st.close()
+        ms = e[0].elapsed_time(e[1])
+        res[f"deferred_chunks_of_{chunk}"] = dict(updates=(n + chunk - 1) // chunk, ms=ms, encrypt_GBps=n / ms / 1e6,
+                                                  equals_one_shot=bool(torch.equal(out, one)))
     # a 256 MiB message (uniform bytes from torch's device generator) in chunks of 64 MiB + 1 byte
     g = torch.Generator(device="cuda")
     g.manual_seed(workloads.SEED["plain_64m"])

@@ -42,6 +42,9 @@ extern "C" {
 #define LZ_TAG_BYTES 24
 #define LZ_MAX_PASSWORD 64
 #define LZ_MAX_MESSAGE (1ull << 32)
+/* staging capacity of a stream's deferred updates (input and output each), and chunks per flush */
+#define LZ_STREAM_DEFER_BYTES (64ull << 20)
+#define LZ_STREAM_DEFER_CHUNKS 4096
 /* Block b of a message starts at r0 + b 2^-24 (every coordinate), so a
  * message may have at most 2^24 blocks: every start then lies within 1 of
  * r0.  With the default block_len of 256 every message up to 2^32 bytes
@@ -301,7 +304,7 @@ int lz_autotune_cached(lz_ctx *ctx, const char *path, double budget_ms, lz_launc
  *
  * lz_stream_open: pw host pointer, 1..64 bytes; the stream owns about 200
  * bytes of device memory (two chain checkpoints and the running tag) and one
- * event.  Synchronous. */
+ * event, and from its first deferred update a staging buffer.  Synchronous. */
 int lz_stream_open(lz_ctx *ctx, int decrypt, const uint8_t *pw, size_t n_pw, lz_stream **out);
 
 /* Processes the next n bytes: d_in and d_out device pointers of n bytes
@@ -311,13 +314,33 @@ int lz_stream_open(lz_ctx *ctx, int decrypt, const uint8_t *pw, size_t n_pw, lz_
  * streams.  LZ_E_INVAL after lz_stream_finish or past 2^32 bytes in total. */
 int lz_stream_update(lz_stream *st, const uint8_t *d_in, size_t n, uint8_t *d_out, void *stream);
 
-/* Ends the message.  Encrypt: writes the 24-byte tag to d_tag (device).
+/* Deferred update: the next n bytes as lz_stream_update computes them, but
+ * the chunk is copied (on stream, device to device) into the stream's staging
+ * buffer and runs later, together with the chunks queued after it, as one
+ * update over their concatenation: at lz_stream_flush, when LZ_STREAM_DEFER_BYTES
+ * are queued or LZ_STREAM_DEFER_CHUNKS chunks, before an immediate update, and at
+ * lz_stream_finish.  Small chunks then share one launch that fills the device.
+ * d_in may be reused as soon as stream reaches the call; d_out is written only
+ * by that later launch, on the stream it is made on, and must stay valid until
+ * then.  A chunk of LZ_STREAM_DEFER_BYTES or more runs at once, after any queued
+ * chunks.  The first deferred update allocates the staging buffer
+ * (2 x LZ_STREAM_DEFER_BYTES of device memory, freed by lz_stream_close;
+ * LZ_E_NOMEM or LZ_E_HIP if that fails, with nothing queued).  Ordered with the
+ * stream's other calls, also across streams.  Errors as lz_stream_update. */
+int lz_stream_update_deferred(lz_stream *st, const uint8_t *d_in, size_t n, uint8_t *d_out, void *stream);
+
+/* Runs the queued deferred chunks now, on stream (nothing to do: LZ_OK).  Their
+ * outputs are complete when stream reaches the end of this call's work.
+ * LZ_E_INVAL after lz_stream_finish. */
+int lz_stream_flush(lz_stream *st, void *stream);
+
+/* Ends the message (running any queued deferred chunks first).  Encrypt: writes the 24-byte tag to d_tag (device).
  * Decrypt: d_tag holds the received tag (device); the result goes to
  * d_status (device int32: LZ_OK or LZ_E_INTEGRITY), or, with d_status NULL,
  * the call synchronises and returns it. */
 int lz_stream_finish(lz_stream *st, uint8_t *d_tag, int32_t *d_status, void *stream);
 
-/* Bytes consumed so far. */
+/* Bytes consumed so far (queued deferred chunks included). */
 uint64_t lz_stream_position(const lz_stream *st);
 
 /* Waits for the stream's work and frees it. */

@@ -106,6 +106,8 @@ SIGNATURES = {
     "lz_autocorrelation_2d": (ctypes.c_int, [vp, vp, ctypes.c_uint32, ctypes.c_uint32, vp, vp]),
     "lz_stream_open": (ctypes.c_int, [vp, ctypes.c_int, u8p, ctypes.c_size_t, ctypes.POINTER(vp)]),
     "lz_stream_update": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp, vp]),
+    "lz_stream_update_deferred": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp, vp]),
+    "lz_stream_flush": (ctypes.c_int, [vp, vp]),
     "lz_stream_finish": (ctypes.c_int, [vp, vp, vp, vp]),
     "lz_stream_position": (ctypes.c_uint64, [vp]),
     "lz_stream_close": (ctypes.c_int, [vp]),

@@ -251,7 +251,26 @@ class Stream:
             out = torch.empty(n, dtype=torch.uint8, device=self.ctx.device)
         if n:
             check(B.lib.lz_stream_update(self._h, _dev_ptr(chunk), n, _dev_ptr(out), _stream(stream, self.ctx.device)))
+            self._deferred = []  # an immediate update runs the queued chunks first
         return out
+
+    def update_deferred(self, chunk: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """lz_stream_update_deferred: `out` is written only when the queued chunks run (flush, a full
+        staging buffer, an immediate update or finish); keep it alive until then."""
+        n = chunk.numel()
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=self.ctx.device)
+        if n:
+            self._deferred = getattr(self, "_deferred", [])
+            self._deferred.append(out)
+            check(B.lib.lz_stream_update_deferred(self._h, _dev_ptr(chunk), n, _dev_ptr(out),
+                                                  _stream(stream, self.ctx.device)))
+        return out
+
+    def flush(self, stream=None):
+        """lz_stream_flush: runs the queued deferred chunks."""
+        check(B.lib.lz_stream_flush(self._h, _stream(stream, self.ctx.device)))
+        self._deferred = []
 
     def finish(self, tag: torch.Tensor | None = None, status: torch.Tensor | None = None, stream=None):
         """Encrypt: returns the 24-byte tag tensor.  Decrypt: checks `tag`; raises IntegrityError
@@ -260,6 +279,7 @@ class Stream:
             tag = torch.empty(TAG_BYTES, dtype=torch.uint8, device=self.ctx.device) if tag is None else tag
         st = ctypes.c_void_p(status.data_ptr()) if status is not None else None
         check(B.lib.lz_stream_finish(self._h, _dev_ptr(tag), st, _stream(stream, self.ctx.device)))
+        self._deferred = []
         return tag
 
     @property

@@ -9,10 +9,18 @@
 // as slow as a whole block) as the lanes after the full blocks: they are
 // independent of the full blocks and of each other, since the new partial block
 // keeps its checkpoint in a second slot.
+//
+// A deferred update copies its chunk into the stream's staging buffer instead
+// and remembers where its output goes; a flush (explicit, when the buffer is
+// full, before an immediate update or at the end) runs the staged bytes as one
+// update and copies each chunk's output out.  Small chunks then share a launch
+// that fills the device, and the result is that of one update over their
+// concatenation.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "internal.h"
 
@@ -33,6 +41,14 @@ struct lz_stream {
     hipEvent_t ev;
     hipStream_t last;
     bool has_last;
+    // deferred updates: staged input and output (LZ_STREAM_DEFER_BYTES each, on first use)
+    struct Deferred {
+        uint8_t *out;
+        uint64_t off, n;
+    };
+    uint8_t *stage;      // input, then output
+    uint64_t fill;       // staged bytes
+    std::vector<Deferred> segs;
 };
 
 namespace {
@@ -42,6 +58,7 @@ void stream_free(lz_stream *st) {
     hipSetDevice(st->ctx->device);
     if (st->has_last) hipEventSynchronize(st->ev);
     if (st->dmem) hipFree(st->dmem);
+    if (st->stage) hipFree(st->stage);
     if (st->h_status) hipHostFree(st->h_status);
     if (st->ev) hipEventDestroy(st->ev);
     delete st;
@@ -94,17 +111,11 @@ extern "C" int lz_stream_open(lz_ctx *c, int decrypt, const uint8_t *pw, size_t 
     return LZ_OK;
 }
 
-extern "C" int lz_stream_update(lz_stream *st, const uint8_t *d_in, size_t n, uint8_t *d_out, void *stream) {
-    if (!st) return fail(LZ_E_INVAL, "stream is NULL");
-    if (st->finished) return fail(LZ_E_INVAL, "stream already finished");
-    if (n == 0) return LZ_OK;
-    if (!d_in || !d_out) return fail(LZ_E_INVAL, "NULL buffer");
+namespace {
+
+// One update over n bytes already checked (n > 0), on s, ordered after the stream's last work.
+int stream_step(lz_stream *st, const uint8_t *d_in, size_t n, uint8_t *d_out, hipStream_t s) {
     lz_ctx *c = st->ctx;
-    if (n > LZ_MAX_MESSAGE || st->pos + n > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
-    if (int rc = check_blocks(c->prm, st->pos + n, nullptr)) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    LZ_HIP(hipSetDevice(c->device));
-    if (int rc = stream_order(st, s)) return rc;
     const uint64_t B = c->prm.block_len;
     const uint64_t r = st->pos % B;
     const uint64_t h = r == 0 ? 0 : (n < B - r ? n : B - r);  // head: finishes the pending partial block
@@ -131,6 +142,84 @@ extern "C" int lz_stream_update(lz_stream *st, const uint8_t *d_in, size_t n, ui
                               st->tag, s));
     if (rem > 0) st->cur ^= 1;
     st->pos = pos0 + n;
+    return LZ_OK;
+}
+
+// Runs the staged chunks as one update and copies each chunk's output to where it goes.
+int stream_flush(lz_stream *st, hipStream_t s) {
+    if (st->fill == 0) return LZ_OK;
+    uint8_t *in = st->stage, *outb = st->stage + LZ_STREAM_DEFER_BYTES;
+    if (int rc = stream_step(st, in, st->fill, outb, s)) return rc;
+    for (const lz_stream::Deferred &d : st->segs)
+        LZ_HIP(hipMemcpyAsync(d.out, outb + d.off, d.n, hipMemcpyDeviceToDevice, s));
+    st->fill = 0;
+    st->segs.clear();
+    return LZ_OK;
+}
+
+int update_checks(lz_stream *st, const uint8_t *d_in, size_t n, uint8_t *d_out) {
+    if (!st) return fail(LZ_E_INVAL, "stream is NULL");
+    if (st->finished) return fail(LZ_E_INVAL, "stream already finished");
+    if (n == 0) return LZ_OK;
+    if (!d_in || !d_out) return fail(LZ_E_INVAL, "NULL buffer");
+    const uint64_t at = st->pos + st->fill;
+    if (n > LZ_MAX_MESSAGE || at + n > LZ_MAX_MESSAGE) return fail(LZ_E_INVAL, "message longer than 2^32 bytes");
+    return check_blocks(st->ctx->prm, at + n, nullptr);
+}
+
+}  // namespace
+
+extern "C" int lz_stream_update(lz_stream *st, const uint8_t *d_in, size_t n, uint8_t *d_out, void *stream) {
+    if (int rc = update_checks(st, d_in, n, d_out)) return rc;
+    if (n == 0) return LZ_OK;
+    hipStream_t s = (hipStream_t)stream;
+    LZ_HIP(hipSetDevice(st->ctx->device));
+    if (int rc = stream_order(st, s)) return rc;
+    if (int rc = stream_flush(st, s)) return rc;  // staged chunks come first
+    if (int rc = stream_step(st, d_in, n, d_out, s)) return rc;
+    return stream_record(st, s);
+}
+
+extern "C" int lz_stream_update_deferred(lz_stream *st, const uint8_t *d_in, size_t n, uint8_t *d_out, void *stream) {
+    if (int rc = update_checks(st, d_in, n, d_out)) return rc;
+    if (n == 0) return LZ_OK;
+    hipStream_t s = (hipStream_t)stream;
+    LZ_HIP(hipSetDevice(st->ctx->device));
+    if (int rc = stream_order(st, s)) return rc;
+    if (n >= LZ_STREAM_DEFER_BYTES) {  // a chunk this large fills the device by itself
+        if (int rc = stream_flush(st, s)) return rc;
+        if (int rc = stream_step(st, d_in, n, d_out, s)) return rc;
+        return stream_record(st, s);
+    }
+    if (!st->stage) {
+        const hipError_t e = hipMalloc(&st->stage, 2 * (size_t)LZ_STREAM_DEFER_BYTES);
+        if (e != hipSuccess) {
+            st->stage = nullptr;
+            return hip_fail(e, "stream staging buffer");
+        }
+    }
+    if (st->fill + n > LZ_STREAM_DEFER_BYTES || st->segs.size() >= LZ_STREAM_DEFER_CHUNKS)
+        if (int rc = stream_flush(st, s)) return rc;
+    LZ_HIP(hipMemcpyAsync(st->stage + st->fill, d_in, n, hipMemcpyDeviceToDevice, s));
+    try {
+        st->segs.push_back({d_out, st->fill, n});
+    } catch (...) {
+        return fail(LZ_E_NOMEM, "host allocation failed");
+    }
+    st->fill += n;
+    if (st->fill == LZ_STREAM_DEFER_BYTES)
+        if (int rc = stream_flush(st, s)) return rc;
+    return stream_record(st, s);
+}
+
+extern "C" int lz_stream_flush(lz_stream *st, void *stream) {
+    if (!st) return fail(LZ_E_INVAL, "stream is NULL");
+    if (st->finished) return fail(LZ_E_INVAL, "stream already finished");
+    if (st->fill == 0) return LZ_OK;
+    hipStream_t s = (hipStream_t)stream;
+    LZ_HIP(hipSetDevice(st->ctx->device));
+    if (int rc = stream_order(st, s)) return rc;
+    if (int rc = stream_flush(st, s)) return rc;
     return stream_record(st, s);
 }
 
@@ -141,6 +230,7 @@ extern "C" int lz_stream_finish(lz_stream *st, uint8_t *d_tag, int32_t *d_status
     hipStream_t s = (hipStream_t)stream;
     LZ_HIP(hipSetDevice(c->device));
     if (int rc = stream_order(st, s)) return rc;
+    if (int rc = stream_flush(st, s)) return rc;
     const int pending = st->pos % c->prm.block_len != 0;
     const int empty = st->pos == 0;
     int32_t *status = d_status ? d_status : st->status;
@@ -154,7 +244,7 @@ extern "C" int lz_stream_finish(lz_stream *st, uint8_t *d_tag, int32_t *d_status
     return LZ_OK;
 }
 
-extern "C" uint64_t lz_stream_position(const lz_stream *st) { return st ? st->pos : 0; }
+extern "C" uint64_t lz_stream_position(const lz_stream *st) { return st ? st->pos + st->fill : 0; }
 
 extern "C" int lz_stream_close(lz_stream *st) {
     stream_free(st);

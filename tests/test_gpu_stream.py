@@ -228,3 +228,132 @@ def test_many_streams_random_chunks(lz):
     for i in range(8):
         dsts[i].close()
         assert np.array_equal(host(backs[i])[:sizes[i]], Ps[i]), i
+
+
+def _deferred_run(lz, ctx, decrypt, pw, X, cuts, rng, tag=None):
+    """Runs the cuts of X through a stream with deferred updates, an immediate update now and then and
+    flushes at random points; returns the output (and the tag when encrypting)."""
+    import torch
+
+    st = lz.Stream(ctx, decrypt, pw)
+    out = torch.empty(sum(b - a for a, b in cuts), dtype=torch.uint8, device="cuda")
+    for a, b in cuts:
+        r = rng.random()
+        if r < 0.1:
+            st.update(X[a:b], out=out[a:b])
+        else:
+            st.update_deferred(X[a:b], out=out[a:b])
+        if r > 0.95:
+            st.flush()
+        assert st.position == b
+    res = st.finish(tag=tag)
+    st.close()
+    return out, res
+
+
+@pytest.mark.parametrize("n", [0, 1, 257, 70000, 300_001])
+def test_deferred_updates_equal_one_shot(lz, n):
+    """Deferred updates (chunks staged and run together at a flush, before an immediate update or at the
+    end) give the one-shot ciphertext and tag, and decrypt back, whatever the chunking."""
+    import torch
+
+    rng = np.random.default_rng(90 + n)
+    ctx = lz.Context(0, lz.params(n_it=25))
+    P = rng.integers(0, 256, n, dtype=np.uint8)
+    Pd = to_dev(P) if n else torch.zeros(0, dtype=torch.uint8, device="cuda")
+    one = host(ctx.encrypt(Pd, b"deferred pw"))
+    if n <= 70000:
+        assert np.array_equal(one, oracle.encrypt(b"deferred pw", P, n_it=25))
+    for trial in range(2):
+        cuts = _chunks(rng, n) if n else []
+        say("n", n, "chunks", len(cuts))
+        out, tag = _deferred_run(lz, ctx, False, b"deferred pw", Pd, cuts, rng)
+        assert np.array_equal(np.concatenate([host(out), host(tag)]), one), (n, trial)
+    C = to_dev(one)
+    back, _ = _deferred_run(lz, ctx, True, b"deferred pw", C, _chunks(rng, n) if n else [], rng, tag=C[n:n + 24].clone())
+    assert np.array_equal(host(back), P)
+
+
+def test_deferred_staging_limits(lz):
+    """Past the staging capacity (LZ_STREAM_DEFER_BYTES, 64 MiB: the queued chunks run first), a chunk that
+    large by itself (run at once), and more than LZ_STREAM_DEFER_CHUNKS small chunks: the 130 MiB result
+    equals the one-shot ciphertext (itself checked against the oracle at full size elsewhere)."""
+    import torch
+
+    MiB = 1 << 20
+    ctx = lz.Context(0, lz.params(n_it=4))
+    n = 130 * MiB + 4999 * 7
+    Pd = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda",
+                       generator=torch.Generator(device="cuda").manual_seed(93))
+    one = ctx.encrypt(Pd, b"staging pw")
+    cuts, pos = [], 0
+    for step in [MiB] * 63 + [MiB + 3, 64 * MiB, MiB - 3] + [7] * 4999:
+        cuts.append((pos, pos + step))
+        pos += step
+    cuts.append((pos, n))
+    assert cuts[-1][0] <= n
+    say("staging limits:", len(cuts), "chunks,", n, "bytes")
+    st = lz.Stream(ctx, False, b"staging pw")
+    out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    for a, b in cuts:
+        st.update_deferred(Pd[a:b], out=out[a:b])
+    tag = st.finish()
+    st.close()
+    assert torch.equal(torch.cat([out, tag]), one)
+
+
+def test_deferred_tamper_and_calls_after_finish(lz):
+    """A decrypt stream of deferred updates flags an altered byte at the end; a flush with nothing queued
+    is a no-op; deferred updates and flushes after finish are rejected."""
+    import torch
+
+    rng = np.random.default_rng(94)
+    ctx = lz.Context(0, lz.params(n_it=25))
+    P = rng.integers(0, 256, 9000, dtype=np.uint8)
+    C = ctx.encrypt(to_dev(P), b"tamper deferred")
+    for flip in (0, 4444, 8999, 9010):
+        bad = C.clone()
+        bad[flip] ^= 0x10
+        st = lz.Stream(ctx, True, b"tamper deferred")
+        st.flush()
+        out = torch.empty(9000, dtype=torch.uint8, device="cuda")
+        for a in range(0, 9000, 1000):
+            st.update_deferred(bad[a:a + 1000], out=out[a:a + 1000])
+        status = torch.full((1,), 9, dtype=torch.int32, device="cuda")
+        st.finish(tag=bad[9000:].clone(), status=status)
+        torch.cuda.synchronize()
+        assert int(status.item()) == -2, flip
+        with pytest.raises(lz.LorenzError):
+            st.update_deferred(bad[:10], out=out[:10])
+        with pytest.raises(lz.LorenzError):
+            st.flush()
+        st.close()
+
+
+def test_deferred_two_streams_on_two_hip_streams(lz):
+    """Two messages, each as deferred updates alternating between two HIP streams (a stream's calls are
+    ordered among themselves across HIP streams), flushed midway: both equal their one-shot results."""
+    import torch
+
+    rng = np.random.default_rng(95)
+    ctx = lz.Context(0, lz.params(n_it=25))
+    Ps = [rng.integers(0, 256, n, dtype=np.uint8) for n in (50_000, 33_333)]
+    Pds = [to_dev(P) for P in Ps]
+    ones = [host(ctx.encrypt(Pd, pw)) for Pd, pw in zip(Pds, (b"one", b"two"))]
+    hs = [torch.cuda.Stream(), torch.cuda.Stream()]
+    sts = [lz.Stream(ctx, False, pw) for pw in (b"one", b"two")]
+    outs = [torch.empty(len(P), dtype=torch.uint8, device="cuda") for P in Ps]
+    torch.cuda.synchronize()
+    cuts = [_chunks(rng, len(P)) for P in Ps]
+    for i in range(max(len(c) for c in cuts)):
+        for m in range(2):
+            if i < len(cuts[m]):
+                a, b = cuts[m][i]
+                sts[m].update_deferred(Pds[m][a:b], out=outs[m][a:b], stream=hs[(i + m) % 2])
+                if i == len(cuts[m]) // 2:
+                    sts[m].flush(stream=hs[(i + m + 1) % 2])
+    tags = [sts[m].finish(stream=hs[m]) for m in range(2)]
+    torch.cuda.synchronize()
+    for m in range(2):
+        assert np.array_equal(np.concatenate([host(outs[m]), host(tags[m])]), ones[m]), m
+        sts[m].close()
