@@ -343,7 +343,8 @@ int lz_stream_finish(lz_stream *st, uint8_t *d_tag, int32_t *d_status, void *str
 /* Bytes consumed so far (queued deferred chunks included). */
 uint64_t lz_stream_position(const lz_stream *st);
 
-/* Waits for the stream's work and frees it. */
+/* Waits for the stream's work and frees it (deferred chunks still queued are
+ * dropped: their outputs are never written). */
 int lz_stream_close(lz_stream *st);
 
 /* ---- serving: continuous batching ------------------------------------------------

@@ -153,15 +153,22 @@ void streams(lz_ctx *ctx) {
         EXPECT(lz_stream_open(ctx, dec, pw.data(), pw.size(), &st) == LZ_OK, "stream open");
         size_t off = 0;
         std::uniform_int_distribution<size_t> cut(0, 3000);
-        while (off < n) {
+        for (int k = 0; off < n; ++k) {  // immediate and deferred updates mixed, a flush now and then
             size_t len = std::min(n - off, cut(rng));
-            EXPECT(lz_stream_update(st, din.p + off, len, dout.p + off, nullptr) == LZ_OK, "update");
+            if (k % 3 == 2)
+                EXPECT(lz_stream_update(st, din.p + off, len, dout.p + off, nullptr) == LZ_OK, "update");
+            else
+                EXPECT(lz_stream_update_deferred(st, din.p + off, len, dout.p + off, nullptr) == LZ_OK, "deferred update");
+            if (k % 7 == 6) EXPECT(lz_stream_flush(st, nullptr) == LZ_OK, "flush");
             off += len;
+            EXPECT(lz_stream_position(st) == off, "position after a chunk");
         }
         EXPECT(lz_stream_position(st) == n, "position");
         int rc = lz_stream_finish(st, dtag.p, nullptr, nullptr);
         EXPECT(rc == LZ_OK, "finish rc=%d", rc);
         EXPECT(lz_stream_finish(st, dtag.p, nullptr, nullptr) == LZ_E_INVAL, "finish twice");
+        EXPECT(lz_stream_flush(st, nullptr) == LZ_E_INVAL, "flush after finish");
+        EXPECT(lz_stream_update_deferred(st, din.p, 1, dout.p, nullptr) == LZ_E_INVAL, "deferred update after finish");
         EXPECT(lz_stream_close(st) == LZ_OK, "close");
         auto out = to_host(dout.p, n);
         EXPECT(out == (dec ? P : std::vector<uint8_t>(C.begin(), C.begin() + n)), "stream body dec=%d", dec);
