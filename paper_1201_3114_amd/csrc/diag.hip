@@ -4,7 +4,8 @@
 // the circular autocorrelation matrix and the 2-D Fourier power spectrum.
 // Integer sums are exact (the results do not depend on the reduction order);
 // the floating-point results are binary64.  The lag sums are int8 matrix
-// products (in windows of 4096 lags) on the matrix cores; the 2-D transforms run
+// products on the matrix cores (up to lag 256 in one launch, beyond that in
+// windows of at most 4096 lags); the 2-D transforms run
 // as FFTs for sides with no prime factor above 5 and as binary64 matrix products
 // on the matrix cores otherwise.
 #include <hip/hip_runtime.h>
