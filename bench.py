@@ -412,11 +412,14 @@ def bench_diag(lz, torch, reps=5):
     L = 16384  # the largest lag count: four windows of 4096 lags on the int8 matrix cores
     ms = timed(lambda: lz.lag_sums(ctx, x[:n16], L))
     res["lag_sums_16MiB_lag16384"] = dict(ms=ms, int_MAC_per_s=n16 * (L + 1) / ms * 1e3)
-    # power-of-two sides: two FFT passes, bound by HBM; algorithmic bytes: the image (1 B per value)
-    # in, 16 B complex out and in again, 8 B |Z|^2 out
+    # power-of-two sides: two FFT passes; algorithmic bytes: the image (1 B per value) in, the half
+    # spectrum (h/2 + 1 of each column's h indices, 16 B complex) out and in again, 8 B |Z|^2 out
+    def spectrum_bytes(h, w):
+        return h * w + 2 * 16 * w * (h // 2 + 1) + 8 * h * w
+
     N = 1024
     ms = timed(lambda: lz.power_spectrum_2d(ctx, img))
-    res["power_spectrum_1024x1024"] = dict(ms=ms, route="fft", hbm_GBps=41 * N * N / ms / 1e6)
+    res["power_spectrum_1024x1024"] = dict(ms=ms, route="fft", hbm_GBps=spectrum_bytes(N, N) / ms / 1e6)
     ms = timed(lambda: lz.autocorrelation_2d(ctx, img))
     res["autocorrelation_2d_1024x1024"] = dict(ms=ms, route="fft")
     a = lz.autocorrelation_2d(ctx, img)
@@ -425,14 +428,18 @@ def bench_diag(lz, torch, reps=5):
     N = 1000
     img_m = x[:N * N].view(N, N)
     ms = timed(lambda: lz.power_spectrum_2d(ctx, img_m))
-    res["power_spectrum_1000x1000"] = dict(ms=ms, route="mixed-radix fft", hbm_GBps=41 * N * N / ms / 1e6)
-    # other sides (1009 is prime): the direct DFT, a dense complex matrix product on the binary64 matrix cores
+    res["power_spectrum_1000x1000"] = dict(ms=ms, route="mixed-radix fft",
+                                           hbm_GBps=spectrum_bytes(N, N) / ms / 1e6)
+    # other sides (1009 is prime): the direct DFT, dense matrix products on the binary64 matrix cores:
+    # the first pass real data times complex twiddles (2 FMA = 4 flops per term) for h/2 + 1 outputs
+    # of each column, the second complex times complex (8 flops per term) for those h/2 + 1 columns
     N = 1009
     img_d = x[:N * N].view(N, N)
-    flops_pass = N * N * N * 8  # complex multiply-add = 4 FMA = 8 flops, N x N outputs of N terms
+    hh = N // 2 + 1
+    flops = 4 * N * hh * N + 8 * N * N * hh
     ms = timed(lambda: lz.power_spectrum_2d(ctx, img_d))
-    res["power_spectrum_1009x1009"] = dict(ms=ms, route="direct", TFLOPs=2 * flops_pass / ms / 1e9,
-                                           frac_of_fp64_matrix_peak=2 * flops_pass / ms * 1e3 / FP64_FMA_COUNTED_PEAK)
+    res["power_spectrum_1009x1009"] = dict(ms=ms, route="direct", TFLOPs=flops / ms / 1e9,
+                                           frac_of_fp64_matrix_peak=flops / ms * 1e3 / FP64_FMA_COUNTED_PEAK)
     ctx.close()
     return res
 

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -811,40 +812,61 @@ __device__ __forceinline__ double2 dft_value(double2 v) { return v; }
 // and out-of-range entries are zeroed when stored to LDS.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// What a pass writes for output value i (row-major in the pass's M x N output): the
-// complex value, |Z|^2, |Z|^2 with entry 0 (the zero frequency of the second pass)
-// set to 0, or Re Z / den (the normalised autocorrelation; NaN when den is).
+// What a pass writes for output (column c, index r) of its transforms, row-major in its
+// M x nout output: the complex value, |Z|^2, |Z|^2 with the zero frequency (c = r = 0 of the
+// second pass) set to 0, or Re Z / den (the normalised autocorrelation; NaN when den is).
+// A real matrix (h rows) has a Hermitian 2-D transform, Z[h - k1][w - k2] = conj Z[k1][k2]
+// (indices mod h and w), so a first pass over real columns keeps only indices r < nout =
+// h/2 + 1 of each column's transform, the second pass transforms those h/2 + 1 columns, and
+// its real results (|Z|^2, or Re Z of an even real matrix's transform) are written twice:
+// row c, and, as row h - c with k2 -> w - k2, each row the pass does not compute itself
+// (mirror = h; 0 writes no mirror rows).
 enum : int { EPI_COMPLEX = 0, EPI_POWER = 1, EPI_POWER_NODC = 2, EPI_ACF = 3 };
 struct PassOut {
     double2 *z;
     double *p;
     const double *den;
+    uint32_t nout;
+    uint32_t mirror;
 };
 
 template <int E>
-__device__ __forceinline__ void pass_store(const PassOut &o, size_t i, double re, double im) {
+__device__ __forceinline__ void pass_store(const PassOut &o, uint32_t c, uint32_t r, uint32_t N, uint32_t M,
+                                           double re, double im) {
+    if (r >= o.nout) return;
+    const size_t i = (size_t)c * o.nout + r;
     if constexpr (E == EPI_COMPLEX) {
         o.z[i] = make_double2(re, im);
-    } else if constexpr (E == EPI_ACF) {
-        const double d = o.den[0];
-        o.p[i] = d != d ? d : re / d;
     } else {
-        o.p[i] = (E == EPI_POWER_NODC && i == 0) ? 0.0 : re * re + im * im;
+        double v;
+        if constexpr (E == EPI_ACF) {
+            const double d = o.den[0];
+            v = d != d ? d : re / d;
+        } else {
+            v = (E == EPI_POWER_NODC && c == 0 && r == 0) ? 0.0 : re * re + im * im;
+        }
+        o.p[i] = v;
+        // the real outputs keep whole rows (nout = N)
+        if (o.mirror && c != 0 && o.mirror - c >= M) o.p[(size_t)(o.mirror - c) * N + (r ? N - r : 0)] = v;
     }
 }
 
-template <typename In, int E>
+template <typename In, int E, int TR>
 __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32_t N, uint32_t M, const double2 *tw,
                                                             double sign, PassOut dst) {
-    // 64 x 64 outputs per workgroup; each wave takes a 32 x 32 block as 2 x 2 tiles of 16 x 16
-    constexpr int TR = DFT_T;
-    constexpr int TB = 2;                            // column tiles per wave
+    // TR x 64 outputs per workgroup: with TR = 64 each wave takes a 32 x 32 block as 2 x 2 tiles of
+    // 16 x 16, with TR = 32 (grids that would not fill the chip) a 32 x 16 block as 2 x 1 tiles.
+    // A real input (bytes or doubles) has no imaginary part: two of the four products are skipped.
+    static_assert(TR == 64 || TR == 32, "tile height");
+    constexpr int WC = TR == 64 ? 2 : 4;             // waves across the tile's columns
+    constexpr int TB = 4 / WC;                       // column tiles per wave
+    constexpr bool REAL = !std::is_same_v<In, double2>;
     constexpr int TWQ = TR * DFT_K / DIAG_WG;        // twiddles each thread stages per k stage
     __shared__ double2 s_src[DFT_K][DFT_T];  // [k][c]
     __shared__ double2 s_tw[DFT_K][TR];      // [k][r]
     const uint32_t r0 = blockIdx.x * TR, c0 = blockIdx.y * DFT_T;
     const uint32_t lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    const uint32_t wr = (wave / 2) * 32, wc = (wave % 2) * 32;
+    const uint32_t wr = (wave / WC) * 32, wc = (wave % WC) * (16 * TB);
     const uint32_t li = lane % 16, lk = lane / 16;
     // staging: column cc of the input tile for k rows kq + 4q; twiddle row tr_s for k rows kt + (DFT_K/TWQ) q
     const uint32_t cc = threadIdx.x % DFT_T, kq = threadIdx.x / DFT_T;
@@ -895,8 +917,10 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
             for (int a = 0; a < 2; ++a)
                 for (int b = 0; b < TB; ++b) {
                     re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[a].x, x[b].x, re[a][b], 0, 0, 0);
-                    re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-w[a].y, x[b].y, re[a][b], 0, 0, 0);
-                    im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[a].x, x[b].y, im[a][b], 0, 0, 0);
+                    if constexpr (!REAL) {
+                        re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-w[a].y, x[b].y, re[a][b], 0, 0, 0);
+                        im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[a].x, x[b].y, im[a][b], 0, 0, 0);
+                    }
                     im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[a].y, x[b].x, im[a][b], 0, 0, 0);
                 }
         }
@@ -906,7 +930,7 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
         for (int b = 0; b < TB; ++b)
             for (int j = 0; j < 4; ++j) {
                 const uint32_t r = r0 + wr + 16 * a + 4 * j + lk, c = c0 + wc + 16 * b + li;
-                if (r < N && c < M) pass_store<E>(dst, (size_t)c * N + r, re[a][b][j], im[a][b][j]);
+                if (r < N && c < M) pass_store<E>(dst, c, r, N, M, re[a][b][j], im[a][b][j]);
             }
 }
 
@@ -1062,7 +1086,7 @@ __global__ __launch_bounds__(DIAG_WG) void fft_pass_kernel(const In *src, uint32
     }
     for (uint32_t e = threadIdx.x; e < total; e += DIAG_WG) {
         const double2 v = cur[e];
-        pass_store<E>(dst, (size_t)c0 * N + e, v.x, v.y);
+        pass_store<E>(dst, c0 + (e >> logN), e & (N - 1), N, M, v.x, v.y);
     }
 }
 
@@ -1200,11 +1224,10 @@ __global__ __launch_bounds__(DIAG_WG) void fft1k_pass_kernel(const In *src, uint
         const uint32_t p = 64 * i + lane;
         double2 a0 = L[p], a1 = L[FFT1K_S2 + p], a2 = L[2 * FFT1K_S2 + p], a3 = L[3 * FFT1K_S2 + p];
         dft4(a0, a1, a2, a3, sign);
-        const size_t o = (size_t)col * FFT1K + p;
-        pass_store<E>(dst, o, a0.x, a0.y);
-        pass_store<E>(dst, o + 256, a1.x, a1.y);
-        pass_store<E>(dst, o + 512, a2.x, a2.y);
-        pass_store<E>(dst, o + 768, a3.x, a3.y);
+        pass_store<E>(dst, col, p, FFT1K, M, a0.x, a0.y);
+        pass_store<E>(dst, col, p + 256, FFT1K, M, a1.x, a1.y);
+        pass_store<E>(dst, col, p + 512, FFT1K, M, a2.x, a2.y);
+        pass_store<E>(dst, col, p + 768, FFT1K, M, a3.x, a3.y);
     }
 }
 
@@ -1320,7 +1343,8 @@ __global__ __launch_bounds__(DIAG_WG) void fft_mixed_pass_kernel(const In *src, 
     }
     for (uint32_t e = threadIdx.x; e < total; e += DIAG_WG) {
         const double2 v = fbuf[e];
-        pass_store<E>(dst, (size_t)c0 * N + e, v.x, v.y);
+        const uint32_t cl = e / N;
+        pass_store<E>(dst, c0 + cl, e - cl * N, N, M, v.x, v.y);
     }
 }
 
@@ -1558,10 +1582,10 @@ bool fft_ok(const lz_ctx *c, uint32_t N) {
     return (N & (N - 1)) == 0 && N <= FFT_MAX && lds <= (size_t)c->dev.lds_per_wg_max;
 }
 
-// Output (M x N) = transpose of (DFT_N along the rows of src (N x M)), stored by epilogue E:
-// by FFT when N is a power of two up to FFT_MAX, by mixed-radix FFT when N <= FFT_MAX has no
-// prime factor above 5, otherwise directly on the matrix cores with 64 x 64 outputs per
-// workgroup (tw: the N-entry table, needed by the last two).
+// Output (M x out.nout) = transpose of (DFT_N along the rows of src (N x M)), its first out.nout
+// rows, stored by epilogue E: by FFT when N is a power of two up to FFT_MAX, by mixed-radix FFT
+// when N <= FFT_MAX has no prime factor above 5, otherwise directly on the matrix cores (tw: the
+// N-entry table, needed by the last two).
 template <typename In, int E>
 int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, const double2 *tw, double sign,
                     PassOut out, hipStream_t s) {
@@ -1570,7 +1594,9 @@ int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, cons
         if (lds > 65536)
             LZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&fft1k_pass_kernel<In, E>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        const uint32_t groups = (M + FFT1K_COLS - 1) / FFT1K_COLS;
+        // a multiple of 8 workgroups, so that neighbouring column groups share an XCD (the
+        // workgroups past the last column only help make the twiddle table and leave)
+        const uint32_t groups = ((M + FFT1K_COLS - 1) / FFT1K_COLS + 7) / 8 * 8;
         hipLaunchKernelGGL((fft1k_pass_kernel<In, E>), dim3(groups), dim3(DIAG_WG), lds, s, src, M, sign, out);
     } else if (fft_ok(c, N)) {
         uint32_t logN = 0;
@@ -1595,15 +1621,26 @@ int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, cons
         hipLaunchKernelGGL((fft_mixed_pass_kernel<In, E>), dim3(groups), dim3(DIAG_WG), lds, s, src, N, M, C,
                            mixed_plan(N), tw, sign, out);
     } else {
-        const dim3 grid((N + DFT_T - 1) / DFT_T, (M + DFT_T - 1) / DFT_T);
-        hipLaunchKernelGGL((dft_pass_kernel<In, E>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, out);
+        // 64 x 64 tiles, or 32 x 64 where those would leave compute units idle
+        const uint32_t gy = (M + DFT_T - 1) / DFT_T;
+        if ((uint64_t)((out.nout + DFT_T - 1) / DFT_T) * gy < (uint64_t)c->dev.cus) {
+            const dim3 grid((out.nout + 31) / 32, gy);
+            hipLaunchKernelGGL((dft_pass_kernel<In, E, 32>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, out);
+        } else {
+            const dim3 grid((out.nout + DFT_T - 1) / DFT_T, gy);
+            hipLaunchKernelGGL((dft_pass_kernel<In, E, 64>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, out);
+        }
     }
     LZ_HIP(hipGetLastError());
     return LZ_OK;
 }
 
-PassOut complex_out(double2 *z) { return PassOut{z, nullptr, nullptr}; }
-PassOut real_out(double *p, const double *den = nullptr) { return PassOut{nullptr, p, den}; }
+// complex results, indices r < nout of each transform; real results, whole rows of n, with the
+// mirror rows of an h-row matrix (0: none)
+PassOut complex_out(double2 *z, uint32_t nout) { return PassOut{z, nullptr, nullptr, nout, 0}; }
+PassOut real_out(double *p, uint32_t n, uint32_t h, const double *den = nullptr) {
+    return PassOut{nullptr, p, den, n, h};
+}
 
 }  // namespace
 
@@ -1643,9 +1680,13 @@ extern "C" int lz_power_spectrum_2d(lz_ctx *c, const uint8_t *d_img, uint32_t h,
     if (int rc = diag_begin(c, s, dft2_bytes(h, w, 0), &ws)) return rc;
     const Dft2 d = dft2_layout(ws, h, w, 0);
     if (int rc = launch_twiddles(c, d, h, w, s)) return rc;
-    // a: w x h; then |Z|^2 of the second pass (h x w) straight into the output
-    if (int rc = launch_dft_pass<uint8_t, EPI_COMPLEX>(c, d_img, h, w, d.tw_h, -1.0, complex_out(d.a), s)) return rc;
-    if (int rc = launch_dft_pass<double2, EPI_POWER>(c, d.a, w, h, d.tw_w, -1.0, real_out(d_power), s)) return rc;
+    // a: w x (h/2 + 1), the columns' transforms up to index h/2 (the rest is their mirror image);
+    // then |Z|^2 of the second pass, rows 0..h/2 and their mirror rows, straight into the output
+    const uint32_t hh = h / 2 + 1;
+    if (int rc = launch_dft_pass<uint8_t, EPI_COMPLEX>(c, d_img, h, w, d.tw_h, -1.0, complex_out(d.a, hh), s))
+        return rc;
+    if (int rc = launch_dft_pass<double2, EPI_POWER>(c, d.a, w, hh, d.tw_w, -1.0, real_out(d_power, w, h), s))
+        return rc;
     return diag_end(c, s);
 }
 
@@ -1666,11 +1707,17 @@ extern "C" int lz_autocorrelation_2d(lz_ctx *c, const uint8_t *d_img, uint32_t h
                        reinterpret_cast<const unsigned long long *>(hist), (uint64_t)n, den);
     LZ_HIP(hipGetLastError());
     if (int rc = launch_twiddles(c, d, h, w, s)) return rc;
-    // a: w x h; b: |Z|^2 with the zero frequency removed (h x w); a: w x h; then Re G / den
+    // a: w x (h/2 + 1); b: |Z|^2 with the zero frequency removed (h x w, real and even);
+    // a: w x (h/2 + 1) again; then Re G / den, rows 0..h/2 and their mirror rows (G is even too)
+    const uint32_t hh = h / 2 + 1;
     double *pm = reinterpret_cast<double *>(d.b);
-    if (int rc = launch_dft_pass<uint8_t, EPI_COMPLEX>(c, d_img, h, w, d.tw_h, -1.0, complex_out(d.a), s)) return rc;
-    if (int rc = launch_dft_pass<double2, EPI_POWER_NODC>(c, d.a, w, h, d.tw_w, -1.0, real_out(pm), s)) return rc;
-    if (int rc = launch_dft_pass<double, EPI_COMPLEX>(c, pm, h, w, d.tw_h, 1.0, complex_out(d.a), s)) return rc;
-    if (int rc = launch_dft_pass<double2, EPI_ACF>(c, d.a, w, h, d.tw_w, 1.0, real_out(d_acf, den), s)) return rc;
+    if (int rc = launch_dft_pass<uint8_t, EPI_COMPLEX>(c, d_img, h, w, d.tw_h, -1.0, complex_out(d.a, hh), s))
+        return rc;
+    if (int rc = launch_dft_pass<double2, EPI_POWER_NODC>(c, d.a, w, hh, d.tw_w, -1.0, real_out(pm, w, h), s))
+        return rc;
+    if (int rc = launch_dft_pass<double, EPI_COMPLEX>(c, pm, h, w, d.tw_h, 1.0, complex_out(d.a, hh), s))
+        return rc;
+    if (int rc = launch_dft_pass<double2, EPI_ACF>(c, d.a, w, hh, d.tw_w, 1.0, real_out(d_acf, w, h, den), s))
+        return rc;
     return diag_end(c, s);
 }

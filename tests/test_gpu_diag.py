@@ -251,14 +251,16 @@ def _power_tol(x):
 @pytest.mark.parametrize("h,w", [(1, 1), (1, 37), (29, 1), (2, 2), (8, 8), (64, 64), (67, 131), (128, 200),
                                  (512, 512), (3, 4096), (4096, 3), (2048, 2048), (2, 8192), (1000, 24),
                                  (768, 960), (45, 81), (7, 250), (4050, 2), (1024, 1024), (1024, 7), (6, 1024),
-                                 (1024, 1), (1024, 4093)])
+                                 (1024, 1), (1024, 4093), (1009, 1009)])
 def test_power_spectrum_2d(lz, ctx, h, w):
     """All routes of a pass: the 1024-point pass of one wave per column (1024; with 1, 6, 7, 1024 and
     4093 columns, so some workgroups have idle waves), the power-of-two FFT up to 4096 (2, 8, 64, 128,
     512, 2048, 4096, and the 1 x 1 identity), the mixed-radix FFT for lengths with no prime factor above
     5 (3, 24, 45, 81, 200, 250, 768, 960, 1000, 4050: radix 5, 3, 4, 2 stages, 4050 needing 130 KB of
-    LDS), and the direct DFT on the matrix cores for the others (7, 29, 37, 67, 131, 4093) and for 8192,
-    above the FFTs' limit; several cases mix them."""
+    LDS), and the direct DFT on the matrix cores for the others (7, 29, 37, 67, 131, 1009, 4093) and for
+    8192, above the FFTs' limit; several cases mix them.  The first pass keeps indices up to h/2 of its
+    column transforms and the second writes the other rows as mirror images, so odd and even h, and
+    h = 1 and 2 (no mirror rows), are all here."""
     rng = np.random.default_rng(100 + h * 7 + w)
     x = rng.integers(0, 256, (h, w), dtype=np.uint8)
     say("power spectrum", h, w)
@@ -337,6 +339,24 @@ def test_autocorrelation_2d_sampled_large(lz, ctx):
         want = dg.autocorrelation_2d_at(img, int(dx), int(dy))
         assert abs(got[dx, dy] - want) <= tol, (dx, dy, got[dx, dy], want, tol)
     assert abs(got[0, 0] - 1.0) <= tol
+
+
+def test_autocorrelation_2d_sampled_direct(lz, ctx):
+    """1009 x 1013 (both prime: all four passes are direct DFTs on the matrix cores), at sampled lags,
+    the mirror rows included (dx above h/2)."""
+    rng = np.random.default_rng(122)
+    H, W = 1009, 1013
+    img = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    img[::4, ::7] = 255
+    got = host(lz.autocorrelation_2d(ctx, to_dev(img.ravel()).view(H, W)))
+    tol = _acf2_tol(img)
+    lags = [(0, 0), (1, 0), (0, 1), (4, 7), (504, 506), (505, 3), (H - 1, W - 1), (H - 4, 7)]
+    lags += [tuple(v) for v in rng.integers(0, [H, W], (6, 2))]
+    for dx, dy in lags:
+        want = dg.autocorrelation_2d_at(img, int(dx), int(dy))
+        assert abs(got[dx, dy] - want) <= tol, (dx, dy, got[dx, dy], want, tol)
+    # an even matrix: A[-dx][-dy] = A[dx][dy], bit for bit for the mirrored rows
+    assert np.array_equal(got[1:], got[:0:-1, np.r_[0, W - 1:0:-1]])
 
 
 def test_autocorrelation_2d_sampled_fft_sizes(lz, ctx):
