@@ -21,8 +21,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "
 # loop headers on 64-byte boundaries: with one wave per SIMD nothing hides a fetch stall, and the
 # unaligned Euler loop of the served kernel ran 25% slower than the same loop aligned
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-falign-loops=64"]
-SOURCES = ["kernels.hip", "diag.hip", "copy.hip", "noalloc.hip", "runtime.cpp", "server.cpp", "stream.cpp",
-           "keysetup.cpp", "units.cpp"]
+SOURCES = ["kernels.hip", "diag_hist.hip", "diag_lags.hip", "diag_fft.hip", "copy.hip", "noalloc.hip", "runtime.cpp",
+           "server.cpp", "stream.cpp", "keysetup.cpp", "units.cpp"]
 
 
 def _run(cmd):
