@@ -19,7 +19,7 @@ namespace {
 // integers, so every twiddle is one table entry.
 
 constexpr int DFT_T = 64;  // output tile edge (r and c)
-constexpr int DFT_K = 16;  // k values per LDS stage
+constexpr int DFT_KS32 = 32, DFT_KS64 = 16;  // terms per LDS stage for 32- and 64-row tiles
 
 // tw[j] = (cos 2 pi j / N, sin 2 pi j / N)
 __global__ void twiddle_kernel(double2 *tw, uint32_t N) {
@@ -38,7 +38,7 @@ __device__ __forceinline__ double2 dft_value(double2 v) { return v; }
 // layout: lane i holds A[i % 16][i / 16] and B[i / 16][i % 16] of the 16x4 and 4x16 operands,
 // and D[4 j + i / 16][i % 16] in its j-th accumulator.  A complex product takes four real
 // products: re += wr xr - wi xi, im += wr xi + wi xr.  The inputs and twiddles of the next
-// 16-deep k stage are loaded into registers while the current stage computes; the loads are
+// k stage (16 or 32 terms) are loaded into registers while the current stage computes; the loads are
 // unconditional, from valid addresses, so nothing waits for them before the stage's products,
 // and out-of-range entries are zeroed when stored to LDS.
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -82,37 +82,40 @@ __device__ __forceinline__ void pass_store(const PassOut &o, uint32_t c, uint32_
     }
 }
 
-template <typename In, int E, int TR>
+template <typename In, int E, int TR, int KS>
 __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32_t N, uint32_t M, const double2 *tw,
                                                             double sign, PassOut dst) {
     // TR x 64 outputs per workgroup: with TR = 64 each wave takes a 32 x 32 block as 2 x 2 tiles of
     // 16 x 16, with TR = 32 (grids that would not fill the chip) a 32 x 16 block as 2 x 1 tiles.
     // A real input (bytes or doubles) has no imaginary part: two of the four products are skipped.
+    // KS terms per LDS stage: the loads of the next stage are in flight during this one's products.
     static_assert(TR == 64 || TR == 32, "tile height");
+    static_assert(KS % 4 == 0 && (TR * KS) % DIAG_WG == 0, "whole rows of the stage per thread");
+    constexpr int QX = KS / 4;                       // input rows each thread stages per k stage
     constexpr int WC = TR == 64 ? 2 : 4;             // waves across the tile's columns
     constexpr int TB = 4 / WC;                       // column tiles per wave
     constexpr bool REAL = !std::is_same_v<In, double2>;
-    constexpr int TWQ = TR * DFT_K / DIAG_WG;        // twiddles each thread stages per k stage
-    __shared__ double2 s_src[DFT_K][DFT_T];  // [k][c]
-    __shared__ double2 s_tw[DFT_K][TR];      // [k][r]
+    constexpr int TWQ = TR * KS / DIAG_WG;           // twiddles each thread stages per k stage
+    __shared__ double2 s_src[KS][DFT_T];  // [k][c]
+    __shared__ double2 s_tw[KS][TR];      // [k][r]
     const uint32_t r0 = blockIdx.x * TR, c0 = blockIdx.y * DFT_T;
     const uint32_t lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const uint32_t wr = (wave / WC) * 32, wc = (wave % WC) * (16 * TB);
     const uint32_t li = lane % 16, lk = lane / 16;
-    // staging: column cc of the input tile for k rows kq + 4q; twiddle row tr_s for k rows kt + (DFT_K/TWQ) q
+    // staging: column cc of the input tile for k rows kq + 4q; twiddle row tr_s for k rows kt + (KS/TWQ) q
     const uint32_t cc = threadIdx.x % DFT_T, kq = threadIdx.x / DFT_T;
     const uint32_t tr_s = threadIdx.x % TR, kt = threadIdx.x / TR;
     const uint32_t rs = r0 + tr_s;
     const uint32_t rmod = rs < N ? rs : 0;
     const uint32_t cs = c0 + cc < M ? c0 + cc : M - 1;
     uint32_t off[TWQ];
-    for (int q = 0; q < TWQ; ++q) off[q] = (uint32_t)(((uint64_t)rmod * (kt + (DFT_K / TWQ) * q)) % N);
-    const uint32_t step = (uint32_t)(((uint64_t)rmod * DFT_K) % N);
+    for (int q = 0; q < TWQ; ++q) off[q] = (uint32_t)(((uint64_t)rmod * (kt + (KS / TWQ) * q)) % N);
+    const uint32_t step = (uint32_t)(((uint64_t)rmod * KS) % N);
     uint32_t base = 0;
-    In nx[4];
+    In nx[QX];
     double2 nw[TWQ];
     auto fetch = [&](uint32_t k0) {
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < QX; ++q) {
             const uint32_t k = k0 + kq + 4 * q;
             nx[q] = src[(size_t)(k < N ? k : N - 1) * M + cs];
         }
@@ -128,19 +131,19 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < TB; ++b) re[a][b] = im[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
     fetch(0);
-    for (uint32_t k0 = 0; k0 < N; k0 += DFT_K) {
-        for (int q = 0; q < 4; ++q) {
+    for (uint32_t k0 = 0; k0 < N; k0 += KS) {
+        for (int q = 0; q < QX; ++q) {
             const uint32_t k = k0 + kq + 4 * q;
             s_src[kq + 4 * q][cc] = (k < N && c0 + cc < M) ? dft_value(nx[q]) : make_double2(0.0, 0.0);
         }
         for (int q = 0; q < TWQ; ++q) {
-            const uint32_t kk = kt + (DFT_K / TWQ) * q, k = k0 + kk;
+            const uint32_t kk = kt + (KS / TWQ) * q, k = k0 + kk;
             s_tw[kk][tr_s] = (k < N && rs < N) ? make_double2(nw[q].x, sign * nw[q].y) : make_double2(0.0, 0.0);
         }
         __syncthreads();
-        if (k0 + DFT_K < N) fetch(k0 + DFT_K);
+        if (k0 + KS < N) fetch(k0 + KS);
 #pragma unroll
-        for (int k4 = 0; k4 < DFT_K / 4; ++k4) {
+        for (int k4 = 0; k4 < KS / 4; ++k4) {
             const int k = 4 * k4 + (int)lk;
             double2 w[2], x[TB];
             for (int t = 0; t < 2; ++t) w[t] = s_tw[k][wr + 16 * t + li];
@@ -717,14 +720,17 @@ int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, cons
         hipLaunchKernelGGL((fft_mixed_pass_kernel<In, E>), dim3(groups), dim3(DIAG_WG), lds, s, src, N, M, C,
                            mixed_plan(N), tw, sign, out);
     } else {
-        // 64 x 64 tiles, or 32 x 64 where those would leave compute units idle
+        // 64 x 64 tiles, or 32 x 64 where those would leave compute units idle; DFT_KS32 and
+        // DFT_KS64 terms per LDS stage (the smaller tiles do half the products per term)
         const uint32_t gy = (M + DFT_T - 1) / DFT_T;
         if ((uint64_t)((out.nout + DFT_T - 1) / DFT_T) * gy < (uint64_t)c->dev.cus) {
             const dim3 grid((out.nout + 31) / 32, gy);
-            hipLaunchKernelGGL((dft_pass_kernel<In, E, 32>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, out);
+            hipLaunchKernelGGL((dft_pass_kernel<In, E, 32, DFT_KS32>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw,
+                               sign, out);
         } else {
             const dim3 grid((out.nout + DFT_T - 1) / DFT_T, gy);
-            hipLaunchKernelGGL((dft_pass_kernel<In, E, 64>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw, sign, out);
+            hipLaunchKernelGGL((dft_pass_kernel<In, E, 64, DFT_KS64>), grid, dim3(DIAG_WG), 0, s, src, N, M, tw,
+                               sign, out);
         }
     }
     LZ_HIP(hipGetLastError());
