@@ -5,7 +5,10 @@
 // checkpoint (r, alpha, mu, Omega) kept in device memory, so a request's bytes
 // do not depend on what else is admitted or when its chains run.  Requests
 // that arrive while a tick runs are admitted at the next tick boundary, as
-// chain slots and the device-memory budget allow (FIFO, no overtaking).
+// chain slots and the device-memory budget allow (FIFO, no overtaking): the
+// host prepares and queues the next tick shortly before the running one is
+// expected to end (from the measured duration of earlier ticks), so that
+// requests arriving during a tick join the very next one.
 //
 // Every chain of a tick advances at the pace of the most loaded SIMD.  Under
 // the adaptive policy a tick holds at most k waves per SIMD, with k chosen
@@ -145,6 +148,13 @@ void add_pieces(CopyPiece *arr, uint32_t &n, const void *src, void *dst, uint64_
     }
 }
 
+// Late admission: the next tick is queued a margin before the running one is expected to end,
+// time for the host to wake, admit, copy inputs and install records on the staging stream.  The
+// margin adapts: when a tick queued this way starts more than LATE_GAP_NS after the one before
+// it, the margin grows by LATE_STEP_UP_NS; otherwise it shrinks by LATE_STEP_DOWN_NS, within
+// [LATE_MARGIN_MIN_NS, LATE_MARGIN_MAX_NS].
+constexpr double LATE_MARGIN_MIN_NS = 150e3, LATE_MARGIN_MAX_NS = 1000e3, LATE_MARGIN_START_NS = 500e3;
+constexpr double LATE_STEP_UP_NS = 100e3, LATE_STEP_DOWN_NS = 5e3, LATE_GAP_NS = 20e3;
 constexpr uint32_t PIECES_MAX = 4096;  // copy pieces staged per tick (inputs) and per batch (outputs)
 constexpr uint64_t DEV_COPY_MAX = (PIECES_MAX / 2) * COPY_PIECE_BYTES;  // larger copies use hipMemcpyAsync
 
@@ -168,7 +178,9 @@ struct TickSlot {
     hipEvent_t ev_start = nullptr, ev_end = nullptr;
     bool in_flight = false;
     uint64_t bytes = 0;
-    uint64_t seq = 0;  // tick sequence number (1, 2, ...)
+    uint64_t seq = 0;     // tick sequence number (1, 2, ...)
+    uint32_t waves = 0;   // waves per SIMD of the tick's chains, at most
+    bool late = false;    // queued by a late step, while the tick before it ran
 };
 
 struct lz_server {
@@ -200,6 +212,11 @@ struct lz_server {
     std::deque<Request *> waiting;  // arrived, not admitted (FIFO); their chains: waiting_chains
     uint64_t hbm_fixed = 0;
     uint64_t tick_seq = 0, done_seq = 0;  // last tick queued, last tick completed (ticks complete in order)
+    // late admission (server thread only): a tick's duration per wave per SIMD (a running mean of
+    // the measured ticks), when the last completed tick was seen to end, and when the next step
+    // may start
+    double tick_ns_per_wave = 0, late_margin_ns = LATE_MARGIN_START_NS;
+    uint64_t tick_end_ns = 0, next_step_ns = 0;
     // shared with submitters / pollers
     std::mutex mu;
     std::condition_variable cv_submit, cv_done;
@@ -289,8 +306,13 @@ void compact_active(lz_server *s);
 int complete_tick(lz_server *s, TickSlot &t) {
     hipStream_t cs = s->copy_stream;
     LZ_HIP(hipEventSynchronize(t.ev_end));
+    s->tick_end_ns = lz_now_ns();
     float ms = 0;
     const bool timed = hipEventElapsedTime(&ms, t.ev_start, t.ev_end) == hipSuccess;
+    if (timed && t.waves) {
+        const double per = (double)ms * 1e6 / t.waves;
+        s->tick_ns_per_wave = s->tick_ns_per_wave > 0 ? 0.75 * s->tick_ns_per_wave + 0.25 * per : per;
+    }
     {
         std::lock_guard<std::mutex> g(s->mu);  // stats are read by lz_server_stats_get on other threads
         if (timed) s->stats.busy_ms += ms;
@@ -425,6 +447,16 @@ int server_step(lz_server *s) {
     TickSlot &t = s->ts[s->cur];
     if (t.in_flight)
         if (int rc = complete_tick(s, t)) return rc;
+    // before this slot's events are recorded again: did the running tick, queued late, start
+    // right after this slot's tick ended?  (both events have completed by now)
+    const TickSlot &run = s->ts[s->cur ^ 1];
+    if (run.in_flight && run.late && t.seq + 1 == run.seq && hipEventQuery(run.ev_start) == hipSuccess) {
+        float gap_ms = 0;
+        if (hipEventElapsedTime(&gap_ms, t.ev_end, run.ev_start) == hipSuccess)
+            s->late_margin_ns = gap_ms * 1e6 > LATE_GAP_NS
+                                    ? std::min(s->late_margin_ns + LATE_STEP_UP_NS, LATE_MARGIN_MAX_NS)
+                                    : std::max(s->late_margin_ns - LATE_STEP_DOWN_NS, LATE_MARGIN_MIN_NS);
+    }
     apply_cancels(s);
     std::vector<Request *> admitted;
     admit(s, admitted);
@@ -527,13 +559,23 @@ int server_step(lz_server *s) {
         LZ_HIP(hipEventRecord(t.ev_end, st));
         t.bytes = tick_bytes;
         t.seq = seq;
+        t.waves = (uint32_t)((n_list + s->simd_chains - 1) / s->simd_chains);
+        t.late = s->ts[s->cur ^ 1].in_flight;
         s->tick_seq = seq;
         t.in_flight = true;
     }
     s->cur ^= 1;
     TickSlot &prev = s->ts[s->cur];
-    if (prev.in_flight)
+    s->next_step_ns = 0;
+    if (prev.in_flight) {
         if (int rc = complete_tick(s, prev)) return rc;
+        // the tick queued above started when the previous one ended: the next step waits until
+        // shortly before it is expected to end, so that the tick after it takes the requests
+        // that arrive meanwhile (and not one tick later)
+        const double est = s->tick_ns_per_wave * t.waves;
+        if (t.in_flight && est > s->late_margin_ns)
+            s->next_step_ns = s->tick_end_ns + (uint64_t)(est - s->late_margin_ns);
+    }
     release_cancelled(s);
     if (!n_list && !prev.in_flight && !s->ts[s->cur ^ 1].in_flight && !s->active.empty())
         return fail(LZ_E_HIP, "server: active requests without pending work");
@@ -547,6 +589,8 @@ void server_loop(lz_server *s) {
     for (;;) {
         {
             std::unique_lock<std::mutex> g(s->mu);
+            for (uint64_t now = lz_now_ns(); now < s->next_step_ns && !s->stop; now = lz_now_ns())
+                s->cv_submit.wait_for(g, std::chrono::nanoseconds(s->next_step_ns - now));
             for (;;) {
                 const uint64_t now = lz_now_ns();
                 while (!s->pending.empty() && s->pending.front()->arrival_ns <= now) {
