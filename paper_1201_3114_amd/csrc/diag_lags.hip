@@ -466,15 +466,19 @@ __global__ __launch_bounds__(LW_WG) void lagsum_wide_kernel(const uint8_t *data,
 // The correction for L <= 256 (one window, one workgroup of LS_FIX_WG threads): thread k takes
 // lag k, sums its LS_COPIES merge copies (all loads issued before the first is used) and clears
 // them; the first and last L bytes are loaded at the same time, and P_k + Q_k comes from one scan
-// of x_j + x_{n-1-j} (a wave scan by shuffles, then the wave totals through LDS).
+// of x_j + x_{n-1-j} (a wave scan by shuffles, then the wave totals through LDS).  With r
+// non-null (n > 0) it also writes the normalised coefficients r_k, as autocorr_norm_kernel does
+// and in the same binary64 operations: A_k + B_k = 2T - (P_k + Q_k) is an exact integer below
+// 2^53, as is each of A_k and B_k there.
 constexpr int LS_FIX_WG = 512;
 static_assert(LS_FIX_WG > 32 * (LS_MAX_NT - 1) && LS_FIX_WG >= (int)LS_COPIES, "a thread per lag and per copy");
 __global__ __launch_bounds__(LS_FIX_WG) void lagsum_fix_small_kernel(const uint8_t *data, uint64_t n, uint32_t L,
                                                                      unsigned long long *merge,
                                                                      unsigned long long *sums,
-                                                                     unsigned long long *total) {
+                                                                     unsigned long long *total, double *r) {
     __shared__ uint32_t wsum[LS_FIX_WG / 64];
     __shared__ unsigned long long tsum[LS_FIX_WG / 64];
+    __shared__ unsigned long long s0;
     const uint32_t k = threadIdx.x, lane = k % 64, wave = k / 64;
     const size_t cs = (size_t)L + 2;  // copy stride: lags 0..L, then the byte total
     unsigned long long part[LS_COPIES];
@@ -496,9 +500,10 @@ __global__ __launch_bounds__(LS_FIX_WG) void lagsum_fix_small_kernel(const uint8
     uint32_t before = 0;
 #pragma unroll
     for (uint32_t w = 0; w < LS_FIX_WG / 64; ++w) before += w < wave ? wsum[w] : 0u;
+    // P_k + Q_k: the bytes j < k of both ends
+    const unsigned long long pq = before + inc - x;
+    unsigned long long sk = 0;
     if (k <= L) {
-        // P_k + Q_k: the bytes j < k of both ends
-        const unsigned long long pq = before + inc - x;
         unsigned long long raw = 0;
 #pragma unroll
         for (uint32_t c = 0; c < LS_COPIES; ++c) {
@@ -506,14 +511,28 @@ __global__ __launch_bounds__(LS_FIX_WG) void lagsum_fix_small_kernel(const uint8
             merge[c * cs + k] = 0;
         }
         const unsigned long long m = k < n ? n - k : 0;
-        sums[k] = raw - 128ull * pq - 16384ull * m;
+        sk = raw - 128ull * pq - 16384ull * m;
+        sums[k] = sk;
+        if (k == 0) s0 = sk;
     }
     if (k < LS_COPIES) merge[k * cs + L + 1] = 0;
-    if (k == 0 && total) {
-        unsigned long long tt = 0;
-        for (uint32_t w = 0; w < LS_FIX_WG / 64; ++w) tt += tsum[w];
-        *total = tt;
-    }
+    unsigned long long T = 0;
+    for (uint32_t w = 0; w < LS_FIX_WG / 64; ++w) T += tsum[w];
+    if (k == 0 && total) *total = T;
+    if (!r) return;
+    __syncthreads();  // S_0
+    if (k > L) return;
+    const unsigned long long S0 = s0;
+    const double mean = (double)T / (double)n;
+    const double den = (double)S0 - (double)n * mean * mean;
+    // no coefficient when every byte is equal: n S_0 = T^2 exactly then, and only then
+    const bool constant = (unsigned __int128)n * S0 == (unsigned __int128)T * T;
+    double v;
+    if (constant) v = __builtin_nan("");
+    else if (k == 0) v = 1.0;
+    else if (k >= n) v = 0.0;
+    else v = ((double)sk - mean * (double)(2 * T - pq) + (double)(n - k) * mean * mean) / den;
+    r[k] = v;
 }
 
 // S_k = raw_k - 128 (P_k + Q_k) - 16384 max(n - k, 0) for k <= L, raw_k the sum of the merge
@@ -655,8 +674,12 @@ __global__ __launch_bounds__(DIAG_WG) void autocorr_norm_kernel(const uint8_t *d
 // The lag sums into sums[0..max_lag]; with total non-null, also the byte total into *total.
 // ordered: the caller has already ordered this stream after the context's other diagnostics
 // (diag_begin) and records the event afterwards itself.
+// r: when the lags fit one launch (and n > 0), the normalised coefficients are written too and
+// *normalised is set.
 int lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, unsigned long long *sums,
-             unsigned long long *total, hipStream_t s, bool ordered = false) {
+             unsigned long long *total, hipStream_t s, bool ordered = false, double *r = nullptr,
+             bool *normalised = nullptr) {
+    if (normalised) *normalised = false;
     if (n > 0) {
         // the workgroups' sums meet in the context's merge copies, which the correction kernel adds
         // up, writes to d_sums and clears: calls on different streams are ordered
@@ -684,8 +707,9 @@ int lag_sums(lz_ctx *c, const uint8_t *d_data, size_t n, uint32_t max_lag, unsig
                 return rc;
             hipLaunchKernelGGL(kern, dim3(blocks), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag, c->diag_merge);
             hipLaunchKernelGGL(lagsum_fix_small_kernel, dim3(1), dim3(LS_FIX_WG), 0, s, d_data, (uint64_t)n, max_lag,
-                               c->diag_merge, sums, total);
+                               c->diag_merge, sums, total, r);
             LZ_HIP(hipGetLastError());
+            if (normalised) *normalised = r != nullptr;
             return ordered ? LZ_OK : diag_end(c, s);
         }
         // windows of at most LW_WINDOW lags, as even as 32-lag steps allow, one launch each
@@ -734,9 +758,11 @@ extern "C" int lz_autocorrelation(lz_ctx *c, const uint8_t *d_data, size_t n, ui
     if (int rc = diag_begin(c, s, 8 + ((size_t)max_lag + 1) * 8, &ws)) return rc;
     unsigned long long *total = reinterpret_cast<unsigned long long *>(ws);
     unsigned long long *sums = total + 1;
-    if (int rc = lag_sums(c, d_data, n, max_lag, sums, total, s, true)) return rc;
-    hipLaunchKernelGGL(autocorr_norm_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag, sums,
-                       total, d_r);
+    bool normalised = false;
+    if (int rc = lag_sums(c, d_data, n, max_lag, sums, total, s, true, d_r, &normalised)) return rc;
+    if (!normalised)
+        hipLaunchKernelGGL(autocorr_norm_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag, sums,
+                           total, d_r);
     LZ_HIP(hipGetLastError());
     return diag_end(c, s);
 }

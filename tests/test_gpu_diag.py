@@ -204,8 +204,10 @@ def test_lag_sums_unaligned_and_many_tasks(lz, ctx, L):
 
 @pytest.mark.parametrize("n,L,kind", [(0, 4, "rand"), (1, 3, "rand"), (7, 12, "rand"), (40, 6, "alt"),
                                       (5000, 300, "rand"), (100_000, 700, "text"), (1000, 5, "const"),
-                                      (300_001, 2000, "rand"), (20_000, 16384, "rand")])
+                                      (300_001, 2000, "rand"), (20_000, 16384, "rand"), (2_000_003, 256, "text"),
+                                      (200, 256, "alt")])
 def test_autocorrelation_1d(lz, ctx, n, L, kind):
+    """Up to lag 256 the correction kernel also normalises; past it a separate kernel does."""
     rng = np.random.default_rng(91 + n)
     if kind == "alt":
         x = np.array([10, 30] * (n // 2), np.uint8)
@@ -226,7 +228,24 @@ def test_autocorrelation_1d(lz, ctx, n, L, kind):
     tol = 64 * EPS * S0 / (S0 - T * T / n)
     assert np.max(np.abs(got - want)) <= tol, (np.max(np.abs(got - want)), tol)
     if kind == "alt":
-        assert np.allclose(got, [(-1) ** k * (n - k) / n for k in range(L + 1)], rtol=0, atol=tol)
+        assert np.allclose(got, [(-1) ** k * max(n - k, 0) / n for k in range(L + 1)], rtol=0, atol=tol)
+
+
+@pytest.mark.parametrize("n,kind", [(1000, "rand"), (1_000_003, "text"), (257, "rand"), (100, "rand")])
+def test_autocorrelation_fused_normalisation_is_bit_identical(lz, ctx, n, kind):
+    """The coefficients up to lag 256 come from the correction kernel of the one-launch lag sums (the
+    fused normalisation); asking for lag 257 runs the windowed lag sums and the separate normalisation
+    kernel.  Both take the same binary64 operations on the same exact sums, so r_0..r_256 agree bit for
+    bit (n = 100: the lags at or past n are exactly 0 on both)."""
+    rng = np.random.default_rng(130 + n)
+    if kind == "text":
+        x = rng.choice(np.frombuffer(b"etaoin shrdlu       ", np.uint8), n)
+    else:
+        x = rng.integers(0, 256, n, dtype=np.uint8)
+    d = _dev(x)
+    fused = host(lz.autocorrelation(ctx, d, 256))
+    windowed = host(lz.autocorrelation(ctx, d, 257))
+    assert fused.view(np.uint64).tolist() == windowed[:257].view(np.uint64).tolist()
 
 
 def _dz_max(x):
