@@ -308,7 +308,7 @@ def bench_streaming(lz, torch):
         ms = e[0].elapsed_time(e[1])
         res[f"chunks_of_{chunk}"] = dict(updates=(n + chunk - 1) // chunk, ms=ms, encrypt_GBps=n / ms / 1e6,
                                          equals_one_shot=bool(torch.equal(out, one)))
-    # deferred updates: small chunks staged and run together (64 MiB of staging), flushed at the end
+    # deferred updates: small chunks staged and run together (runs of one wave per SIMD), flushed at the end
     for chunk in ((1 << 20) + 1, (64 << 10) + 1):
         out.zero_()
         st = lz.Stream(ctx, False, pw)

@@ -317,13 +317,17 @@ int lz_stream_update(lz_stream *st, const uint8_t *d_in, size_t n, uint8_t *d_ou
 /* Deferred update: the next n bytes as lz_stream_update computes them, but
  * the chunk is copied (on stream, device to device) into the stream's staging
  * buffer and runs later, together with the chunks queued after it, as one
- * update over their concatenation: at lz_stream_flush, when LZ_STREAM_DEFER_BYTES
- * are queued or LZ_STREAM_DEFER_CHUNKS chunks, before an immediate update, and at
- * lz_stream_finish.  Small chunks then share one launch that fills the device.
- * d_in may be reused as soon as stream reaches the call; d_out is written only
- * by that later launch, on the stream it is made on, and must stay valid until
- * then.  A chunk of LZ_STREAM_DEFER_BYTES or more runs at once, after any queued
- * chunks.  The first deferred update allocates the staging buffer
+ * update over their concatenation: at lz_stream_flush, when the queued bytes'
+ * blocks reach one chain per lane of a wave on every SIMD of the device (CUs x 4
+ * x 64 blocks, 16 MiB on a 256-CU device with 256-byte blocks, where an update
+ * already runs at the full rate; at most LZ_STREAM_DEFER_BYTES; a chunk that
+ * would pass that point is split between two runs), when LZ_STREAM_DEFER_CHUNKS
+ * chunks are queued, before an immediate update, and at lz_stream_finish.  Small
+ * chunks then share one launch that fills the device, and the host queues the
+ * next ones while it runs.  d_in may be reused as soon
+ * as stream reaches the call; d_out is written only by that later launch, on
+ * the stream it is made on, and must stay valid until then.  A chunk of that
+ * run size or more runs at once, after any queued chunks.  The first deferred update allocates the staging buffer
  * (2 x LZ_STREAM_DEFER_BYTES of device memory, freed by lz_stream_close;
  * LZ_E_NOMEM or LZ_E_HIP if that fails, with nothing queued).  Ordered with the
  * stream's other calls, also across streams.  Errors as lz_stream_update. */

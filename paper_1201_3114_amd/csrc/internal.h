@@ -152,11 +152,24 @@ struct CopyPiece {
     uint64_t len;
 };
 constexpr uint64_t COPY_PIECE_BYTES = 1ull << 20;  // requests are cut into pieces of at most this size
+// Appends the pieces of one copy of len bytes (at most COPY_PIECE_BYTES each) to arr[n...].
+inline void add_copy_pieces(CopyPiece *arr, uint32_t &n, const void *src, void *dst, uint64_t len) {
+    for (uint64_t o = 0; o < len; o += COPY_PIECE_BYTES) {
+        CopyPiece &p = arr[n++];
+        p.src = static_cast<const uint8_t *>(src) + o;
+        p.dst = static_cast<uint8_t *>(dst) + o;
+        p.len = len - o < COPY_PIECE_BYTES ? len - o : COPY_PIECE_BYTES;
+    }
+}
 // diagnostics merge buffer: workgroup b of the histogram and of the lag sums adds its partial
 // results into copy b mod DIAG_MERGE; the one-workgroup kernel that follows sums and clears them
 constexpr int DIAG_MERGE = 8;
 constexpr size_t DIAG_MERGE_WORDS = (size_t)DIAG_MERGE * 16386;  // 64-bit: 256 bins, or up to 16385 lags + the byte total, a copy
 hipError_t launch_copy_many(const CopyPiece *pieces, uint32_t n, hipStream_t s);
+// the same from a table in host memory, passed in the kernels' arguments (no upload, so nothing
+// waits for the stream): one launch per COPY_ARG_PIECES pieces
+constexpr uint32_t COPY_ARG_PIECES = 144;  // with the implicit arguments, under 4 KB of kernel arguments
+hipError_t launch_copy_pieces_host(const CopyPiece *pieces, uint32_t n, hipStream_t s);
 
 // The method's scalar pieces over device arrays (R, Theta, F^steps), for checking.
 hipError_t launch_unit_r(const double *alpha, const uint8_t *om, size_t n, uint8_t *out, hipStream_t s);

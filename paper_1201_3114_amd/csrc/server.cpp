@@ -138,16 +138,6 @@ bool is_device_ptr(const void *p) {
     return a.type == hipMemoryTypeDevice;
 }
 
-// Appends the pieces of one copy to a staging array.
-void add_pieces(CopyPiece *arr, uint32_t &n, const void *src, void *dst, uint64_t len) {
-    for (uint64_t o = 0; o < len; o += COPY_PIECE_BYTES) {
-        CopyPiece &p = arr[n++];
-        p.src = static_cast<const uint8_t *>(src) + o;
-        p.dst = static_cast<uint8_t *>(dst) + o;
-        p.len = len - o < COPY_PIECE_BYTES ? len - o : COPY_PIECE_BYTES;
-    }
-}
-
 // Late admission: the next tick is queued a margin before the running one is expected to end,
 // time for the host to wake, admit, copy inputs and install records on the staging stream.  The
 // margin adapts: when a tick queued this way starts more than LATE_GAP_NS after the one before
@@ -353,7 +343,7 @@ int complete_tick(lz_server *s, TickSlot &t) {
         if (len && r->dst_dev) {
             if (n_out + pieces_of(len) > PIECES_MAX)
                 if (int rc = flush_out()) return rc;
-            add_pieces(s->h_out, n_out, req_out(s, r), r->dst, len);
+            add_copy_pieces(s->h_out, n_out, req_out(s, r), r->dst, len);
         } else if (len) {
             LZ_HIP(hipMemcpyAsync(r->dst, req_out(s, r), len, hipMemcpyDefault, cs));
         }
@@ -487,7 +477,7 @@ int server_step(lz_server *s) {
             t.h_meta[3 * i + 2] = n_idx;
             std::memcpy(t.h_idx + n_idx, r->slots.data(), r->nb * sizeof(uint32_t));
             n_idx += r->nb;
-            if (in_len(*r) && r->src_dev) add_pieces(t.h_in, n_in, r->src, req_in(s, r), in_len(*r));
+            if (in_len(*r) && r->src_dev) add_copy_pieces(t.h_in, n_in, r->src, req_in(s, r), in_len(*r));
             else if (in_len(*r)) LZ_HIP(hipMemcpyAsync(req_in(s, r), r->src, in_len(*r), hipMemcpyDefault, pre));
             s->active.push_back(r);
         }

@@ -49,6 +49,7 @@ struct lz_stream {
     uint8_t *stage;      // input, then output
     uint64_t fill;       // staged bytes
     std::vector<Deferred> segs;
+    std::vector<CopyPiece> pieces;  // the staged chunks' output copies, built at a flush
 };
 
 namespace {
@@ -145,13 +146,50 @@ int stream_step(lz_stream *st, const uint8_t *d_in, size_t n, uint8_t *d_out, hi
     return LZ_OK;
 }
 
-// Runs the staged chunks as one update and copies each chunk's output to where it goes.
+// Queued chunks run as soon as their blocks make up a chain per lane of one wave on every SIMD (four
+// per CU): such an update already issues at the full rate, and the host queues the next chunks
+// while it runs.  One chain more would put a second wave on one SIMD and double the run's time, so
+// a run from the stream's position holds at most run_room bytes (its first block may be one that
+// an earlier run began), and a chunk that does not fit is split between runs.  At most the
+// staging capacity.
+uint64_t run_bytes(const lz_stream *st) {
+    const uint64_t b = (uint64_t)st->ctx->dev.cus * 4 * WAVE_LANES * st->ctx->prm.block_len;
+    return b < LZ_STREAM_DEFER_BYTES ? b : LZ_STREAM_DEFER_BYTES;
+}
+
+uint64_t run_room(const lz_stream *st) {
+    const uint64_t B = st->ctx->prm.block_len;
+    const uint64_t b = (uint64_t)st->ctx->dev.cus * 4 * WAVE_LANES * B - st->pos % B;
+    return b < LZ_STREAM_DEFER_BYTES ? b : LZ_STREAM_DEFER_BYTES;
+}
+
+// Pieces of the staged chunks' output copies at most: every chunk, plus one per COPY_PIECE_BYTES.
+constexpr uint32_t STREAM_PIECES = (uint32_t)(LZ_STREAM_DEFER_BYTES / COPY_PIECE_BYTES) + LZ_STREAM_DEFER_CHUNKS;
+
+// The staging buffer of deferred updates and the host table of their output copies, on first use.
+int stream_staging(lz_stream *st) {
+    if (st->stage) return LZ_OK;
+    try {
+        st->pieces.resize(STREAM_PIECES);
+    } catch (...) {
+        return fail(LZ_E_NOMEM, "host allocation failed");
+    }
+    void *p = nullptr;
+    const hipError_t e = hipMalloc(&p, 2 * (size_t)LZ_STREAM_DEFER_BYTES);
+    if (e != hipSuccess) return hip_fail(e, "stream staging buffer");
+    st->stage = static_cast<uint8_t *>(p);
+    return LZ_OK;
+}
+
+// Runs the staged chunks as one update, then copies each chunk's output to where it goes: all
+// chunks by batched copies whose pieces travel in the kernel arguments.
 int stream_flush(lz_stream *st, hipStream_t s) {
     if (st->fill == 0) return LZ_OK;
     uint8_t *in = st->stage, *outb = st->stage + LZ_STREAM_DEFER_BYTES;
     if (int rc = stream_step(st, in, st->fill, outb, s)) return rc;
-    for (const lz_stream::Deferred &d : st->segs)
-        LZ_HIP(hipMemcpyAsync(d.out, outb + d.off, d.n, hipMemcpyDeviceToDevice, s));
+    uint32_t np = 0;
+    for (const lz_stream::Deferred &d : st->segs) add_copy_pieces(st->pieces.data(), np, outb + d.off, d.out, d.n);
+    LZ_HIP(launch_copy_pieces_host(st->pieces.data(), np, s));
     st->fill = 0;
     st->segs.clear();
     return LZ_OK;
@@ -186,29 +224,29 @@ extern "C" int lz_stream_update_deferred(lz_stream *st, const uint8_t *d_in, siz
     hipStream_t s = (hipStream_t)stream;
     LZ_HIP(hipSetDevice(st->ctx->device));
     if (int rc = stream_order(st, s)) return rc;
-    if (n >= LZ_STREAM_DEFER_BYTES) {  // a chunk this large fills the device by itself
+    if (n >= run_bytes(st)) {  // a chunk this large fills the device by itself
         if (int rc = stream_flush(st, s)) return rc;
         if (int rc = stream_step(st, d_in, n, d_out, s)) return rc;
         return stream_record(st, s);
     }
-    if (!st->stage) {
-        const hipError_t e = hipMalloc(&st->stage, 2 * (size_t)LZ_STREAM_DEFER_BYTES);
-        if (e != hipSuccess) {
-            st->stage = nullptr;
-            return hip_fail(e, "stream staging buffer");
+    if (int rc = stream_staging(st)) return rc;
+    while (n > 0) {  // fill < run_room here: a full run has been flushed
+        if (st->segs.size() >= LZ_STREAM_DEFER_CHUNKS)
+            if (int rc = stream_flush(st, s)) return rc;
+        const uint64_t room = run_room(st) - st->fill, take = n < room ? n : room;
+        LZ_HIP(hipMemcpyAsync(st->stage + st->fill, d_in, take, hipMemcpyDeviceToDevice, s));
+        try {
+            st->segs.push_back({d_out, st->fill, take});
+        } catch (...) {
+            return fail(LZ_E_NOMEM, "host allocation failed");
         }
+        st->fill += take;
+        d_in += take;
+        d_out += take;
+        n -= take;
+        if (st->fill == run_room(st))
+            if (int rc = stream_flush(st, s)) return rc;
     }
-    if (st->fill + n > LZ_STREAM_DEFER_BYTES || st->segs.size() >= LZ_STREAM_DEFER_CHUNKS)
-        if (int rc = stream_flush(st, s)) return rc;
-    LZ_HIP(hipMemcpyAsync(st->stage + st->fill, d_in, n, hipMemcpyDeviceToDevice, s));
-    try {
-        st->segs.push_back({d_out, st->fill, n});
-    } catch (...) {
-        return fail(LZ_E_NOMEM, "host allocation failed");
-    }
-    st->fill += n;
-    if (st->fill == LZ_STREAM_DEFER_BYTES)
-        if (int rc = stream_flush(st, s)) return rc;
     return stream_record(st, s);
 }
 

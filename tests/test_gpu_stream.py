@@ -275,19 +275,22 @@ def test_deferred_updates_equal_one_shot(lz, n):
 
 
 def test_deferred_staging_limits(lz):
-    """Past the staging capacity (LZ_STREAM_DEFER_BYTES, 64 MiB: the queued chunks run first), a chunk that
-    large by itself (run at once), and more than LZ_STREAM_DEFER_CHUNKS small chunks: the 130 MiB result
-    equals the one-shot ciphertext (itself checked against the oracle at full size elsewhere)."""
+    """Queued chunks run when they reach one wave on every SIMD (16 MiB on a 256-CU device): 1 MiB chunks
+    that reach it exactly and one that crosses it; chunks of that size or more, up to and past the staging
+    capacity (LZ_STREAM_DEFER_BYTES, 64 MiB), run at once after the queued ones; and more than
+    LZ_STREAM_DEFER_CHUNKS small chunks.  The 166 MiB result equals the one-shot ciphertext (itself checked
+    against the oracle at full size elsewhere)."""
     import torch
 
     MiB = 1 << 20
     ctx = lz.Context(0, lz.params(n_it=4))
-    n = 130 * MiB + 4999 * 7
+    steps = [MiB] * 63 + [MiB + 3, 64 * MiB, MiB - 3, 16 * MiB - 5, 20 * MiB] + [7] * 4999
+    n = sum(steps) + 11
     Pd = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda",
                        generator=torch.Generator(device="cuda").manual_seed(93))
     one = ctx.encrypt(Pd, b"staging pw")
     cuts, pos = [], 0
-    for step in [MiB] * 63 + [MiB + 3, 64 * MiB, MiB - 3] + [7] * 4999:
+    for step in steps:
         cuts.append((pos, pos + step))
         pos += step
     cuts.append((pos, n))
