@@ -274,6 +274,32 @@ def test_deferred_updates_equal_one_shot(lz, n):
     assert np.array_equal(host(back), P)
 
 
+@pytest.mark.parametrize("block_len", [5, 16])
+def test_deferred_runs_split_chunks_at_the_wave_boundary(lz, block_len):
+    """With short blocks a run of one wave per SIMD holds only 65,536 x block_len bytes (minus the part of
+    the block it continues), so the chunks of a 1.5-2 MiB message are split between many runs, at positions
+    that are mostly not block-aligned: the output and tag still equal the one-shot ones, and decrypt back."""
+    import torch
+
+    rng = np.random.default_rng(140 + block_len)
+    ctx = lz.Context(0, lz.params(n_it=4, block_len=block_len))
+    n = int(rng.integers(1_500_000, 2_000_000))
+    P = rng.integers(0, 256, n, dtype=np.uint8)
+    Pd = to_dev(P)
+    one = host(ctx.encrypt(Pd, b"split pw"))
+    cuts, pos = [], 0
+    while pos < n:
+        step = int(rng.integers(1, 200_000))
+        cuts.append((pos, min(n, pos + step)))
+        pos += step
+    say("block_len", block_len, "n", n, "chunks", len(cuts))
+    out, tag = _deferred_run(lz, ctx, False, b"split pw", Pd, cuts, rng)
+    assert np.array_equal(np.concatenate([host(out), host(tag)]), one)
+    C = to_dev(one)
+    back, _ = _deferred_run(lz, ctx, True, b"split pw", C, cuts, rng, tag=C[n:n + 24].clone())
+    assert np.array_equal(host(back), P)
+
+
 def test_deferred_staging_limits(lz):
     """Queued chunks run when they reach one wave on every SIMD (16 MiB on a 256-CU device): 1 MiB chunks
     that reach it exactly and one that crosses it; chunks of that size or more, up to and past the staging
