@@ -170,7 +170,7 @@ struct TickSlot {
     uint64_t bytes = 0;
     uint64_t seq = 0;     // tick sequence number (1, 2, ...)
     uint32_t waves = 0;   // waves per SIMD of the tick's chains, at most
-    bool late = false;    // queued by a late step, while the tick before it ran
+    bool late = false;    // queued while the tick before it ran: its start shows whether in time
 };
 
 struct lz_server {
