@@ -52,14 +52,66 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // its real results (|Z|^2, or Re Z of an even real matrix's transform) are written twice:
 // row c, and, as row h - c with k2 -> w - k2, each row the pass does not compute itself
 // (mirror = h; 0 writes no mirror rows).
+// The autocorrelation matrix's denominator n S2 - S1^2 comes from the moment sums mom: a first
+// pass over bytes adds each workgroup's S1 = sum x and S2 = sum x^2 into copy (slot mod
+// MOM_COPIES), mom[MOM_STRIDE copy] and the word after it, a cache line per copy so that the
+// device atomics of different copies do not wait for each other (exact: S1 < 2^32 and S2 < 2^40
+// for at most 2^24 bytes); in the last pass one thread per workgroup adds up the copies (den,
+// NaN when n S2 = S1^2, that is when every byte is equal).
+constexpr uint32_t MOM_COPIES = 32, MOM_STRIDE = 16;  // 16 words: 128 bytes
 enum : int { EPI_COMPLEX = 0, EPI_POWER = 1, EPI_POWER_NODC = 2, EPI_ACF = 3 };
 struct PassOut {
     double2 *z;
     double *p;
-    const double *den;
     uint32_t nout;
     uint32_t mirror;
+    unsigned long long *mom;  // first pass over bytes: add the moment sums here (or nullptr)
+    uint64_t n;               // EPI_ACF: the matrix's n = h w, with mom holding its moment sums
+    double den;               // EPI_ACF: set by the kernel from mom and n
 };
+
+// The workgroup's moment sums (per-thread s1, s2) into copy slot mod MOM_COPIES of o.mom; every
+// thread of the workgroup (DIAG_WG threads) calls it: it holds a barrier.
+__device__ __forceinline__ void add_moments(const PassOut &o, unsigned long long s1, unsigned long long s2,
+                                            uint32_t slot) {
+    __shared__ unsigned long long mred[2][DIAG_WG / 64];
+    for (int k = 32; k > 0; k >>= 1) {
+        s1 += __shfl_xor(s1, k, 64);
+        s2 += __shfl_xor(s2, k, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        mred[0][threadIdx.x / 64] = s1;
+        mred[1][threadIdx.x / 64] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t1 = 0, t2 = 0;
+        for (int w = 0; w < DIAG_WG / 64; ++w) {
+            t1 += mred[0][w];
+            t2 += mred[1][w];
+        }
+        unsigned long long *m = o.mom + MOM_STRIDE * (slot % MOM_COPIES);
+        if (t1) atomicAdd(&m[0], t1);
+        if (t2) atomicAdd(&m[1], t2);
+    }
+}
+
+// n S2 - S1^2 from the moment copies, exactly (n <= 2^24 keeps both products below 2^64): thread 0
+// adds up the copies and the workgroup (DIAG_WG threads, all of which call it) shares the result.
+__device__ __forceinline__ double acf_den(const PassOut &o) {
+    __shared__ double den_s;
+    if (threadIdx.x == 0) {
+        unsigned long long s1 = 0, s2 = 0;
+        for (uint32_t c = 0; c < MOM_COPIES; ++c) {
+            s1 += o.mom[MOM_STRIDE * c];
+            s2 += o.mom[MOM_STRIDE * c + 1];
+        }
+        const unsigned long long d = o.n * s2 - s1 * s1;
+        den_s = d == 0 ? __builtin_nan("") : (double)d;
+    }
+    __syncthreads();
+    return den_s;
+}
 
 template <int E>
 __device__ __forceinline__ void pass_store(const PassOut &o, uint32_t c, uint32_t r, uint32_t N, uint32_t M,
@@ -71,7 +123,7 @@ __device__ __forceinline__ void pass_store(const PassOut &o, uint32_t c, uint32_
     } else {
         double v;
         if constexpr (E == EPI_ACF) {
-            const double d = o.den[0];
+            const double d = o.den;
             v = d != d ? d : re / d;
         } else {
             v = (E == EPI_POWER_NODC && c == 0 && r == 0) ? 0.0 : re * re + im * im;
@@ -85,6 +137,10 @@ __device__ __forceinline__ void pass_store(const PassOut &o, uint32_t c, uint32_
 template <typename In, int E, int TR, int KS>
 __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32_t N, uint32_t M, const double2 *tw,
                                                             double sign, PassOut dst) {
+    if constexpr (E == EPI_ACF) dst.den = acf_den(dst);
+    // the workgroups of the first row tile see every input once: they add the moment sums
+    const bool moments = std::is_same_v<In, uint8_t> && dst.mom && blockIdx.x == 0;
+    unsigned long long m1 = 0, m2 = 0;
     // TR x 64 outputs per workgroup: with TR = 64 each wave takes a 32 x 32 block as 2 x 2 tiles of
     // 16 x 16, with TR = 32 (grids that would not fill the chip) a 32 x 16 block as 2 x 1 tiles.
     // A real input (bytes or doubles) has no imaginary part: two of the four products are skipped.
@@ -134,7 +190,13 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
     for (uint32_t k0 = 0; k0 < N; k0 += KS) {
         for (int q = 0; q < QX; ++q) {
             const uint32_t k = k0 + kq + 4 * q;
-            s_src[kq + 4 * q][cc] = (k < N && c0 + cc < M) ? dft_value(nx[q]) : make_double2(0.0, 0.0);
+            const bool in = k < N && c0 + cc < M;
+            s_src[kq + 4 * q][cc] = in ? dft_value(nx[q]) : make_double2(0.0, 0.0);
+            if constexpr (std::is_same_v<In, uint8_t>) {
+                const unsigned long long xv = in ? nx[q] : 0;
+                m1 += xv;
+                m2 += xv * xv;
+            }
         }
         for (int q = 0; q < TWQ; ++q) {
             const uint32_t kk = kt + (KS / TWQ) * q, k = k0 + kk;
@@ -160,6 +222,7 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
         }
         __syncthreads();
     }
+    if (moments) add_moments(dst, m1, m2, blockIdx.y);
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < TB; ++b)
             for (int j = 0; j < 4; ++j) {
@@ -210,6 +273,7 @@ __device__ __forceinline__ double2 fft_twiddle(const double2 *q, uint32_t j, uin
 template <typename In, int E>
 __global__ __launch_bounds__(DIAG_WG) void fft_pass_kernel(const In *src, uint32_t N, uint32_t M, uint32_t logN,
                                                             uint32_t C, double sign, PassOut dst) {
+    if constexpr (E == EPI_ACF) dst.den = acf_den(dst);
     // C columns of N values (twice when N <= FFT_PP_MAX: each stage reads one copy and writes the
     // other, so it needs one barrier instead of two), then the twiddles
     extern __shared__ double2 fbuf[];
@@ -240,14 +304,20 @@ __global__ __launch_bounds__(DIAG_WG) void fft_pass_kernel(const In *src, uint32
             sincospi(2.0 * (double)j / (double)N, &sn, &cs);
             ftw[j] = make_double2(cs, sign * sn);
         }
+        unsigned long long m1 = 0, m2 = 0;
 #pragma unroll
         for (int i = 0; i < FFT_EPT; ++i) {
             const uint32_t e = threadIdx.x + i * DIAG_WG;
             if (e < total) {
                 const uint32_t k = e / cols, cl = e - k * cols;
                 cur[cl * N + k] = dft_value(v[i]);
+                if constexpr (std::is_same_v<In, uint8_t>) {
+                    m1 += v[i];
+                    m2 += (unsigned long long)v[i] * v[i];
+                }
             }
         }
+        if (std::is_same_v<In, uint8_t> && dst.mom) add_moments(dst, m1, m2, blockIdx.x);
     }
     __syncthreads();
     uint32_t st = 0;  // log2 of the stride s
@@ -414,6 +484,7 @@ __device__ __forceinline__ void dft16(double2 (&v)[16], double sign) {
 
 template <typename In, int E>
 __global__ __launch_bounds__(DIAG_WG) void fft1k_pass_kernel(const In *src, uint32_t M, double sign, PassOut dst) {
+    if constexpr (E == EPI_ACF) dst.den = acf_den(dst);
     extern __shared__ double2 fbuf[];
     const uint32_t lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     double2 *L = fbuf + (size_t)wave * FFT1K_WAVE;
@@ -433,7 +504,19 @@ __global__ __launch_bounds__(DIAG_WG) void fft1k_pass_kernel(const In *src, uint
         q[threadIdx.x] = make_double2(cs, sign * sn);
     }
     __syncthreads();
-    if (!live) return;
+    if constexpr (std::is_same_v<In, uint8_t>) {
+        if (dst.mom) {  // every thread: the waves past the last column add nothing
+            unsigned long long m1 = 0, m2 = 0;
+            if (live)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    m1 += x[j];
+                    m2 += (unsigned long long)x[j] * x[j];
+                }
+            add_moments(dst, m1, m2, blockIdx.x);
+        }
+    }
+    if (!live) return;  // the whole wave
     double2 v[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = dft_value(x[j]);
@@ -535,6 +618,7 @@ template <typename In, int E>
 __global__ __launch_bounds__(DIAG_WG) void fft_mixed_pass_kernel(const In *src, uint32_t N, uint32_t M, uint32_t C,
                                                                   FftPlan plan, const double2 *tw, double sign,
                                                                   PassOut dst) {
+    if constexpr (E == EPI_ACF) dst.den = acf_den(dst);
     extern __shared__ double2 fbuf[];  // C columns of N values, then the N twiddles
     double2 *ftw = fbuf + (size_t)C * N;
     uint32_t g = blockIdx.x;
@@ -556,14 +640,20 @@ __global__ __launch_bounds__(DIAG_WG) void fft_mixed_pass_kernel(const In *src, 
             const double2 w = tw[j];
             ftw[j] = make_double2(w.x, sign * w.y);
         }
+        unsigned long long m1 = 0, m2 = 0;
 #pragma unroll
         for (int i = 0; i < FFT_EPT; ++i) {
             const uint32_t e = threadIdx.x + i * DIAG_WG;
             if (e < total) {
                 const uint32_t k = e / cols, cl = e - k * cols;
                 fbuf[cl * N + k] = dft_value(v[i]);
+                if constexpr (std::is_same_v<In, uint8_t>) {
+                    m1 += v[i];
+                    m2 += (unsigned long long)v[i] * v[i];
+                }
             }
         }
+        if (std::is_same_v<In, uint8_t> && dst.mom) add_moments(dst, m1, m2, blockIdx.x);
     }
     __syncthreads();
     uint32_t s = 1;
@@ -579,20 +669,6 @@ __global__ __launch_bounds__(DIAG_WG) void fft_mixed_pass_kernel(const In *src, 
         const double2 v = fbuf[e];
         const uint32_t cl = e / N;
         pass_store<E>(dst, c0 + cl, e - cl * N, N, M, v.x, v.y);
-    }
-}
-
-// n S2 - S1^2 from the histogram (exact: n <= 2^24 keeps both products below 2^64),
-// the zero-lag sum of the mean-removed image scaled by n.
-__global__ __launch_bounds__(DIAG_WG) void acf2_den_kernel(const unsigned long long *hist, uint64_t n,
-                                                            double *den) {
-    __shared__ unsigned long long ired[DIAG_WG];
-    const unsigned long long v = threadIdx.x, h = hist[threadIdx.x];
-    const unsigned long long s1 = block_sum<unsigned long long>(h * v, ired);
-    const unsigned long long s2 = block_sum<unsigned long long>(h * v * v, ired);
-    if (threadIdx.x == 0) {
-        const unsigned long long d = (unsigned long long)n * s2 - s1 * s1;
-        den[0] = d == 0 ? __builtin_nan("") : (double)d;
     }
 }
 
@@ -739,9 +815,11 @@ int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, cons
 
 // complex results, indices r < nout of each transform; real results, whole rows of n, with the
 // mirror rows of an h-row matrix (0: none)
-PassOut complex_out(double2 *z, uint32_t nout) { return PassOut{z, nullptr, nullptr, nout, 0}; }
-PassOut real_out(double *p, uint32_t n, uint32_t h, const double *den = nullptr) {
-    return PassOut{nullptr, p, den, n, h};
+PassOut complex_out(double2 *z, uint32_t nout, unsigned long long *mom = nullptr) {
+    return PassOut{z, nullptr, nout, 0, mom, 0, 0.0};
+}
+PassOut real_out(double *p, uint32_t n, uint32_t h, unsigned long long *mom = nullptr, uint64_t count = 0) {
+    return PassOut{nullptr, p, n, h, mom, count, 0.0};
 }
 
 }  // namespace
@@ -774,28 +852,25 @@ extern "C" int lz_autocorrelation_2d(lz_ctx *c, const uint8_t *d_img, uint32_t h
     hipStream_t s = (hipStream_t)stream;
     LZ_HIP(hipSetDevice(c->device));
     char *ws;
-    const size_t extra = 256 * 8 + 8;  // histogram, then the denominator
+    const size_t extra = (size_t)MOM_STRIDE * MOM_COPIES * 8;  // the moment sums S1, S2 (a pair per copy)
     if (int rc = diag_begin(c, s, dft2_bytes(h, w, extra), &ws)) return rc;
-    uint64_t *hist = reinterpret_cast<uint64_t *>(ws);
-    double *den = reinterpret_cast<double *>(hist + 256);
+    unsigned long long *mom = reinterpret_cast<unsigned long long *>(ws);
     const Dft2 d = dft2_layout(ws, h, w, extra);
-    const size_t n = (size_t)h * w;
-    if (int rc = lz_histogram(c, d_img, n, hist, stream)) return rc;
-    hipLaunchKernelGGL(acf2_den_kernel, dim3(1), dim3(DIAG_WG), 0, s,
-                       reinterpret_cast<const unsigned long long *>(hist), (uint64_t)n, den);
-    LZ_HIP(hipGetLastError());
+    const uint64_t n = (uint64_t)h * w;
+    LZ_HIP(launch_fill_u64(mom, (size_t)MOM_STRIDE * MOM_COPIES, s));
     if (int rc = launch_twiddles(c, d, h, w, s)) return rc;
-    // a: w x (h/2 + 1); b: |Z|^2 with the zero frequency removed (h x w, real and even);
-    // a: w x (h/2 + 1) again; then Re G / den, rows 0..h/2 and their mirror rows (G is even too)
+    // a: w x (h/2 + 1), adding the moment sums; b: |Z|^2 with the zero frequency removed (h x w,
+    // real and even); a: w x (h/2 + 1) again; then Re G / den, den = n S2 - S1^2 from the moment
+    // sums, rows 0..h/2 and their mirror rows (G is even too)
     const uint32_t hh = h / 2 + 1;
     double *pm = reinterpret_cast<double *>(d.b);
-    if (int rc = launch_dft_pass<uint8_t, EPI_COMPLEX>(c, d_img, h, w, d.tw_h, -1.0, complex_out(d.a, hh), s))
+    if (int rc = launch_dft_pass<uint8_t, EPI_COMPLEX>(c, d_img, h, w, d.tw_h, -1.0, complex_out(d.a, hh, mom), s))
         return rc;
     if (int rc = launch_dft_pass<double2, EPI_POWER_NODC>(c, d.a, w, hh, d.tw_w, -1.0, real_out(pm, w, h), s))
         return rc;
     if (int rc = launch_dft_pass<double, EPI_COMPLEX>(c, pm, h, w, d.tw_h, 1.0, complex_out(d.a, hh), s))
         return rc;
-    if (int rc = launch_dft_pass<double2, EPI_ACF>(c, d.a, w, hh, d.tw_w, 1.0, real_out(d_acf, w, h, den), s))
+    if (int rc = launch_dft_pass<double2, EPI_ACF>(c, d.a, w, hh, d.tw_w, 1.0, real_out(d_acf, w, h, mom, n), s))
         return rc;
     return diag_end(c, s);
 }
