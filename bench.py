@@ -409,9 +409,11 @@ def bench_diag(lz, torch, reps=5):
     ms = timed(lambda: lz.lag_sums(ctx, x[:n16], L))
     res["lag_sums_16MiB_lag256"] = dict(ms=ms, int_MAC_per_s=n16 * (L + 1) / ms * 1e3,
                                         hbm_GBps=n16 / ms / 1e6)
-    L = 16384  # the largest lag count: four windows of 4096 lags on the int8 matrix cores
+    L = 16384  # the largest lag count: five windows of at most 4096 lags on the int8 matrix cores
     ms = timed(lambda: lz.lag_sums(ctx, x[:n16], L))
     res["lag_sums_16MiB_lag16384"] = dict(ms=ms, int_MAC_per_s=n16 * (L + 1) / ms * 1e3)
+    ms = timed(lambda: lz.autocorrelation(ctx, x[:n16], L))
+    res["autocorrelation_16MiB_lag16384"] = dict(ms=ms, int_MAC_per_s=n16 * (L + 1) / ms * 1e3)
     # power-of-two sides: two FFT passes; algorithmic bytes: the image (1 B per value) in, the half
     # spectrum (h/2 + 1 of each column's h indices, 16 B complex) out and in again, 8 B |Z|^2 out
     def spectrum_bytes(h, w):

@@ -624,51 +624,51 @@ __global__ __launch_bounds__(DIAG_WG) void lagsum_fix_kernel(const uint8_t *data
 // r_k for k = 0..L of a byte sequence x_0..x_{n-1} with mean m:
 //   r_k = sum_{i<n-k} (x_i - m)(x_{i+k} - m) / sum_i (x_i - m)^2
 //       = (S_k - m (A_k + B_k) + (n-k) m^2) / (S_0 - n m^2),
-// A_k = sum_{i<n-k} x_i = T - (sum of the last k bytes), B_k = sum_{i>=k} x_i = T - (sum of the first k bytes).
-// One workgroup scans the first and last L bytes in chunks of 256.
+// A_k = sum_{i<n-k} x_i = T - (sum of the last k bytes), B_k = sum_{i>=k} x_i = T - (sum of the first k bytes),
+// so A_k + B_k = 2T - (P_k + Q_k) with P_k + Q_k = sum_{j<k} (x_j + x_{n-1-j}), an exact integer below 2^53.
+// One workgroup per 256 lags: workgroup b takes k = 256 b + 1 .. 256 b + 256 (and workgroup 0 also r_0):
+// the sum of x_j + x_{n-1-j} over j < 256 b (16-byte loads where aligned, a workgroup sum), then a
+// wave scan over its own 256 values of j.  NaN for no bytes or one repeated byte (n S_0 = T^2 exactly,
+// compared in 128-bit integers), 0 for k >= n.
 __global__ __launch_bounds__(DIAG_WG) void autocorr_norm_kernel(const uint8_t *data, uint64_t n, uint32_t L,
                                                                  const unsigned long long *sums,
                                                                  const unsigned long long *total, double *r) {
-    __shared__ unsigned long long sh[DIAG_WG], st[DIAG_WG];
+    __shared__ unsigned long long red[DIAG_WG];
+    __shared__ uint32_t wsum[DIAG_WG / 64];
+    const uint32_t t = threadIdx.x, lane = t % 64, wave = t / 64;
+    const uint64_t kb = (uint64_t)blockIdx.x * DIAG_WG;
     const unsigned long long T = *total;
-    const double m = (double)T / (double)n;
-    const double den = (double)sums[0] - (double)n * m * m;
-    // no coefficient when every byte is equal (or there are none): n S_0 = T^2 exactly then, and
-    // only then (the equality case of Cauchy-Schwarz), compared in 128-bit integers
     const bool constant = n == 0 || (unsigned __int128)n * sums[0] == (unsigned __int128)T * T;
-    unsigned long long carry_h = 0, carry_t = 0;
-    if (threadIdx.x == 0) r[0] = constant ? __builtin_nan("") : 1.0;
-    for (uint32_t c = 0; c < L; c += DIAG_WG) {
-        const uint64_t i = (uint64_t)c + threadIdx.x;  // k = i + 1 includes byte i of the head / tail
-        sh[threadIdx.x] = i < n ? data[i] : 0;
-        st[threadIdx.x] = i < n ? data[n - 1 - i] : 0;
-        __syncthreads();
-        for (int s = 1; s < DIAG_WG; s <<= 1) {  // inclusive scans
-            const unsigned long long a = threadIdx.x >= (unsigned)s ? sh[threadIdx.x - s] : 0;
-            const unsigned long long b = threadIdx.x >= (unsigned)s ? st[threadIdx.x - s] : 0;
-            __syncthreads();
-            sh[threadIdx.x] += a;
-            st[threadIdx.x] += b;
-            __syncthreads();
-        }
-        const uint64_t k = i + 1;
-        if (k <= L) {
-            double v;
-            if (constant) {
-                v = __builtin_nan("");
-            } else if (k >= n) {
-                v = 0.0;
-            } else {
-                const double Ak = (double)(T - (carry_t + st[threadIdx.x]));
-                const double Bk = (double)(T - (carry_h + sh[threadIdx.x]));
-                v = ((double)sums[k] - m * (Ak + Bk) + (double)(n - k) * m * m) / den;
-            }
-            r[k] = v;
-        }
-        carry_h += sh[DIAG_WG - 1];
-        carry_t += st[DIAG_WG - 1];
-        __syncthreads();
+    const uint64_t mb = kb < n ? kb : n;
+    const unsigned long long base =
+        block_sum<unsigned long long>(fix_range_part(data, 0, mb) + fix_range_part(data, n - mb, n), red);
+    const uint64_t j = kb + t;  // lag k = j + 1 includes byte j of both ends
+    const uint32_t x = j < n ? (uint32_t)data[j] + data[n - 1 - j] : 0u;
+    uint32_t inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if ((int)lane >= o) inc += y;
     }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t w = 0; w < wave; ++w) before += wsum[w];
+    if (blockIdx.x == 0 && t == 0) r[0] = constant ? __builtin_nan("") : 1.0;
+    const uint64_t k = j + 1;
+    if (k > L) return;
+    double v;
+    if (constant) {
+        v = __builtin_nan("");
+    } else if (k >= n) {
+        v = 0.0;
+    } else {
+        const unsigned long long pq = base + before + inc;  // P_k + Q_k
+        const double mean = (double)T / (double)n;
+        const double den = (double)sums[0] - (double)n * mean * mean;
+        v = ((double)sums[k] - mean * (double)(2 * T - pq) + (double)(n - k) * mean * mean) / den;
+    }
+    r[k] = v;
 }
 
 // The lag sums into sums[0..max_lag]; with total non-null, also the byte total into *total.
@@ -761,8 +761,8 @@ extern "C" int lz_autocorrelation(lz_ctx *c, const uint8_t *d_data, size_t n, ui
     bool normalised = false;
     if (int rc = lag_sums(c, d_data, n, max_lag, sums, total, s, true, d_r, &normalised)) return rc;
     if (!normalised)
-        hipLaunchKernelGGL(autocorr_norm_kernel, dim3(1), dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag, sums,
-                           total, d_r);
+        hipLaunchKernelGGL(autocorr_norm_kernel, dim3(max_lag > 0 ? (max_lag + DIAG_WG - 1) / DIAG_WG : 1),
+                           dim3(DIAG_WG), 0, s, d_data, (uint64_t)n, max_lag, sums, total, d_r);
     LZ_HIP(hipGetLastError());
     return diag_end(c, s);
 }
