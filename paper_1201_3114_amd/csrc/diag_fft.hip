@@ -138,8 +138,13 @@ template <typename In, int E, int TR, int KS>
 __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32_t N, uint32_t M, const double2 *tw,
                                                             double sign, PassOut dst) {
     if constexpr (E == EPI_ACF) dst.den = acf_den(dst);
+    // Workgroups are dealt to the 8 XCDs in turn: when the tiles divide evenly, those sharing an
+    // input column tile go to one XCD, whose L2 then reads those columns from HBM once.
+    const uint32_t nt = gridDim.x * gridDim.y, lin = blockIdx.x + gridDim.x * blockIdx.y;
+    const uint32_t tix = nt % 8 == 0 ? (lin % 8) * (nt / 8) + lin / 8 : lin;
+    const uint32_t rt = tix % gridDim.x, ct = tix / gridDim.x;  // row tile, column tile
     // the workgroups of the first row tile see every input once: they add the moment sums
-    const bool moments = std::is_same_v<In, uint8_t> && dst.mom && blockIdx.x == 0;
+    const bool moments = std::is_same_v<In, uint8_t> && dst.mom && rt == 0;
     unsigned long long m1 = 0, m2 = 0;
     // TR x 64 outputs per workgroup: with TR = 64 each wave takes a 32 x 32 block as 2 x 2 tiles of
     // 16 x 16, with TR = 32 (grids that would not fill the chip) a 32 x 16 block as 2 x 1 tiles.
@@ -154,7 +159,7 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
     constexpr int TWQ = TR * KS / DIAG_WG;           // twiddles each thread stages per k stage
     __shared__ double2 s_src[KS][DFT_T];  // [k][c]
     __shared__ double2 s_tw[KS][TR];      // [k][r]
-    const uint32_t r0 = blockIdx.x * TR, c0 = blockIdx.y * DFT_T;
+    const uint32_t r0 = rt * TR, c0 = ct * DFT_T;
     const uint32_t lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const uint32_t wr = (wave / WC) * 32, wc = (wave % WC) * (16 * TB);
     const uint32_t li = lane % 16, lk = lane / 16;
@@ -222,7 +227,7 @@ __global__ __launch_bounds__(DIAG_WG) void dft_pass_kernel(const In *src, uint32
         }
         __syncthreads();
     }
-    if (moments) add_moments(dst, m1, m2, blockIdx.y);
+    if (moments) add_moments(dst, m1, m2, ct);
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < TB; ++b)
             for (int j = 0; j < 4; ++j) {
@@ -285,6 +290,7 @@ __global__ __launch_bounds__(DIAG_WG) void fft_pass_kernel(const In *src, uint32
     uint32_t g = blockIdx.x;
     if (gridDim.x % 8 == 0) g = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
     const uint32_t c0 = g * C;
+    if (c0 >= M) return;  // a workgroup of the padding (the grid is a multiple of 8)
     const uint32_t cols = M - c0 < C ? M - c0 : C;
     const uint32_t total = cols * N;
     {
@@ -624,6 +630,7 @@ __global__ __launch_bounds__(DIAG_WG) void fft_mixed_pass_kernel(const In *src, 
     uint32_t g = blockIdx.x;
     if (gridDim.x % 8 == 0) g = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
     const uint32_t c0 = g * C;
+    if (c0 >= M) return;  // a workgroup of the padding (the grid is a multiple of 8)
     const uint32_t cols = M - c0 < C ? M - c0 : C;
     const uint32_t total = cols * N;
     {
@@ -778,7 +785,7 @@ int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, cons
         while ((1u << logN) < N) ++logN;
         const uint32_t per_wg = N > FFT_WG_ELEMS ? N : FFT_WG_ELEMS;
         const uint32_t C = per_wg / N;
-        const uint32_t groups = (M + C - 1) / C;
+        const uint32_t groups = ((M + C - 1) / C + 7) / 8 * 8;  // a multiple of 8: the XCD-aware order
         const size_t lds = fft_lds(N);
         if (lds > 65536)
             LZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_pass_kernel<In, E>),
@@ -788,7 +795,7 @@ int launch_dft_pass(const lz_ctx *c, const In *src, uint32_t N, uint32_t M, cons
     } else if (mixed_ok(c, N)) {
         const uint32_t per_wg = N > FFT_WG_ELEMS ? N : FFT_WG_ELEMS;
         const uint32_t C = per_wg / N;
-        const uint32_t groups = (M + C - 1) / C;
+        const uint32_t groups = ((M + C - 1) / C + 7) / 8 * 8;  // a multiple of 8: the XCD-aware order
         const size_t lds = mixed_lds(N);
         if (lds > 65536)
             LZ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&fft_mixed_pass_kernel<In, E>),
